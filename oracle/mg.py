@@ -1,0 +1,291 @@
+"""Multigrid V-cycle and Krylov solvers on assembled free-DoF matrices.
+
+V-cycle (paper Section 4: one V-cycle approximates the inverse of the viscous
+block): damped Jacobi smoothing with the diagonal of the level operator,
+omega = 2/3, nu1 pre- and nu2 post-sweeps, restriction = P^T, interpolation = P
+(Section 2.1), zero initial guess on every coarser level, and a dense direct
+solve on level 0.  The Chebyshev smoother and the SOR-CG coarse solver of the
+paper are replaced by damped Jacobi and a direct solve (benchmark choices).
+
+Solvers, all starting from x0 = 0 and stopping when ||b - A x||_2 <= tol ||b||_2
+(eq. (4.3) with the benchmark's tolerance):
+  stationary MG, PCG, flexible CG (FCG(1)), iterative refinement, FGMRES(m),
+  MINRES.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import agca as _agca
+from . import fem, mesh, transfer
+
+
+@dataclass
+class Hierarchy:
+    levels: list
+    ncomp: int
+    ops_full: List[sp.csr_matrix]            # Neumann operators, all nodes
+    A: List[sp.csr_matrix]                   # free-DoF operators
+    P: List[sp.csr_matrix]                   # free-DoF interpolation, level l -> l+1
+    P_full: List[sp.csr_matrix]              # all-node interpolation
+    free: List[np.ndarray]                   # free dof indices per level
+    flags: List[np.ndarray]
+    nu_levels: List[np.ndarray]
+    omega: float = 2.0 / 3.0
+    nu1: int = 2
+    nu2: int = 2
+    coarse_chol: object = None
+    D: List[np.ndarray] = field(default_factory=list)
+
+    @property
+    def L(self) -> int:
+        return len(self.levels) - 1
+
+
+def build(L: int, nu_levels: List[np.ndarray], ncomp: int, tau: float = 10.0,
+          mode: int = _agca.FLAG_RATIO, levels=None) -> Hierarchy:
+    """Assemble the AGCA hierarchy for coefficients ``nu_levels`` (canonical ids per level)."""
+    if levels is None:
+        levels = mesh.hierarchy(L)
+    Pf = transfer.prolongations(levels, ncomp)
+    res = _agca.agca_operators(levels, Pf, nu_levels, ncomp, tau, mode)
+    free = [fem.free_dofs(lv, ncomp) for lv in levels]
+    A = [fem.restrict_free(op, fr) for op, fr in zip(res["ops"], free)]
+    P = [Pf[l][free[l + 1]][:, free[l]].tocsr() for l in range(L)]
+    H = Hierarchy(levels, ncomp, res["ops"], A, P, Pf, free, res["flags"], nu_levels)
+    H.D = [a.diagonal().copy() for a in A]
+    A0 = A[0].toarray()
+    H.coarse_chol = sla.cho_factor(A0)
+    return H
+
+
+def full_to_free(H: Hierarchy, l: int, x: np.ndarray) -> np.ndarray:
+    return x[H.free[l]]
+
+
+def free_to_full(H: Hierarchy, l: int, xf: np.ndarray) -> np.ndarray:
+    n = H.ncomp * (H.levels[l].n + 1) ** 3
+    x = np.zeros(n)
+    x[H.free[l]] = xf
+    return x
+
+
+def jacobi(H: Hierarchy, l: int, b: np.ndarray, x: np.ndarray, sweeps: int) -> np.ndarray:
+    A, D = H.A[l], H.D[l]
+    for _ in range(sweeps):
+        x = x + H.omega * (b - A @ x) / D
+    return x
+
+
+def vcycle(H: Hierarchy, b: np.ndarray, l: Optional[int] = None, x: Optional[np.ndarray] = None):
+    """One V-cycle on level l for A_l x = b (free-DoF vectors)."""
+    if l is None:
+        l = H.L
+    if x is None:
+        x = np.zeros_like(b)
+    if l == 0:
+        return sla.cho_solve(H.coarse_chol, b)
+    x = jacobi(H, l, b, x, H.nu1)
+    r = b - H.A[l] @ x
+    rc = H.P[l - 1].T @ r
+    ec = vcycle(H, rc, l - 1, None)
+    x = x + H.P[l - 1] @ ec
+    x = jacobi(H, l, b, x, H.nu2)
+    return x
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iterations: int
+    history: List[float]
+    converged: bool
+
+
+def _rel(r, bn):
+    return float(np.linalg.norm(r) / bn)
+
+
+def stationary(H: Hierarchy, b: np.ndarray, tol: float, maxit: int = 200) -> SolveResult:
+    """x <- x + V(b - A x) until the relative residual is below tol."""
+    A = H.A[H.L]
+    bn = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    hist = [_rel(r, bn)]
+    for it in range(1, maxit + 1):
+        x = x + vcycle(H, r)
+        r = b - A @ x
+        hist.append(_rel(r, bn))
+        if hist[-1] <= tol:
+            return SolveResult(x, it, hist, True)
+    return SolveResult(x, maxit, hist, False)
+
+
+def pcg(A, b, M: Callable, tol: float, maxit: int = 500) -> SolveResult:
+    """Preconditioned conjugate gradients (M a symmetric positive definite preconditioner)."""
+    bn = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = M(r)
+    p = z.copy()
+    rz = r @ z
+    hist = [_rel(r, bn)]
+    for it in range(1, maxit + 1):
+        q = A @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        hist.append(_rel(r, bn))
+        if hist[-1] <= tol:
+            return SolveResult(x, it, hist, True)
+        z = M(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return SolveResult(x, maxit, hist, False)
+
+
+def fcg(A, b, M: Callable, tol: float, maxit: int = 500) -> SolveResult:
+    """Flexible CG with one-term orthogonalisation (FCG(1), Notay):
+    beta = z_k . (r_k - r_{k-1}) / (z_{k-1} . r_{k-1})  (Polak-Ribiere form)."""
+    bn = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = M(r)
+    p = z.copy()
+    rz = r @ z
+    hist = [_rel(r, bn)]
+    for it in range(1, maxit + 1):
+        q = A @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r_old = r.copy()
+        r -= alpha * q
+        hist.append(_rel(r, bn))
+        if hist[-1] <= tol:
+            return SolveResult(x, it, hist, True)
+        z = M(r)
+        beta = (z @ (r - r_old)) / rz
+        rz = r @ z
+        p = z + beta * p
+    return SolveResult(x, maxit, hist, False)
+
+
+def iterative_refinement(A, b, M: Callable, tol: float, maxit: int = 500) -> SolveResult:
+    """x <- x + M(b - A x)."""
+    bn = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    hist = [_rel(r, bn)]
+    for it in range(1, maxit + 1):
+        x = x + M(r)
+        r = b - A @ x
+        hist.append(_rel(r, bn))
+        if hist[-1] <= tol:
+            return SolveResult(x, it, hist, True)
+    return SolveResult(x, maxit, hist, False)
+
+
+def fgmres(A, b, M: Callable, tol: float, restart: int = 30, maxit: int = 500) -> SolveResult:
+    """Right-preconditioned flexible GMRES(m) with modified Gram-Schmidt."""
+    bn = np.linalg.norm(b)
+    n = b.size
+    x = np.zeros(n)
+    r = b.copy()
+    hist = [_rel(r, bn)]
+    it = 0
+    while it < maxit:
+        beta = np.linalg.norm(r)
+        V = np.zeros((restart + 1, n))
+        Z = np.zeros((restart, n))
+        Hm = np.zeros((restart + 1, restart))
+        V[0] = r / beta
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        cs = np.zeros(restart)
+        sn = np.zeros(restart)
+        k_done = 0
+        for k in range(restart):
+            Z[k] = M(V[k])
+            w = A @ Z[k]
+            for i in range(k + 1):
+                Hm[i, k] = w @ V[i]
+                w = w - Hm[i, k] * V[i]
+            Hm[k + 1, k] = np.linalg.norm(w)
+            if Hm[k + 1, k] > 0:
+                V[k + 1] = w / Hm[k + 1, k]
+            for i in range(k):
+                t = cs[i] * Hm[i, k] + sn[i] * Hm[i + 1, k]
+                Hm[i + 1, k] = -sn[i] * Hm[i, k] + cs[i] * Hm[i + 1, k]
+                Hm[i, k] = t
+            d = np.hypot(Hm[k, k], Hm[k + 1, k])
+            cs[k], sn[k] = Hm[k, k] / d, Hm[k + 1, k] / d
+            Hm[k, k] = d
+            Hm[k + 1, k] = 0.0
+            g[k + 1] = -sn[k] * g[k]
+            g[k] = cs[k] * g[k]
+            it += 1
+            k_done = k + 1
+            hist.append(abs(g[k + 1]) / bn)
+            if hist[-1] <= tol or it >= maxit:
+                break
+        y = sla.solve_triangular(Hm[:k_done, :k_done], g[:k_done])
+        x = x + Z[:k_done].T @ y
+        r = b - A @ x
+        hist[-1] = _rel(r, bn)
+        if hist[-1] <= tol:
+            return SolveResult(x, it, hist, True)
+    return SolveResult(x, it, hist, False)
+
+
+def minres(A, b, M: Callable, tol: float, maxit: int = 500) -> SolveResult:
+    """Preconditioned MINRES (Paige-Saunders) for symmetric A and SPD M."""
+    n = b.size
+    bn = np.linalg.norm(b)
+    x = np.zeros(n)
+    r1 = b.copy()
+    y = M(r1)
+    beta1 = np.sqrt(r1 @ y)
+    hist = [1.0]
+    if beta1 == 0:
+        return SolveResult(x, 0, hist, True)
+    oldb, beta, dbar, epsln, phibar = 0.0, beta1, 0.0, 0.0, beta1
+    cs, sn = -1.0, 0.0
+    w = np.zeros(n)
+    w2 = np.zeros(n)
+    r2 = r1.copy()
+    for it in range(1, maxit + 1):
+        s = 1.0 / beta
+        v = s * y
+        y = A @ v
+        if it >= 2:
+            y = y - (beta / oldb) * r1
+        alfa = v @ y
+        y = y - (alfa / beta) * r2
+        r1, r2 = r2, y
+        y = M(r2)
+        oldb, beta = beta, np.sqrt(r2 @ y)
+        oldeps = epsln
+        delta = cs * dbar + sn * alfa
+        gbar = sn * dbar - cs * alfa
+        epsln = sn * beta
+        dbar = -cs * beta
+        gamma = max(np.hypot(gbar, beta), 1e-300)
+        cs, sn = gbar / gamma, beta / gamma
+        phi = cs * phibar
+        phibar = sn * phibar
+        w1, w2 = w2, w
+        w = (v - oldeps * w1 - delta * w2) / gamma
+        x = x + phi * w
+        rel = _rel(b - A @ x, bn)
+        hist.append(rel)
+        if rel <= tol:
+            return SolveResult(x, it, hist, True)
+    return SolveResult(x, maxit, hist, False)

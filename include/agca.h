@@ -1,0 +1,212 @@
+/*
+ * agca.h -- C ABI of the AGCA multigrid library for MI355X (gfx950).
+ *
+ * Adaptive Galerkin coarse-grid approximation (AGCA) multigrid for the
+ * variable-coefficient P1 operators of "Large-scale multigrid with adaptive
+ * Galerkin coarsening" (Boehm, Kohl, Koestler, Ruede):
+ *   - scalar diffusion      -div(nu grad u) = f                  (ncomp = 1)
+ *   - vector viscous block  -div(2 nu eps(u)) = f, eq. (3.1)/(3.5) (ncomp = 3)
+ * on the unit cube with homogeneous Dirichlet data, discretised on the
+ * uniformly refined 48-tetrahedron macro grid (2x2x2 cubes, 6 tets each along
+ * the (1,1,1) diagonal), Section 2.1, eq. (2.2).
+ *
+ * Grid and numbering (all levels l = 0..L, n_l = 2^(l+1) cells per axis):
+ *   node  p = x + (n+1) (y + (n+1) z),        0 <= x,y,z <= n
+ *   elem  e = s + 6 (cx + n (cy + n cz)),     0 <= cx,cy,cz < n
+ *   where s = 0..5 is the axis order of the element's three unit steps from
+ *   its lowest corner: 0 xyz, 1 xzy, 2 yxz, 3 yzx, 4 zxy, 5 zyx.
+ *   Uniform (Bey) refinement maps element (C, s) to 8 children in the cubes
+ *   2C + {0, e_a1, e_a1 + e_a2, (1,1,1)}.
+ *
+ * Vectors ("level vectors") are SoA: ncomp blocks of (n_l+1)^3 values,
+ * component-major, one slot per lattice node including the boundary.
+ * Boundary slots are ignored on input and written as 0 on output.
+ * Coefficients are one value per element (P0), indexed by element id.
+ *
+ * Memory and streams: every pointer documented "device" is device memory owned
+ * by the caller (for example a contiguous torch tensor's data pointer).  The
+ * library copies the coefficients it keeps; it owns flags, Galerkin blocks,
+ * diagonals and work vectors.  Work is enqueued on the HIP stream given to
+ * agca_create.  apply / residual / smooth / restrict / prolong_add / vcycle /
+ * cast / grad / load_vector are asynchronous; create, set_nu, query, get_*,
+ * dot and solve synchronise that stream.
+ *
+ * Errors: every function returns an agca_status and never aborts or throws
+ * across the ABI.  A message describing the last error of the calling thread
+ * is available from agca_last_error().  After AGCA_E_HIP the hierarchy refuses
+ * further work with AGCA_E_STATE.
+ */
+#ifndef AGCA_H
+#define AGCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AGCA_OK = 0,
+    AGCA_E_INVALID = -1, /* bad argument, config or coefficient (non-finite or <= 0) */
+    AGCA_E_OOM = -2,     /* device allocation failed or mem_limit_bytes exceeded      */
+    AGCA_E_HIP = -3,     /* a HIP runtime call failed                                 */
+    AGCA_E_NOCONV = -4,  /* solver stopped at max_iter; x and stats are still filled   */
+    AGCA_E_NUMERIC = -5, /* solver saw a non-finite or exploding residual             */
+    AGCA_E_STATE = -6    /* hierarchy is in an error state                            */
+} agca_status;
+
+typedef enum { AGCA_F64 = 0, AGCA_F32 = 1, AGCA_BF16 = 2 } agca_dtype;
+
+/* Coarse-operator selection (Section 2.3).
+ *  RATIO : a level-l element (l < L) uses its stored Galerkin block when the
+ *          maximum of the finest coefficient over its finest descendants exceeds
+ *          flag_ratio times the minimum (strict, FP64); DCA otherwise.
+ *  NONE  : DCA on every coarse element (eq. (2.5)).
+ *  ALL   : Galerkin blocks on every coarse element (eqs. (2.6)-(2.7)). */
+enum { AGCA_FLAG_RATIO = 0, AGCA_FLAG_NONE = 2, AGCA_FLAG_ALL = 3 };
+
+typedef struct {
+    int32_t L;               /* finest level, 1 <= L <= 9                                  */
+    int32_t ncomp;           /* 1 or 3                                                      */
+    int32_t flag_mode;       /* AGCA_FLAG_*                                                 */
+    int32_t mg_dtype;        /* AGCA_F64 or AGCA_F32: precision of the V-cycle, its stored
+                                blocks, diagonals and work vectors                          */
+    int32_t mg_nu_dtype;     /* AGCA_F64, AGCA_F32 or AGCA_BF16: finest-level coefficient
+                                copy used by the V-cycle (must not be wider than mg_dtype)  */
+    int32_t pre_sweeps;      /* damped-Jacobi sweeps before / after the coarse correction   */
+    int32_t post_sweeps;
+    int32_t reserved;
+    double flag_ratio;       /* tau (10 in the paper's experiments)                         */
+    double omega;            /* Jacobi damping (2/3)                                        */
+    uint64_t mem_limit_bytes;/* 0 = unlimited; larger totals fail with AGCA_E_OOM           */
+} agca_config;
+
+typedef struct {
+    int64_t n;               /* cells per axis                                              */
+    int64_t nodes;           /* (n+1)^3                                                     */
+    int64_t free_nodes;      /* (n-1)^3                                                     */
+    int64_t elements;        /* 6 n^3                                                       */
+    int64_t flagged;         /* elements with a stored Galerkin block (0 on level L)        */
+    int64_t block_bytes;     /* bytes of stored Galerkin blocks on this level               */
+    int64_t level_bytes;     /* all device bytes the library holds for this level           */
+} agca_level_info;
+
+typedef struct agca_hier agca_hier;
+
+/* Fill a config with the defaults: L = 3, scalar, ratio flags, tau = 10,
+ * FP64 V-cycle, V(2,2) damped Jacobi with omega = 2/3.  Host only. */
+void agca_default_config(agca_config* cfg);
+
+/* Check a config without touching the device.  Host only. */
+int32_t agca_validate_config(const agca_config* cfg);
+
+/* Build the hierarchy (Sections 2.1-2.3): copy the coefficients, check them
+ * (finite, > 0), flag coarse elements, form the local Galerkin blocks of the
+ * flagged elements by the element-wise recursion (2.7) in FP64, and the Jacobi
+ * diagonals and the coarsest-level inverse.
+ *   nu_fine   : device, 6 n_L^3 doubles, finest-level coefficient by element id.
+ *   nu_coarse : host array of L device pointers; nu_coarse[l] holds 6 n_l^3
+ *               doubles, the coefficient evaluated on level l for DCA (eq. (2.5)).
+ *   stream    : hipStream_t (NULL = default stream).
+ * On success *out receives the handle; free it with agca_destroy. */
+int32_t agca_create(const agca_config* cfg, const double* nu_fine,
+                    const double* const* nu_coarse, void* stream, agca_hier** out);
+
+int32_t agca_destroy(agca_hier* h);
+
+/* Replace the coefficients and rebuild flags, blocks and diagonals. */
+int32_t agca_set_nu(agca_hier* h, const double* nu_fine, const double* const* nu_coarse);
+
+int32_t agca_query(const agca_hier* h, int32_t level, agca_level_info* out);
+
+/* Sorted ids of the flagged elements of a coarse level (host buffer of cap
+ * entries); *n receives the count even when cap is too small (then AGCA_E_INVALID). */
+int32_t agca_get_flags(const agca_hier* h, int32_t level, int32_t* ids_host, int64_t cap,
+                       int64_t* n);
+
+/* FP64 Galerkin blocks of a coarse level, in flagged-id order: flagged x
+ * (4 ncomp)^2 doubles, row (c, a) = 4 c + a, column (d, b) = 4 d + b, vertices a,b
+ * in path order (lowest corner first).  Host buffer of cap doubles. */
+int32_t agca_get_blocks(const agca_hier* h, int32_t level, double* blocks_host, int64_t cap);
+
+/* Jacobi diagonal of a level operator, FP64, as a host level vector (0 on the boundary). */
+int32_t agca_get_diagonal(const agca_hier* h, int32_t level, double* diag_host, int64_t cap);
+
+/* v = A_l u (eq. (2.3) on the finest level, eq. (2.9) on coarser levels).
+ * dtype AGCA_F64 uses the FP64 coefficients and blocks; AGCA_F32 needs
+ * mg_dtype == AGCA_F32 and uses the V-cycle's copies.  u, v: device level vectors. */
+int32_t agca_apply(agca_hier* h, int32_t level, int32_t dtype, const void* u, void* v);
+
+/* r = b - A_l x. */
+int32_t agca_residual(agca_hier* h, int32_t level, int32_t dtype, const void* b,
+                      const void* x, void* r);
+
+/* sweeps of damped Jacobi x <- x + omega D^-1 (b - A_l x), in place on x. */
+int32_t agca_smooth(agca_hier* h, int32_t level, int32_t dtype, int32_t sweeps, double omega,
+                    const void* b, void* x);
+
+/* r_c = P^T r_f with P the linear interpolation from level fine_level-1 (Section 2.1). */
+int32_t agca_restrict(agca_hier* h, int32_t fine_level, int32_t dtype, const void* r_f,
+                      void* r_c);
+
+/* x_f += P e_c, from level coarse_level to coarse_level+1. */
+int32_t agca_prolong_add(agca_hier* h, int32_t coarse_level, int32_t dtype, const void* e_c,
+                         void* x_f);
+
+/* x = B b: one V(pre,post)-cycle on level L from a zero initial guess, in the
+ * hierarchy's mg_dtype (dtype must equal it).  b, x: device level vectors. */
+int32_t agca_vcycle(agca_hier* h, int32_t dtype, const void* b, void* x);
+
+/* Deterministic reduction: *out = sum over all slots of x * y (FP64 accumulation). */
+int32_t agca_dot(agca_hier* h, int32_t level, int32_t dtype, const void* x, const void* y,
+                 double* out);
+
+/* Elementwise precision conversion with round-to-nearest-even:
+ * F64 -> F32, F32 -> F64, F64 -> BF16 (BF16 stored as uint16). count elements. */
+int32_t agca_cast(agca_hier* h, int32_t from, int32_t to, const void* src, void* dst,
+                  int64_t count);
+
+enum { AGCA_SOLVER_PCG = 0, AGCA_SOLVER_FCG = 1, AGCA_SOLVER_IR = 2, AGCA_SOLVER_STATIONARY = 3 };
+
+typedef struct {
+    int32_t solver;          /* AGCA_SOLVER_*                                              */
+    int32_t max_iter;
+    double tol;              /* stop when ||b - A x||_2 <= tol ||b||_2 (eq. (4.3))          */
+    int32_t use_x0;          /* 0: start from x = 0; 1: start from the given x              */
+    int32_t record_history;  /* store the relative residual of every iteration             */
+} agca_solve_opts;
+
+#define AGCA_MAX_HISTORY 1024
+typedef struct {
+    int32_t iterations;
+    int32_t converged;
+    double rel_residual;     /* final ||b - A x|| / ||b|| in FP64 with FP64 coefficients    */
+    double seconds;          /* wall time of the solve (after setup)                        */
+    double history[AGCA_MAX_HISTORY];
+} agca_solve_stats;
+
+/* Solve A_L x = b with the AGCA V-cycle as preconditioner inside an FP64 outer
+ * loop (PCG for an FP64 V-cycle; FCG(1) or iterative refinement around an FP32
+ * V-cycle; stationary V-cycle iteration).  b, x: device FP64 level vectors. */
+int32_t agca_solve(agca_hier* h, const agca_solve_opts* opts, const double* b, double* x,
+                   agca_solve_stats* stats);
+
+/* Adjoint gradient (not in the paper): g_e = -w_e^T A_e u_e for every finest
+ * element, i.e. dJ/dlog nu_e when w solves A w = u - u_obs.
+ * u, w: device FP64 level vectors on level L; g: device, 6 n_L^3 doubles. */
+int32_t agca_grad_log_nu(agca_hier* h, const double* u, const double* w, double* g);
+
+/* b = load vector of a per-element constant source: b_i = sum_e f_e |e| / 4 on
+ * level L.  f: device, ncomp blocks of 6 n_L^3 doubles; b: device FP64 level vector. */
+int32_t agca_load_vector(agca_hier* h, const double* f, double* b);
+
+/* Bytes of device memory the library holds for this hierarchy. */
+int64_t agca_device_bytes(const agca_hier* h);
+
+const char* agca_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AGCA_H */

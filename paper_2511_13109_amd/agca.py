@@ -1,0 +1,244 @@
+"""Python binding of the AGCA multigrid library (thin wrapper over include/agca.h).
+
+Device memory and streams come from PyTorch: vectors are contiguous CUDA
+(HIP) tensors and their data pointers are handed to the C ABI unchanged.  All
+arithmetic runs in the library's HIP kernels; if libagca.so is missing, the
+import of this module raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import AGCAError, check  # noqa: F401
+
+_DT = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16}
+_TORCH = {_lib.F64: torch.float64, _lib.F32: torch.float32}
+_FLAG = {"ratio": _lib.FLAG_RATIO, "none": _lib.FLAG_NONE, "dca": _lib.FLAG_NONE,
+         "all": _lib.FLAG_ALL, "gca": _lib.FLAG_ALL}
+_SOLVER = {"pcg": _lib.SOLVER_PCG, "fcg": _lib.SOLVER_FCG, "ir": _lib.SOLVER_IR,
+           "stationary": _lib.SOLVER_STATIONARY}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dtype_of(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return _lib.F64
+    if t.dtype == torch.float32:
+        return _lib.F32
+    raise ValueError(f"unsupported dtype {t.dtype}")
+
+
+def default_config() -> _lib.Config:
+    cfg = _lib.Config()
+    _lib.load().agca_default_config(C.byref(cfg))
+    return cfg
+
+
+def validate_config(cfg: _lib.Config) -> int:
+    return _lib.load().agca_validate_config(C.byref(cfg))
+
+
+class Hierarchy:
+    """AGCA multigrid hierarchy on levels 0..L (paper Section 2).
+
+    nu_fine: (6 n_L^3,) float64 device tensor; nu_coarse: L tensors, level l holding
+    6 n_l^3 float64 values (the DCA coefficient of that level).
+    """
+
+    def __init__(self, L: int, ncomp: int, nu_fine: torch.Tensor, nu_coarse: Sequence[torch.Tensor],
+                 flag_mode: str = "ratio", tau: float = 10.0, mg_dtype: str = "f64",
+                 mg_nu_dtype: Optional[str] = None, pre: int = 2, post: int = 2,
+                 omega: float = 2.0 / 3.0, mem_limit_bytes: int = 0, stream=None):
+        self._lib = _lib.load()
+        cfg = default_config()
+        cfg.L, cfg.ncomp = L, ncomp
+        cfg.flag_mode = _FLAG[flag_mode]
+        cfg.flag_ratio = tau
+        cfg.mg_dtype = _DT[mg_dtype]
+        cfg.mg_nu_dtype = _DT[mg_nu_dtype or mg_dtype]
+        cfg.pre_sweeps, cfg.post_sweeps, cfg.omega = pre, post, omega
+        cfg.mem_limit_bytes = mem_limit_bytes
+        self.cfg = cfg
+        self.L, self.ncomp = L, ncomp
+        self.mg_dtype = cfg.mg_dtype
+        self.device = nu_fine.device
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._keep = [nu_fine] + list(nu_coarse)
+        arr = (C.c_void_p * max(1, L))(*[t.data_ptr() for t in nu_coarse])
+        self._check_nu(nu_fine, nu_coarse)
+        h = C.c_void_p()
+        check(self._lib.agca_create(C.byref(cfg), _ptr(nu_fine), arr,
+                                    C.c_void_p(self._stream.cuda_stream), C.byref(h)), "agca_create")
+        self._h = h
+
+    def _check_nu(self, nu_fine, nu_coarse):
+        if len(nu_coarse) != self.L:
+            raise ValueError("need one coarse coefficient per level 0..L-1")
+        for l, t in enumerate(list(nu_coarse) + [nu_fine]):
+            lev = l if l < self.L else self.L
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("coefficients must be contiguous float64 device tensors")
+            if t.numel() != 6 * (2 ** (lev + 1)) ** 3:
+                raise ValueError(f"coefficient of level {lev} has the wrong size")
+
+    # -- lifecycle --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.agca_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_nu(self, nu_fine: torch.Tensor, nu_coarse: Sequence[torch.Tensor]):
+        self._check_nu(nu_fine, nu_coarse)
+        arr = (C.c_void_p * max(1, self.L))(*[t.data_ptr() for t in nu_coarse])
+        check(self._lib.agca_set_nu(self._h, _ptr(nu_fine), arr), "agca_set_nu")
+        self._keep = [nu_fine] + list(nu_coarse)
+
+    # -- sizes ------------------------------------------------------------
+    def n(self, level: int) -> int:
+        return 2 ** (level + 1)
+
+    def nodes(self, level: int) -> int:
+        return (self.n(level) + 1) ** 3
+
+    def vec(self, level: int, dtype=torch.float64) -> torch.Tensor:
+        return torch.zeros(self.ncomp * self.nodes(level), dtype=dtype, device=self.device)
+
+    def query(self, level: int) -> dict:
+        info = _lib.LevelInfo()
+        check(self._lib.agca_query(self._h, level, C.byref(info)), "agca_query")
+        return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def device_bytes(self) -> int:
+        return int(self._lib.agca_device_bytes(self._h))
+
+    def flags(self, level: int) -> np.ndarray:
+        n = C.c_int64()
+        info = self.query(level)
+        ids = np.zeros(max(1, info["flagged"]), dtype=np.int32)
+        check(self._lib.agca_get_flags(self._h, level, ids.ctypes.data_as(C.c_void_p), ids.size,
+                                       C.byref(n)), "agca_get_flags")
+        return ids[:n.value].copy()
+
+    def blocks(self, level: int) -> np.ndarray:
+        info = self.query(level)
+        M = 4 * self.ncomp
+        out = np.zeros((max(1, info["flagged"]), M, M))
+        check(self._lib.agca_get_blocks(self._h, level, out.ctypes.data_as(C.c_void_p), out.size),
+              "agca_get_blocks")
+        return out[:info["flagged"]].copy()
+
+    def diagonal(self, level: int) -> np.ndarray:
+        out = np.zeros(self.ncomp * self.nodes(level))
+        check(self._lib.agca_get_diagonal(self._h, level, out.ctypes.data_as(C.c_void_p), out.size),
+              "agca_get_diagonal")
+        return out
+
+    # -- level operations -------------------------------------------------
+    def apply(self, level: int, u: torch.Tensor, v: Optional[torch.Tensor] = None) -> torch.Tensor:
+        v = torch.empty_like(u) if v is None else v
+        check(self._lib.agca_apply(self._h, level, _dtype_of(u), _ptr(u), _ptr(v)), "agca_apply")
+        return v
+
+    def residual(self, level: int, b: torch.Tensor, x: torch.Tensor,
+                 r: Optional[torch.Tensor] = None) -> torch.Tensor:
+        r = torch.empty_like(b) if r is None else r
+        check(self._lib.agca_residual(self._h, level, _dtype_of(b), _ptr(b), _ptr(x), _ptr(r)),
+              "agca_residual")
+        return r
+
+    def smooth(self, level: int, b: torch.Tensor, x: torch.Tensor, sweeps: int,
+               omega: Optional[float] = None) -> torch.Tensor:
+        om = self.cfg.omega if omega is None else omega
+        check(self._lib.agca_smooth(self._h, level, _dtype_of(b), sweeps, om, _ptr(b), _ptr(x)),
+              "agca_smooth")
+        return x
+
+    def restrict(self, fine_level: int, r_f: torch.Tensor, r_c: Optional[torch.Tensor] = None):
+        r_c = self.vec(fine_level - 1, r_f.dtype) if r_c is None else r_c
+        check(self._lib.agca_restrict(self._h, fine_level, _dtype_of(r_f), _ptr(r_f), _ptr(r_c)),
+              "agca_restrict")
+        return r_c
+
+    def prolong_add(self, coarse_level: int, e_c: torch.Tensor, x_f: torch.Tensor):
+        check(self._lib.agca_prolong_add(self._h, coarse_level, _dtype_of(e_c), _ptr(e_c), _ptr(x_f)),
+              "agca_prolong_add")
+        return x_f
+
+    def vcycle(self, b: torch.Tensor, x: Optional[torch.Tensor] = None) -> torch.Tensor:
+        x = torch.empty_like(b) if x is None else x
+        check(self._lib.agca_vcycle(self._h, _dtype_of(b), _ptr(b), _ptr(x)), "agca_vcycle")
+        return x
+
+    def dot(self, level: int, x: torch.Tensor, y: torch.Tensor) -> float:
+        out = C.c_double()
+        check(self._lib.agca_dot(self._h, level, _dtype_of(x), _ptr(x), _ptr(y), C.byref(out)),
+              "agca_dot")
+        return out.value
+
+    def cast(self, src: torch.Tensor, to: str) -> torch.Tensor:
+        frm = _dtype_of(src)
+        code = _DT[to]
+        if code == _lib.BF16:
+            dst = torch.empty(src.numel(), dtype=torch.int16, device=src.device)
+        else:
+            dst = torch.empty(src.numel(), dtype=_TORCH[code], device=src.device)
+        check(self._lib.agca_cast(self._h, frm, code, _ptr(src), _ptr(dst), src.numel()), "agca_cast")
+        return dst
+
+    def solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, solver: str = "pcg",
+              tol: float = 1e-8, max_iter: int = 500, record_history: bool = True,
+              raise_on_noconv: bool = True):
+        opts = _lib.SolveOpts()
+        opts.solver = _SOLVER[solver]
+        opts.max_iter = max_iter
+        opts.tol = tol
+        opts.use_x0 = 0 if x is None else 1
+        opts.record_history = 1 if record_history else 0
+        x = torch.zeros_like(b) if x is None else x
+        st = _lib.SolveStats()
+        rc = self._lib.agca_solve(self._h, C.byref(opts), _ptr(b), _ptr(x), C.byref(st))
+        stats = {"iterations": st.iterations, "converged": bool(st.converged),
+                 "rel_residual": st.rel_residual, "seconds": st.seconds,
+                 "history": list(st.history[:min(st.iterations + 1, _lib.MAX_HISTORY)])
+                 if record_history else [], "status": rc}
+        if rc != _lib.AGCA_OK and (rc != _lib.AGCA_E_NOCONV or raise_on_noconv):
+            check(rc, "agca_solve")
+        return x, stats
+
+    def grad_log_nu(self, u: torch.Tensor, w: torch.Tensor, g: Optional[torch.Tensor] = None):
+        g = torch.empty(6 * self.n(self.L) ** 3, dtype=torch.float64, device=u.device) if g is None else g
+        check(self._lib.agca_grad_log_nu(self._h, _ptr(u), _ptr(w), _ptr(g)), "agca_grad_log_nu")
+        return g
+
+    def load_vector(self, f: torch.Tensor, b: Optional[torch.Tensor] = None) -> torch.Tensor:
+        b = self.vec(self.L) if b is None else b
+        check(self._lib.agca_load_vector(self._h, _ptr(f.contiguous()), _ptr(b)), "agca_load_vector")
+        return b
+
+
+def coefficients_from_field(field, L: int, device="cuda") -> List[torch.Tensor]:
+    """Sample a coefficient field at the element centroids of every level 0..L (host evaluation)."""
+    from .grid import element_centroids
+    out = []
+    for l in range(L + 1):
+        out.append(torch.from_numpy(np.ascontiguousarray(field.nu(element_centroids(l)))).to(device))
+    return out

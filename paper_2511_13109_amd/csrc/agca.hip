@@ -1,0 +1,938 @@
+// C ABI of the AGCA multigrid library: hierarchy construction, level
+// operations, V-cycle and FP64 outer solvers (declared in include/agca.h).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cube_math.h"
+#include "internal.h"
+
+using namespace agca;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+struct Level {
+    int n = 0;
+    int64_t nodes = 0, elems = 0;
+    double* nu64 = nullptr;      // finest: nu_L; coarse: DCA coefficient of this level
+    float* nu32 = nullptr;       // FP32 copy (FP32 V-cycle)
+    uint16_t* nubf = nullptr;    // BF16 copy of the finest coefficient (FP32 V-cycle option)
+    int32_t* flag = nullptr;
+    int32_t* blk = nullptr;
+    int32_t* ids = nullptr;
+    int64_t nflag = 0;
+    double* blocks64 = nullptr;
+    float* blocks32 = nullptr;
+    double* diag = nullptr;
+    double* dinv64 = nullptr;
+    float* dinv32 = nullptr;
+    void* b = nullptr;  // V-cycle work vectors, mg precision
+    void* x = nullptr;
+    void* t = nullptr;
+    void* r = nullptr;
+    int64_t bytes = 0;
+};
+
+}  // namespace
+
+struct agca_hier {
+    agca_config cfg{};
+    hipStream_t st = nullptr;
+    std::vector<Level> lv;
+    double* ainv0 = nullptr;
+    double* partial = nullptr;
+    int nb_partial = 1024;
+    double* red = nullptr;       // reduction results (device)
+    int* counter = nullptr;      // invalid-coefficient counter (device)
+    double* red_host = nullptr;  // pinned host mirror
+    // FP64 solver vectors on the finest level
+    double* s_r = nullptr;
+    double* s_z = nullptr;
+    double* s_p = nullptr;
+    double* s_q = nullptr;
+    double* s_ro = nullptr;
+    float* s_r32 = nullptr;
+    float* s_z32 = nullptr;
+    double* trans[2] = {nullptr, nullptr};
+    std::vector<void*> allocs;
+    int64_t bytes = 0;
+    bool error = false;
+};
+
+namespace {
+
+int64_t nodes_of(int n) { return (int64_t)(n + 1) * (n + 1) * (n + 1); }
+int64_t elems_of(int n) { return 6LL * n * n * n; }
+
+#define HIPCHK(h, call)                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            (h)->error = true;                                                                 \
+            return fail(AGCA_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+        }                                                                                      \
+    } while (0)
+
+int32_t dev_alloc(agca_hier* h, void** p, size_t bytes, int64_t* level_bytes = nullptr) {
+    *p = nullptr;
+    if (bytes == 0) return AGCA_OK;
+    if (h->cfg.mem_limit_bytes && (uint64_t)(h->bytes + (int64_t)bytes) > h->cfg.mem_limit_bytes)
+        return fail(AGCA_E_OOM, "mem_limit_bytes exceeded (" + std::to_string(h->bytes + bytes) +
+                                    " > " + std::to_string(h->cfg.mem_limit_bytes) + ")");
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(AGCA_E_OOM, "hipMalloc(" + std::to_string(bytes) + ") failed: " +
+                                    hipGetErrorString(e));
+    }
+    h->allocs.push_back(*p);
+    h->bytes += (int64_t)bytes;
+    if (level_bytes) *level_bytes += (int64_t)bytes;
+    return AGCA_OK;
+}
+
+template <typename P>
+int32_t alloc_t(agca_hier* h, P** p, size_t count, int64_t* lb = nullptr) {
+    void* v = nullptr;
+    int32_t rc = dev_alloc(h, &v, count * sizeof(P), lb);
+    *p = static_cast<P*>(v);
+    return rc;
+}
+
+#define TRY(x)                       \
+    do {                             \
+        int32_t rc_ = (x);           \
+        if (rc_ != AGCA_OK) return rc_; \
+    } while (0)
+
+bool mg32(const agca_hier* h) { return h->cfg.mg_dtype == AGCA_F32; }
+size_t mg_size(const agca_hier* h) { return mg32(h) ? sizeof(float) : sizeof(double); }
+
+template <typename T>
+LevelOp<T> level_op(const agca_hier* h, int l);
+
+template <>
+LevelOp<double> level_op<double>(const agca_hier* h, int l) {
+    const Level& L = h->lv[l];
+    LevelOp<double> op;
+    op.n = L.n;
+    op.nu = L.nu64;
+    op.nu_kind = AGCA_F64;
+    op.blk = (l < h->cfg.L && L.nflag > 0) ? L.blk : nullptr;
+    op.blocks = L.blocks64;
+    op.dinv = L.dinv64;
+    return op;
+}
+template <>
+LevelOp<float> level_op<float>(const agca_hier* h, int l) {
+    const Level& L = h->lv[l];
+    LevelOp<float> op;
+    op.n = L.n;
+    if (l == h->cfg.L && h->cfg.mg_nu_dtype == AGCA_BF16) {
+        op.nu = L.nubf;
+        op.nu_kind = AGCA_BF16;
+    } else {
+        op.nu = L.nu32;
+        op.nu_kind = AGCA_F32;
+    }
+    op.blk = (l < h->cfg.L && L.nflag > 0) ? L.blk : nullptr;
+    op.blocks = L.blocks32;
+    op.dinv = L.dinv32;
+    return op;
+}
+
+int32_t check_level(const agca_hier* h, int level) {
+    if (!h) return fail(AGCA_E_INVALID, "null hierarchy");
+    if (h->error) return fail(AGCA_E_STATE, "hierarchy is in an error state");
+    if (level < 0 || level > h->cfg.L) return fail(AGCA_E_INVALID, "level out of range");
+    return AGCA_OK;
+}
+
+int32_t check_dtype(const agca_hier* h, int dtype, bool need_mg) {
+    if (dtype != AGCA_F64 && dtype != AGCA_F32) return fail(AGCA_E_INVALID, "dtype must be F64 or F32");
+    if (dtype == AGCA_F32 && !mg32(h)) return fail(AGCA_E_INVALID, "F32 needs mg_dtype == F32");
+    if (need_mg && dtype != h->cfg.mg_dtype) return fail(AGCA_E_INVALID, "dtype must equal mg_dtype");
+    return AGCA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// level operations (templated on the vector precision)
+// ---------------------------------------------------------------------------
+template <typename T>
+int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, T omega) {
+    HIPCHK(h, launch_cube<T>(h->cfg.ncomp, mode, level_op<T>(h, l), u, b, out, omega, h->st));
+    return AGCA_OK;
+}
+
+template <typename T>
+int32_t do_smooth(agca_hier* h, int l, int sweeps, double omega, const T* b, T* x) {
+    T* tmp = static_cast<T*>(h->lv[l].t);
+    T* src = x;
+    T* dst = tmp;
+    for (int i = 0; i < sweeps; ++i) {
+        TRY(do_cube<T>(h, l, MODE_JACOBI, src, b, dst, T(omega)));
+        T* s = src;
+        src = dst;
+        dst = s;
+    }
+    if (src != x)
+        HIPCHK(h, hipMemcpyAsync(x, src, sizeof(T) * h->cfg.ncomp * h->lv[l].nodes,
+                                 hipMemcpyDeviceToDevice, h->st));
+    return AGCA_OK;
+}
+
+template <typename T>
+int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
+    const int L = h->cfg.L, nc = h->cfg.ncomp;
+    const double om = h->cfg.omega;
+    for (int l = L; l >= 1; --l) {
+        const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
+        T* xl = (l == L) ? xL : static_cast<T*>(h->lv[l].x);
+        HIPCHK(h, hipMemsetAsync(xl, 0, sizeof(T) * nc * h->lv[l].nodes, h->st));
+        TRY(do_smooth<T>(h, l, h->cfg.pre_sweeps, om, bl, xl));
+        T* rl = static_cast<T*>(h->lv[l].r);
+        TRY(do_cube<T>(h, l, MODE_RESIDUAL, xl, bl, rl, T(0)));
+        HIPCHK(h, launch_restrict<T>(nc, h->lv[l].n, rl, static_cast<T*>(h->lv[l - 1].b), h->st));
+    }
+    HIPCHK(h, launch_coarse_solve<T>(nc, h->ainv0, static_cast<const T*>(h->lv[0].b),
+                                     static_cast<T*>(h->lv[0].x), h->st));
+    for (int l = 1; l <= L; ++l) {
+        const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
+        T* xl = (l == L) ? xL : static_cast<T*>(h->lv[l].x);
+        HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, static_cast<const T*>(h->lv[l - 1].x), xl,
+                                        h->st));
+        TRY(do_smooth<T>(h, l, h->cfg.post_sweeps, om, bl, xl));
+    }
+    return AGCA_OK;
+}
+
+template <typename T>
+int32_t do_dot(agca_hier* h, const T* x, const T* y, int64_t count, double* out) {
+    HIPCHK(h, launch_dot_partial<T>(x, y, count, h->partial, h->nb_partial, h->st));
+    HIPCHK(h, launch_sum_partials(h->partial, h->nb_partial, h->red, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->red_host, h->red, sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    *out = h->red_host[0];
+    return AGCA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+int32_t validate(const agca_config* c) {
+    if (!c) return fail(AGCA_E_INVALID, "null config");
+    if (c->L < 1 || c->L > 9) return fail(AGCA_E_INVALID, "L must be in [1, 9]");
+    if (c->ncomp != 1 && c->ncomp != 3) return fail(AGCA_E_INVALID, "ncomp must be 1 or 3");
+    if (c->flag_mode != AGCA_FLAG_RATIO && c->flag_mode != AGCA_FLAG_NONE &&
+        c->flag_mode != AGCA_FLAG_ALL)
+        return fail(AGCA_E_INVALID, "unknown flag_mode");
+    if (c->mg_dtype != AGCA_F64 && c->mg_dtype != AGCA_F32)
+        return fail(AGCA_E_INVALID, "mg_dtype must be F64 or F32");
+    if (c->mg_nu_dtype != AGCA_F64 && c->mg_nu_dtype != AGCA_F32 && c->mg_nu_dtype != AGCA_BF16)
+        return fail(AGCA_E_INVALID, "mg_nu_dtype must be F64, F32 or BF16");
+    if (c->mg_dtype == AGCA_F64 && c->mg_nu_dtype != AGCA_F64)
+        return fail(AGCA_E_INVALID, "an FP64 V-cycle needs an FP64 coefficient");
+    if (c->mg_dtype == AGCA_F32 && c->mg_nu_dtype == AGCA_F64)
+        return fail(AGCA_E_INVALID, "an FP32 V-cycle uses an FP32 or BF16 coefficient");
+    if (c->pre_sweeps < 0 || c->post_sweeps < 0 || c->pre_sweeps > 64 || c->post_sweeps > 64)
+        return fail(AGCA_E_INVALID, "sweeps must be in [0, 64]");
+    if (!(c->omega > 0.0 && c->omega < 2.0)) return fail(AGCA_E_INVALID, "omega must be in (0, 2)");
+    if (!(c->flag_ratio >= 1.0) || !std::isfinite(c->flag_ratio))
+        return fail(AGCA_E_INVALID, "flag_ratio must be finite and >= 1");
+    return AGCA_OK;
+}
+
+int32_t count_invalid(agca_hier* h, const double* v, int64_t n, int* out) {
+    int* cnt = h->counter;
+    HIPCHK(h, hipMemsetAsync(cnt, 0, sizeof(int), h->st));
+    HIPCHK(h, launch_count_invalid(v, n, cnt, h->st));
+    HIPCHK(h, hipMemcpyAsync(out, cnt, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return AGCA_OK;
+}
+
+// level-0 operator on its single free node (1,1,1): ncomp x ncomp, inverted on the host
+int32_t build_coarsest(agca_hier* h) {
+    const int nc = h->cfg.ncomp, M = 4 * nc;
+    Level& L0 = h->lv[0];
+    std::vector<double> nu(48);
+    HIPCHK(h, hipMemcpyAsync(nu.data(), L0.nu64, 48 * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    std::vector<int32_t> blk(48, -1);
+    std::vector<double> blocks;
+    const bool has_blocks = h->cfg.L > 0 && L0.nflag > 0;
+    if (has_blocks) {
+        HIPCHK(h, hipMemcpyAsync(blk.data(), L0.blk, 48 * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+        blocks.resize((size_t)L0.nflag * M * M);
+        HIPCHK(h, hipMemcpyAsync(blocks.data(), L0.blocks64, blocks.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->st));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const double scale = 1.0 / (6.0 * 2);
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    // node (1,1,1) is corner k = 7 - (cell offset bits) of each of the 8 cells
+    for (int cell = 0; cell < 8; ++cell) {
+        const int k = 7 - cell;  // cell (cx,cy,cz) = bits of 'cell'; node at corner 7 - cell
+        for (int s = 0; s < 6; ++s) {
+            int a = -1;
+            for (int j = 0; j < 4; ++j)
+                if (path_corner(s, j) == k) a = j;
+            if (a < 0) continue;
+            const int e = 6 * cell + s;
+            for (int c = 0; c < nc; ++c)
+                for (int d = 0; d < nc; ++d) {
+                    double v;
+                    if (blk[e] >= 0)
+                        v = blocks[(size_t)blk[e] * M * M + (4 * c + a) * M + 4 * d + a];
+                    else
+                        v = nu[e] * scale * elem_entry(nc, s, c, a, d, a);
+                    A[c][d] += v;
+                }
+        }
+    }
+    double inv[9] = {0};
+    if (nc == 1) {
+        if (!(A[0][0] > 0)) return fail(AGCA_E_NUMERIC, "coarsest operator is not positive");
+        inv[0] = 1.0 / A[0][0];
+    } else {
+        const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                           A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        if (!(std::fabs(det) > 0)) return fail(AGCA_E_NUMERIC, "coarsest operator is singular");
+        inv[0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+        inv[1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+        inv[2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+        inv[3] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+        inv[4] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+        inv[5] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+        inv[6] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+        inv[7] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+        inv[8] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+    }
+    HIPCHK(h, hipMemcpyAsync(h->ainv0, inv, sizeof(double) * nc * nc, hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return AGCA_OK;
+}
+
+int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const* nu_coarse) {
+    const int L = h->cfg.L, nc = h->cfg.ncomp, M = 4 * nc;
+    // coefficients
+    for (int l = 0; l <= L; ++l) {
+        const double* src = (l == L) ? nu_fine : nu_coarse[l];
+        if (!src) return fail(AGCA_E_INVALID, "null coefficient pointer for level " + std::to_string(l));
+        HIPCHK(h, hipMemcpyAsync(h->lv[l].nu64, src, sizeof(double) * h->lv[l].elems,
+                                 hipMemcpyDeviceToDevice, h->st));
+    }
+    for (int l = 0; l <= L; ++l) {
+        int bad = 0;
+        TRY(count_invalid(h, h->lv[l].nu64, h->lv[l].elems, &bad));
+        if (bad)
+            return fail(AGCA_E_INVALID, std::to_string(bad) + " coefficient values on level " +
+                                            std::to_string(l) + " are not finite and positive");
+    }
+    // flags: min/max pyramid from level L-1 down to 0
+    {
+        double *mn[2] = {nullptr, nullptr}, *mx[2] = {nullptr, nullptr};
+        const int64_t emax = h->lv[L - 1].elems;
+        void* scratch = nullptr;
+        size_t sbytes = 0;
+        HIPCHK(h, compact_scratch_bytes(emax, &sbytes));
+        // transient buffers: allocated with plain hipMalloc and released at the end of setup
+        std::vector<void*> tmp;
+        auto talloc = [&](void** p, size_t bytes) -> int32_t {
+            hipError_t e = hipMalloc(p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(AGCA_E_OOM, "transient hipMalloc failed");
+            }
+            tmp.push_back(*p);
+            return AGCA_OK;
+        };
+        auto release = [&]() {
+            hipStreamSynchronize(h->st);
+            for (void* p : tmp) hipFree(p);
+            tmp.clear();
+        };
+        int32_t rc = AGCA_OK;
+        for (int i = 0; i < 2 && rc == AGCA_OK; ++i) {
+            rc = talloc((void**)&mn[i], emax * sizeof(double));
+            if (rc == AGCA_OK) rc = talloc((void**)&mx[i], emax * sizeof(double));
+        }
+        if (rc == AGCA_OK) rc = talloc(&scratch, sbytes);
+        int64_t* cnt_dev = nullptr;
+        if (rc == AGCA_OK) rc = talloc((void**)&cnt_dev, sizeof(int64_t) * 16);
+        if (rc != AGCA_OK) {
+            release();
+            return rc;
+        }
+        for (int l = L - 1; l >= 0; --l) {
+            const int cur = l & 1, fin = (l + 1) & 1;
+            hipError_t e = (l == L - 1)
+                               ? launch_minmax_from_fine(h->lv[l].n, h->lv[L].nu64, mn[cur], mx[cur], h->st)
+                               : launch_minmax_up(h->lv[l].n, mn[fin], mx[fin], mn[cur], mx[cur], h->st);
+            if (e == hipSuccess)
+                e = launch_flag(h->lv[l].elems, mn[cur], mx[cur], h->cfg.flag_ratio, h->cfg.flag_mode,
+                                h->lv[l].flag, h->st);
+            if (e == hipSuccess)
+                e = launch_compact(h->lv[l].elems, h->lv[l].flag, h->lv[l].blk, h->lv[l].ids,
+                                   cnt_dev + l, scratch, sbytes, h->st);
+            if (e != hipSuccess) {
+                release();
+                h->error = true;
+                return fail(AGCA_E_HIP, std::string("flag kernels: ") + hipGetErrorString(e));
+            }
+        }
+        std::vector<int64_t> counts(16, 0);
+        hipError_t e = hipMemcpyAsync(counts.data(), cnt_dev, sizeof(int64_t) * L,
+                                      hipMemcpyDeviceToHost, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+        release();
+        if (e != hipSuccess) {
+            h->error = true;
+            return fail(AGCA_E_HIP, std::string("flag count readback: ") + hipGetErrorString(e));
+        }
+        for (int l = 0; l < L; ++l) h->lv[l].nflag = counts[l];
+    }
+    // block storage
+    for (int l = 0; l < L; ++l) {
+        Level& lv = h->lv[l];
+        lv.blocks64 = nullptr;
+        lv.blocks32 = nullptr;
+        if (lv.nflag > 0) {
+            TRY(alloc_t(h, &lv.blocks64, (size_t)lv.nflag * M * M, &lv.bytes));
+            if (mg32(h)) TRY(alloc_t(h, &lv.blocks32, (size_t)lv.nflag * M * M, &lv.bytes));
+        }
+    }
+    // Galerkin blocks, bottom-up (eq. (2.7))
+    {
+        int lowest = -1;  // coarsest... any flagged level <= L-2 ?
+        for (int l = 0; l <= L - 2; ++l)
+            if (h->lv[l].nflag > 0) {
+                lowest = l;
+                break;
+            }
+        const double h_fine = 1.0 / h->lv[L].n;
+        if (lowest < 0) {
+            if (L >= 1 && h->lv[L - 1].nflag > 0)
+                HIPCHK(h, launch_gca_from_fine(nc, h->lv[L - 1].n, h->lv[L - 1].nflag, h->lv[L - 1].ids,
+                                               h->lv[L].nu64, h_fine, h->lv[L - 1].blocks64, h->st));
+        } else {
+            // levels L-2 .. lowest need the Galerkin matrices of every element of the level
+            // below them while any coarser level is flagged; transient ping-pong buffers
+            std::vector<void*> tmp;
+            int32_t rc = AGCA_OK;
+            for (int i = 0; i < 2; ++i) {
+                const int l = L - 2 - i;
+                if (l < lowest + 1) break;  // trans of level l is needed only if some level < l is flagged
+                void* p = nullptr;
+                hipError_t e = hipMalloc(&p, (size_t)h->lv[l].elems * M * M * sizeof(double));
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    rc = fail(AGCA_E_OOM, "transient Galerkin buffer allocation failed");
+                    break;
+                }
+                tmp.push_back(p);
+                h->trans[i] = static_cast<double*>(p);
+            }
+            if (rc == AGCA_OK) {
+                const int l2 = L - 2;
+                double* out2 = (l2 > lowest) ? h->trans[0] : nullptr;
+                hipError_t e = launch_gca_fused2(nc, h->lv[l2].n, h->lv[L].nu64, h_fine, h->lv[L - 1].blk,
+                                                 h->lv[L - 1].blocks64, h->lv[l2].blk, h->lv[l2].blocks64,
+                                                 out2, h->st);
+                int cur = 0;
+                for (int l = L - 3; l >= lowest && e == hipSuccess; --l) {
+                    double* in = h->trans[cur];
+                    // trans[1-cur] held level l+2 (no longer needed) and is large enough
+                    double* out = (l > lowest) ? h->trans[1 - cur] : nullptr;
+                    e = launch_gca_up(nc, h->lv[l].n, in, h->lv[l].blk, h->lv[l].blocks64, out, h->st);
+                    cur = 1 - cur;
+                }
+                if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+                if (e != hipSuccess) {
+                    h->error = true;
+                    rc = fail(AGCA_E_HIP, std::string("Galerkin kernels: ") + hipGetErrorString(e));
+                }
+            }
+            for (void* p : tmp) hipFree(p);
+            h->trans[0] = h->trans[1] = nullptr;
+            if (rc != AGCA_OK) return rc;
+        }
+    }
+    // diagonals, FP32 copies
+    for (int l = 0; l <= L; ++l) {
+        Level& lv = h->lv[l];
+        const double scale = 1.0 / (6.0 * lv.n);
+        HIPCHK(h, launch_diagonal(nc, lv.n, lv.nu64, scale, (l < L && lv.nflag > 0) ? lv.blk : nullptr,
+                                  lv.blocks64, lv.diag, h->st));
+        const int64_t cnt = (int64_t)nc * lv.nodes;
+        if (mg32(h)) {
+            HIPCHK(h, launch_invert_diag<float>(cnt, lv.diag, lv.dinv32, h->st));
+            // the finest level holds either an FP32 or a BF16 copy, coarse levels an FP32 one
+            if (l == L && h->cfg.mg_nu_dtype == AGCA_BF16)
+                HIPCHK(h, launch_cast(AGCA_F64, AGCA_BF16, lv.nu64, lv.nubf, lv.elems, h->st));
+            else
+                HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, lv.nu64, lv.nu32, lv.elems, h->st));
+            if (lv.blocks32)
+                HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, lv.blocks64, lv.blocks32,
+                                      (int64_t)lv.nflag * M * M, h->st));
+        } else {
+            HIPCHK(h, launch_invert_diag<double>(cnt, lv.diag, lv.dinv64, h->st));
+        }
+    }
+    TRY(build_coarsest(h));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return AGCA_OK;
+}
+
+void free_all(agca_hier* h) {
+    if (h->st) hipStreamSynchronize(h->st);
+    for (void* p : h->allocs) hipFree(p);
+    h->allocs.clear();
+    if (h->red_host) hipHostFree(h->red_host);
+    h->red_host = nullptr;
+}
+
+int32_t free_blocks(agca_hier* h) {
+    // blocks are re-sized on every rebuild: drop the old ones from the allocation list
+    for (auto& lv : h->lv) {
+        for (void* p : {(void*)lv.blocks64, (void*)lv.blocks32}) {
+            if (!p) continue;
+            for (size_t i = 0; i < h->allocs.size(); ++i)
+                if (h->allocs[i] == p) {
+                    hipFree(p);
+                    h->allocs.erase(h->allocs.begin() + i);
+                    break;
+                }
+        }
+        const int M = 4 * h->cfg.ncomp;
+        const int64_t freed = (lv.blocks64 ? lv.nflag * M * M * (int64_t)sizeof(double) : 0) +
+                              (lv.blocks32 ? lv.nflag * M * M * (int64_t)sizeof(float) : 0);
+        h->bytes -= freed;
+        lv.bytes -= freed;
+        lv.blocks64 = nullptr;
+        lv.blocks32 = nullptr;
+        lv.nflag = 0;
+    }
+    return AGCA_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// ABI
+// ===========================================================================
+extern "C" {
+
+const char* agca_last_error(void) { return g_err.c_str(); }
+
+void agca_default_config(agca_config* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->L = 3;
+    c->ncomp = 1;
+    c->flag_mode = AGCA_FLAG_RATIO;
+    c->mg_dtype = AGCA_F64;
+    c->mg_nu_dtype = AGCA_F64;
+    c->pre_sweeps = 2;
+    c->post_sweeps = 2;
+    c->flag_ratio = 10.0;
+    c->omega = 2.0 / 3.0;
+    c->mem_limit_bytes = 0;
+}
+
+int32_t agca_validate_config(const agca_config* cfg) { return validate(cfg); }
+
+int32_t agca_create(const agca_config* cfg, const double* nu_fine, const double* const* nu_coarse,
+                    void* stream, agca_hier** out) {
+    if (!out) return fail(AGCA_E_INVALID, "null output handle");
+    *out = nullptr;
+    TRY(validate(cfg));
+    if (!nu_fine || !nu_coarse) return fail(AGCA_E_INVALID, "null coefficient pointer");
+    agca_hier* h = new agca_hier();
+    h->cfg = *cfg;
+    h->st = static_cast<hipStream_t>(stream);
+    const int L = cfg->L, nc = cfg->ncomp;
+    const size_t ts = mg_size(h);
+    auto bail = [&](int32_t rc) {
+        std::string msg = g_err;
+        free_all(h);
+        delete h;
+        g_err = msg;
+        return rc;
+    };
+    h->lv.resize(L + 1);
+    int32_t rc = AGCA_OK;
+    for (int l = 0; l <= L && rc == AGCA_OK; ++l) {
+        Level& lv = h->lv[l];
+        lv.n = 1 << (l + 1);
+        lv.nodes = nodes_of(lv.n);
+        lv.elems = elems_of(lv.n);
+        const int64_t nv = (int64_t)nc * lv.nodes;
+        rc = alloc_t(h, &lv.nu64, lv.elems, &lv.bytes);
+        if (rc == AGCA_OK && mg32(h) && !(l == L && cfg->mg_nu_dtype == AGCA_BF16))
+            rc = alloc_t(h, &lv.nu32, lv.elems, &lv.bytes);
+        if (rc == AGCA_OK && mg32(h) && l == L && cfg->mg_nu_dtype == AGCA_BF16)
+            rc = alloc_t(h, &lv.nubf, lv.elems, &lv.bytes);
+        if (rc == AGCA_OK && l < L) rc = alloc_t(h, &lv.flag, lv.elems, &lv.bytes);
+        if (rc == AGCA_OK && l < L) rc = alloc_t(h, &lv.blk, lv.elems, &lv.bytes);
+        if (rc == AGCA_OK && l < L) rc = alloc_t(h, &lv.ids, lv.elems, &lv.bytes);
+        if (rc == AGCA_OK) rc = alloc_t(h, &lv.diag, nv, &lv.bytes);
+        if (rc == AGCA_OK && mg32(h)) rc = alloc_t(h, &lv.dinv32, nv, &lv.bytes);
+        if (rc == AGCA_OK && !mg32(h)) rc = alloc_t(h, &lv.dinv64, nv, &lv.bytes);
+        if (rc == AGCA_OK && l < L) rc = dev_alloc(h, &lv.b, nv * ts, &lv.bytes);
+        if (rc == AGCA_OK && l < L) rc = dev_alloc(h, &lv.x, nv * ts, &lv.bytes);
+        if (rc == AGCA_OK && l > 0) rc = dev_alloc(h, &lv.t, nv * ts, &lv.bytes);
+        if (rc == AGCA_OK && l > 0) rc = dev_alloc(h, &lv.r, nv * ts, &lv.bytes);
+    }
+    if (rc == AGCA_OK) rc = alloc_t(h, &h->ainv0, 9);
+    if (rc == AGCA_OK) rc = alloc_t(h, &h->partial, h->nb_partial);
+    if (rc == AGCA_OK) rc = alloc_t(h, &h->red, 16);
+    if (rc == AGCA_OK) rc = alloc_t(h, &h->counter, 4);
+    if (rc == AGCA_OK) {
+        hipError_t e = hipHostMalloc((void**)&h->red_host, 16 * sizeof(double));
+        if (e != hipSuccess) rc = fail(AGCA_E_OOM, "hipHostMalloc failed");
+    }
+    if (rc != AGCA_OK) return bail(rc);
+    rc = build_operators(h, nu_fine, nu_coarse);
+    if (rc != AGCA_OK) return bail(rc);
+    *out = h;
+    return AGCA_OK;
+}
+
+int32_t agca_destroy(agca_hier* h) {
+    if (!h) return AGCA_OK;
+    free_all(h);
+    delete h;
+    return AGCA_OK;
+}
+
+int32_t agca_set_nu(agca_hier* h, const double* nu_fine, const double* const* nu_coarse) {
+    TRY(check_level(h, 0));
+    if (!nu_fine || !nu_coarse) return fail(AGCA_E_INVALID, "null coefficient pointer");
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    free_blocks(h);
+    return build_operators(h, nu_fine, nu_coarse);
+}
+
+int32_t agca_query(const agca_hier* h, int32_t level, agca_level_info* out) {
+    TRY(check_level(h, level));
+    if (!out) return fail(AGCA_E_INVALID, "null output");
+    const Level& lv = h->lv[level];
+    const int M = 4 * h->cfg.ncomp;
+    out->n = lv.n;
+    out->nodes = lv.nodes;
+    out->free_nodes = (int64_t)(lv.n - 1) * (lv.n - 1) * (lv.n - 1);
+    out->elements = lv.elems;
+    out->flagged = level < h->cfg.L ? lv.nflag : 0;
+    out->block_bytes = (lv.blocks64 ? lv.nflag * M * M * 8 : 0) + (lv.blocks32 ? lv.nflag * M * M * 4 : 0);
+    out->level_bytes = lv.bytes;
+    return AGCA_OK;
+}
+
+int32_t agca_get_flags(const agca_hier* h, int32_t level, int32_t* ids_host, int64_t cap, int64_t* n) {
+    TRY(check_level(h, level));
+    if (level >= h->cfg.L) return fail(AGCA_E_INVALID, "the finest level has no flags");
+    const Level& lv = h->lv[level];
+    if (n) *n = lv.nflag;
+    if (cap < lv.nflag || (!ids_host && lv.nflag > 0)) return fail(AGCA_E_INVALID, "ids buffer too small");
+    agca_hier* hh = const_cast<agca_hier*>(h);
+    if (lv.nflag > 0) {
+        HIPCHK(hh, hipMemcpyAsync(ids_host, lv.ids, lv.nflag * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hh, hipStreamSynchronize(h->st));
+    }
+    return AGCA_OK;
+}
+
+int32_t agca_get_blocks(const agca_hier* h, int32_t level, double* blocks_host, int64_t cap) {
+    TRY(check_level(h, level));
+    if (level >= h->cfg.L) return fail(AGCA_E_INVALID, "the finest level has no blocks");
+    const Level& lv = h->lv[level];
+    const int M = 4 * h->cfg.ncomp;
+    if (cap < lv.nflag * M * M) return fail(AGCA_E_INVALID, "blocks buffer too small");
+    agca_hier* hh = const_cast<agca_hier*>(h);
+    if (lv.nflag > 0) {
+        HIPCHK(hh, hipMemcpyAsync(blocks_host, lv.blocks64, lv.nflag * M * M * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hh, hipStreamSynchronize(h->st));
+    }
+    return AGCA_OK;
+}
+
+int32_t agca_get_diagonal(const agca_hier* h, int32_t level, double* diag_host, int64_t cap) {
+    TRY(check_level(h, level));
+    const Level& lv = h->lv[level];
+    const int64_t cnt = (int64_t)h->cfg.ncomp * lv.nodes;
+    if (cap < cnt || !diag_host) return fail(AGCA_E_INVALID, "diagonal buffer too small");
+    agca_hier* hh = const_cast<agca_hier*>(h);
+    HIPCHK(hh, hipMemcpyAsync(diag_host, lv.diag, cnt * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hh, hipStreamSynchronize(h->st));
+    return AGCA_OK;
+}
+
+int32_t agca_apply(agca_hier* h, int32_t level, int32_t dtype, const void* u, void* v) {
+    TRY(check_level(h, level));
+    TRY(check_dtype(h, dtype, false));
+    if (!u || !v || u == v) return fail(AGCA_E_INVALID, "u and v must be distinct non-null vectors");
+    if (dtype == AGCA_F64)
+        return do_cube<double>(h, level, MODE_APPLY, (const double*)u, nullptr, (double*)v, 0.0);
+    return do_cube<float>(h, level, MODE_APPLY, (const float*)u, nullptr, (float*)v, 0.0f);
+}
+
+int32_t agca_residual(agca_hier* h, int32_t level, int32_t dtype, const void* b, const void* x, void* r) {
+    TRY(check_level(h, level));
+    TRY(check_dtype(h, dtype, false));
+    if (!b || !x || !r || r == x) return fail(AGCA_E_INVALID, "bad vector pointers");
+    if (dtype == AGCA_F64)
+        return do_cube<double>(h, level, MODE_RESIDUAL, (const double*)x, (const double*)b, (double*)r, 0.0);
+    return do_cube<float>(h, level, MODE_RESIDUAL, (const float*)x, (const float*)b, (float*)r, 0.0f);
+}
+
+int32_t agca_smooth(agca_hier* h, int32_t level, int32_t dtype, int32_t sweeps, double omega,
+                    const void* b, void* x) {
+    TRY(check_level(h, level));
+    TRY(check_dtype(h, dtype, true));
+    if (level == 0) return fail(AGCA_E_INVALID, "level 0 is solved directly");
+    if (!b || !x || b == x) return fail(AGCA_E_INVALID, "bad vector pointers");
+    if (sweeps < 0) return fail(AGCA_E_INVALID, "sweeps must be >= 0");
+    if (dtype == AGCA_F64) return do_smooth<double>(h, level, sweeps, omega, (const double*)b, (double*)x);
+    return do_smooth<float>(h, level, sweeps, omega, (const float*)b, (float*)x);
+}
+
+int32_t agca_restrict(agca_hier* h, int32_t fine_level, int32_t dtype, const void* r_f, void* r_c) {
+    TRY(check_level(h, fine_level));
+    TRY(check_dtype(h, dtype, false));
+    if (fine_level == 0) return fail(AGCA_E_INVALID, "level 0 has no coarser level");
+    if (!r_f || !r_c) return fail(AGCA_E_INVALID, "null vector");
+    if (dtype == AGCA_F64)
+        HIPCHK(h, launch_restrict<double>(h->cfg.ncomp, h->lv[fine_level].n, (const double*)r_f, (double*)r_c, h->st));
+    else
+        HIPCHK(h, launch_restrict<float>(h->cfg.ncomp, h->lv[fine_level].n, (const float*)r_f, (float*)r_c, h->st));
+    return AGCA_OK;
+}
+
+int32_t agca_prolong_add(agca_hier* h, int32_t coarse_level, int32_t dtype, const void* e_c, void* x_f) {
+    TRY(check_level(h, coarse_level));
+    TRY(check_dtype(h, dtype, false));
+    if (coarse_level >= h->cfg.L) return fail(AGCA_E_INVALID, "no finer level");
+    if (!e_c || !x_f) return fail(AGCA_E_INVALID, "null vector");
+    const int nf = h->lv[coarse_level + 1].n;
+    if (dtype == AGCA_F64)
+        HIPCHK(h, launch_prolong_add<double>(h->cfg.ncomp, nf, (const double*)e_c, (double*)x_f, h->st));
+    else
+        HIPCHK(h, launch_prolong_add<float>(h->cfg.ncomp, nf, (const float*)e_c, (float*)x_f, h->st));
+    return AGCA_OK;
+}
+
+int32_t agca_vcycle(agca_hier* h, int32_t dtype, const void* b, void* x) {
+    TRY(check_level(h, 0));
+    TRY(check_dtype(h, dtype, true));
+    if (!b || !x || b == x) return fail(AGCA_E_INVALID, "bad vector pointers");
+    if (dtype == AGCA_F64) return do_vcycle<double>(h, (const double*)b, (double*)x);
+    return do_vcycle<float>(h, (const float*)b, (float*)x);
+}
+
+int32_t agca_dot(agca_hier* h, int32_t level, int32_t dtype, const void* x, const void* y, double* out) {
+    TRY(check_level(h, level));
+    TRY(check_dtype(h, dtype, false));
+    if (!x || !y || !out) return fail(AGCA_E_INVALID, "null pointer");
+    const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[level].nodes;
+    if (dtype == AGCA_F64) return do_dot<double>(h, (const double*)x, (const double*)y, cnt, out);
+    return do_dot<float>(h, (const float*)x, (const float*)y, cnt, out);
+}
+
+int32_t agca_cast(agca_hier* h, int32_t from, int32_t to, const void* src, void* dst, int64_t count) {
+    TRY(check_level(h, 0));
+    const bool ok = (from == AGCA_F64 && (to == AGCA_F32 || to == AGCA_BF16 || to == AGCA_F64)) ||
+                    (from == AGCA_F32 && (to == AGCA_F64 || to == AGCA_F32));
+    if (!ok) return fail(AGCA_E_INVALID, "unsupported conversion");
+    if (count < 0 || (count > 0 && (!src || !dst))) return fail(AGCA_E_INVALID, "bad buffers");
+    if (count == 0) return AGCA_OK;
+    HIPCHK(h, launch_cast(from, to, src, dst, count, h->st));
+    return AGCA_OK;
+}
+
+int64_t agca_device_bytes(const agca_hier* h) { return h ? h->bytes : 0; }
+
+int32_t agca_grad_log_nu(agca_hier* h, const double* u, const double* w, double* g) {
+    TRY(check_level(h, 0));
+    if (!u || !w || !g) return fail(AGCA_E_INVALID, "null pointer");
+    const Level& lv = h->lv[h->cfg.L];
+    HIPCHK(h, launch_grad(h->cfg.ncomp, lv.n, lv.nu64, 1.0 / (6.0 * lv.n), u, w, g, h->st));
+    return AGCA_OK;
+}
+
+int32_t agca_load_vector(agca_hier* h, const double* f, double* b) {
+    TRY(check_level(h, 0));
+    if (!f || !b) return fail(AGCA_E_INVALID, "null pointer");
+    const Level& lv = h->lv[h->cfg.L];
+    const double hh = 1.0 / lv.n;
+    HIPCHK(h, launch_load_vector(h->cfg.ncomp, lv.n, f, hh * hh * hh / 6.0 / 4.0, b, h->st));
+    return AGCA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solvers
+// ---------------------------------------------------------------------------
+static int32_t ensure_solver_vectors(agca_hier* h) {
+    if (h->s_r) return AGCA_OK;
+    const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[h->cfg.L].nodes;
+    TRY(alloc_t(h, &h->s_r, cnt));
+    TRY(alloc_t(h, &h->s_z, cnt));
+    TRY(alloc_t(h, &h->s_p, cnt));
+    TRY(alloc_t(h, &h->s_q, cnt));
+    TRY(alloc_t(h, &h->s_ro, cnt));
+    if (mg32(h)) {
+        TRY(alloc_t(h, &h->s_r32, cnt));
+        TRY(alloc_t(h, &h->s_z32, cnt));
+    }
+    return AGCA_OK;
+}
+
+// z = B r with the hierarchy's V-cycle (FP32 V-cycle: cast in and out)
+static int32_t precondition(agca_hier* h, const double* r, double* z) {
+    if (!mg32(h)) return do_vcycle<double>(h, r, z);
+    const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[h->cfg.L].nodes;
+    HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, r, h->s_r32, cnt, h->st));
+    TRY(do_vcycle<float>(h, h->s_r32, h->s_z32));
+    HIPCHK(h, launch_cast(AGCA_F32, AGCA_F64, h->s_z32, z, cnt, h->st));
+    return AGCA_OK;
+}
+
+int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, double* x,
+                   agca_solve_stats* stats) {
+    TRY(check_level(h, 0));
+    if (!o || !b || !x || !stats) return fail(AGCA_E_INVALID, "null pointer");
+    if (o->max_iter < 0 || !(o->tol >= 0.0)) return fail(AGCA_E_INVALID, "bad solve options");
+    if (o->solver < AGCA_SOLVER_PCG || o->solver > AGCA_SOLVER_STATIONARY)
+        return fail(AGCA_E_INVALID, "unknown solver");
+    TRY(ensure_solver_vectors(h));
+    std::memset(stats, 0, sizeof(*stats));
+    const int L = h->cfg.L;
+    const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[L].nodes;
+    double *r = h->s_r, *z = h->s_z, *p = h->s_p, *q = h->s_q, *ro = h->s_ro;
+    auto t0 = std::chrono::steady_clock::now();
+    if (!o->use_x0) HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * cnt, h->st));
+    HIPCHK(h, launch_zero_boundary<double>(h->cfg.ncomp, h->lv[L].n, x, h->st));
+    double bb = 0.0;
+    TRY(do_dot<double>(h, b, b, cnt, &bb));
+    const double bn = std::sqrt(bb);
+    if (!(bn >= 0.0) || !std::isfinite(bn)) return fail(AGCA_E_NUMERIC, "non-finite right-hand side");
+    TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
+    double rr = 0.0;
+    TRY(do_dot<double>(h, r, r, cnt, &rr));
+    double rel = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+    int hist_n = 0;
+    auto record = [&](double v) {
+        if (o->record_history && hist_n < AGCA_MAX_HISTORY) stats->history[hist_n++] = v;
+    };
+    record(rel);
+    int it = 0;
+    int32_t status = AGCA_OK;
+    if (bn == 0.0) {
+        HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * cnt, h->st));
+        rel = 0.0;
+    } else if (rel > o->tol) {
+        if (o->solver == AGCA_SOLVER_PCG || o->solver == AGCA_SOLVER_FCG) {
+            TRY(precondition(h, r, z));
+            double rz = 0.0;
+            TRY(do_dot<double>(h, r, z, cnt, &rz));
+            HIPCHK(h, hipMemcpyAsync(p, z, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
+            int replacements = 0;
+            while (it < o->max_iter) {
+                if (!(rz > 0.0) || !std::isfinite(rz)) {
+                    status = fail(AGCA_E_NUMERIC, "preconditioned residual is not positive");
+                    break;
+                }
+                TRY(do_cube<double>(h, L, MODE_APPLY, p, nullptr, q, 0.0));
+                double pq = 0.0;
+                TRY(do_dot<double>(h, p, q, cnt, &pq));
+                if (!(pq > 0.0) || !std::isfinite(pq)) {
+                    status = fail(AGCA_E_NUMERIC, "search direction has non-positive energy");
+                    break;
+                }
+                const double alpha = rz / pq;
+                HIPCHK(h, launch_axpby<double>(cnt, alpha, p, 1.0, x, h->st));
+                if (o->solver == AGCA_SOLVER_FCG)
+                    HIPCHK(h, hipMemcpyAsync(ro, r, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
+                HIPCHK(h, launch_axpby<double>(cnt, -alpha, q, 1.0, r, h->st));
+                ++it;
+                TRY(do_dot<double>(h, r, r, cnt, &rr));
+                rel = std::sqrt(rr) / bn;
+                record(rel);
+                if (!std::isfinite(rel) || rel > 1e30) {
+                    status = fail(AGCA_E_NUMERIC, "residual diverged");
+                    break;
+                }
+                bool restart = false;
+                if (rel <= o->tol) {
+                    // the recurrence says converged: confirm with the true residual and, if
+                    // rounding has opened a gap, restart from it (residual replacement)
+                    TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
+                    TRY(do_dot<double>(h, r, r, cnt, &rr));
+                    rel = std::sqrt(rr) / bn;
+                    if (rel <= o->tol || ++replacements > 4) break;
+                    restart = true;
+                }
+                TRY(precondition(h, r, z));
+                if (restart) {
+                    TRY(do_dot<double>(h, r, z, cnt, &rz));
+                    HIPCHK(h, hipMemcpyAsync(p, z, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
+                    continue;
+                }
+                double rz_new = 0.0;
+                TRY(do_dot<double>(h, r, z, cnt, &rz_new));
+                double beta;
+                if (o->solver == AGCA_SOLVER_FCG) {
+                    double zro = 0.0;
+                    TRY(do_dot<double>(h, z, ro, cnt, &zro));
+                    beta = (rz_new - zro) / rz;
+                } else {
+                    beta = rz_new / rz;
+                }
+                rz = rz_new;
+                HIPCHK(h, launch_axpby<double>(cnt, 1.0, z, beta, p, h->st));
+            }
+        } else {
+            // iterative refinement / stationary: x += B r, r = b - A x
+            while (it < o->max_iter) {
+                TRY(precondition(h, r, z));
+                HIPCHK(h, launch_axpby<double>(cnt, 1.0, z, 1.0, x, h->st));
+                TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
+                ++it;
+                TRY(do_dot<double>(h, r, r, cnt, &rr));
+                rel = std::sqrt(rr) / bn;
+                record(rel);
+                if (!std::isfinite(rel) || rel > 1e30) {
+                    status = fail(AGCA_E_NUMERIC, "residual diverged");
+                    break;
+                }
+                if (rel <= o->tol) break;
+            }
+        }
+    }
+    // final FP64 residual with FP64 coefficients
+    TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
+    TRY(do_dot<double>(h, r, r, cnt, &rr));
+    stats->rel_residual = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+    stats->iterations = it;
+    stats->converged = stats->rel_residual <= o->tol * (1.0 + 1e-12) || bn == 0.0;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (status != AGCA_OK) return status;
+    if (!stats->converged) return fail(AGCA_E_NOCONV, "no convergence within max_iter");
+    return AGCA_OK;
+}
+
+}  // extern "C"

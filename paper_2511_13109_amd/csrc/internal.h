@@ -1,0 +1,95 @@
+// Internal declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "agca.h"
+
+namespace agca {
+
+// Operator data of one level as seen by the element-loop kernels, in one precision.
+template <typename T>
+struct LevelOp {
+    int n = 0;                 // cells per axis
+    const void* nu = nullptr;  // 6 n^3 coefficients (T, or uint16 bf16 bits on the finest level)
+    int nu_kind = 0;           // AGCA_F64 / AGCA_F32 / AGCA_BF16 storage of nu
+    const int32_t* blk = nullptr;  // per element: index of its stored block or -1 (coarse levels)
+    const T* blocks = nullptr;     // flagged x (4 ncomp)^2 entries
+    const T* dinv = nullptr;       // inverse Jacobi diagonal, level vector (0 on the boundary)
+};
+
+enum CubeMode { MODE_APPLY = 0, MODE_RESIDUAL = 1, MODE_JACOBI = 2 };
+
+// v = A u / r = b - A u / x_out = x + omega D^-1 (b - A x)   (one element-loop pass)
+template <typename T>
+hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,
+                       T omega, hipStream_t st);
+
+// transfers (Section 2.1)
+template <typename T>
+hipError_t launch_restrict(int ncomp, int n_fine, const T* rf, T* rc, hipStream_t st);
+template <typename T>
+hipError_t launch_prolong_add(int ncomp, int n_fine, const T* ec, T* xf, hipStream_t st);
+
+// level-0 solve: x = A0^-1 b on the single free node (ncomp x ncomp inverse in FP64)
+template <typename T>
+hipError_t launch_coarse_solve(int ncomp, const double* ainv, const T* b, T* x, hipStream_t st);
+
+// vector kernels
+template <typename T>
+hipError_t launch_dot_partial(const T* x, const T* y, int64_t n, double* partial, int nblocks,
+                              hipStream_t st);
+hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStream_t st);  // y = a x + b y
+hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_zero_boundary(int ncomp, int n, T* x, hipStream_t st);
+hipError_t launch_count_invalid(const double* v, int64_t n, int* counter, hipStream_t st);
+
+// setup kernels (Sections 2.2-2.3)
+hipError_t launch_minmax_from_fine(int n_coarse, const double* nu_fine, double* mn, double* mx,
+                                   hipStream_t st);
+hipError_t launch_minmax_up(int n_coarse, const double* mn_f, const double* mx_f, double* mn,
+                            double* mx, hipStream_t st);
+hipError_t launch_flag(int64_t ne, const double* mn, const double* mx, double tau, int mode,
+                       int32_t* flag, hipStream_t st);
+// exclusive scan of flags -> blk index (or -1) and total count (device int64)
+hipError_t launch_compact(int64_t ne, const int32_t* flag, int32_t* blk, int32_t* ids,
+                          int64_t* count_dev, void* scratch, size_t scratch_bytes,
+                          hipStream_t st);
+hipError_t compact_scratch_bytes(int64_t ne, size_t* bytes);
+
+// Galerkin blocks (eq. (2.7)), FP64.
+// fused: for every element of level l = L-2 (n cells), from the finest coefficient on
+// level L (4n cells): forms the blocks of its children (level L-1) and its own;
+// stores flagged ones and optionally writes all of level l to trans_out.
+hipError_t launch_gca_fused2(int ncomp, int n, const double* nu_fine, double h_fine,
+                             const int32_t* blk_child, double* blocks_child,
+                             const int32_t* blk_self, double* blocks_self, double* trans_out,
+                             hipStream_t st);
+// flagged elements of level L-1 only (n cells), from the finest level
+hipError_t launch_gca_from_fine(int ncomp, int n, int64_t nflag, const int32_t* ids,
+                                const double* nu_fine, double h_fine, double* blocks,
+                                hipStream_t st);
+// level l (n cells) from the transient blocks of level l+1
+hipError_t launch_gca_up(int ncomp, int n, const double* trans_in, const int32_t* blk_self,
+                         double* blocks_self, double* trans_out, hipStream_t st);
+
+// diagonal of a level operator (FP64): D = sum of element diagonals (DCA or stored block)
+hipError_t launch_diagonal(int ncomp, int n, const double* nu, double scale, const int32_t* blk,
+                           const double* blocks, double* diag, hipStream_t st);
+template <typename T>
+hipError_t launch_invert_diag(int64_t count, const double* diag, T* dinv, hipStream_t st);
+
+// adjoint gradient and load vector (finest level)
+hipError_t launch_grad(int ncomp, int n, const double* nu, double scale, const double* u,
+                       const double* w, double* g, hipStream_t st);
+hipError_t launch_load_vector(int ncomp, int n, const double* f, double vol4, double* b,
+                              hipStream_t st);
+
+}  // namespace agca

@@ -1,0 +1,345 @@
+// Grid transfers, level-0 solve, reductions, precision conversions, the adjoint
+// gradient and the load vector.
+#include <hip/hip_runtime.h>
+
+#include "cube_math.h"
+#include "internal.h"
+
+namespace agca {
+namespace {
+
+constexpr int NT = 256;
+
+// ---------------------------------------------------------------------------
+// Transfers (paper Section 2.1).  Linear interpolation between nested P1 spaces
+// on the Kuhn lattice: a fine node X = 2Y is a coarse node and copies its value;
+// every other fine node is the midpoint of the coarse edge (Y, Y + d) with
+// d = X mod 2 in {0,1}^3 (all such offsets are edges of the lattice), so
+//   (P e)(X) = (e((X - d)/2) + e((X + d)/2)) / 2.
+// Restriction is the transpose: a coarse node Y collects r(2Y) plus half of
+// r(2Y + d) and r(2Y - d) for the 7 offsets d.  Boundary nodes stay zero.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_restrict(int ncomp, int nc, const T* __restrict__ rf, T* __restrict__ rc) {
+    const int64_t nc1 = nc + 1, Nc = nc1 * nc1 * nc1;
+    const int64_t nf1 = 2 * nc + 1, Nf = nf1 * nf1 * nf1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= Nc) return;
+    const int x = (int)(p % nc1), y = (int)((p / nc1) % nc1), z = (int)(p / (nc1 * nc1));
+    const bool interior = x > 0 && y > 0 && z > 0 && x < nc && y < nc && z < nc;
+    const int64_t q = 2 * x + nf1 * (2 * y + nf1 * (int64_t)(2 * z));
+    for (int c = 0; c < ncomp; ++c) {
+        T acc = T(0);
+        if (interior) {
+            const T* f = rf + c * Nf;
+            T half = T(0);
+#pragma unroll
+            for (int d = 1; d < 8; ++d) {
+                const int64_t off = (d & 1) + nf1 * (((d >> 1) & 1) + nf1 * ((d >> 2) & 1));
+                half += f[q + off] + f[q - off];
+            }
+            acc = f[q] + T(0.5) * half;
+        }
+        rc[c * Nc + p] = acc;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_prolong_add(int ncomp, int nf, const T* __restrict__ ec, T* __restrict__ xf) {
+    const int nc = nf / 2;
+    const int64_t nc1 = nc + 1, Nc = nc1 * nc1 * nc1;
+    const int64_t nf1 = nf + 1, Nf = nf1 * nf1 * nf1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= Nf) return;
+    const int x = (int)(p % nf1), y = (int)((p / nf1) % nf1), z = (int)(p / (nf1 * nf1));
+    if (x == 0 || y == 0 || z == 0 || x == nf || y == nf || z == nf) return;
+    const int dx = x & 1, dy = y & 1, dz = z & 1;
+    const int64_t lo = ((x - dx) >> 1) + nc1 * (((y - dy) >> 1) + nc1 * (int64_t)((z - dz) >> 1));
+    const int64_t hi = ((x + dx) >> 1) + nc1 * (((y + dy) >> 1) + nc1 * (int64_t)((z + dz) >> 1));
+    const bool even = (dx | dy | dz) == 0;
+    for (int c = 0; c < ncomp; ++c) {
+        const T* e = ec + c * Nc;
+        const T v = even ? e[lo] : T(0.5) * (e[lo] + e[hi]);
+        xf[c * Nf + p] += v;
+    }
+}
+
+// level 0 has n = 2: a single free node (1,1,1), id 13 of 27
+template <typename T>
+__global__ void k_coarse_solve(int ncomp, const double* __restrict__ ainv, const T* __restrict__ b,
+                               T* __restrict__ x) {
+    const int t = threadIdx.x;
+    if (t >= 27 * ncomp) return;
+    const int c = t / 27, p = t % 27;
+    double v = 0.0;
+    if (p == 13)
+        for (int d = 0; d < ncomp; ++d) v += ainv[c * ncomp + d] * (double)b[d * 27 + 13];
+    x[t] = T(v);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: fixed-order two-pass sum (wavefront shuffle, then LDS across the
+// workgroup's 4 wavefronts, then one workgroup over the partials) so results
+// are bitwise reproducible.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_dot_partial(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
+              double* __restrict__ partial) {
+    __shared__ double red[NT / 64];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride)
+        acc += (double)x[i] * (double)y[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        partial[blockIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(NT)
+k_sum_partials(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+    __shared__ double red[NT / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += NT) acc += partial[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        *out = s;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_axpby(int64_t n, double a, const T* __restrict__ x, double b, T* __restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    const T ta = T(a), tb = T(b);
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride)
+        y[i] = ta * x[i] + tb * y[i];
+}
+
+// FP64 -> BF16 with a single round-to-nearest-even: round to FP32 with
+// "round to odd" (truncate, then set the last bit if inexact), which keeps the
+// information a second rounding needs, then round that FP32 value to BF16.
+__device__ __forceinline__ uint16_t f64_to_bf16(double x) {
+    float f = __double2float_rz(x);
+    uint32_t bits = __float_as_uint(f);
+    if ((double)f != x) bits |= 1u;
+    const uint32_t lsb = (bits >> 16) & 1u;
+    bits += 0x7fffu + lsb;
+    return (uint16_t)(bits >> 16);
+}
+
+__global__ void __launch_bounds__(NT)
+k_cast(int from, int to, const void* __restrict__ src, void* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
+        if (from == AGCA_F64 && to == AGCA_F32)
+            static_cast<float*>(dst)[i] = (float)static_cast<const double*>(src)[i];
+        else if (from == AGCA_F32 && to == AGCA_F64)
+            static_cast<double*>(dst)[i] = (double)static_cast<const float*>(src)[i];
+        else if (from == AGCA_F64 && to == AGCA_BF16)
+            static_cast<uint16_t*>(dst)[i] = f64_to_bf16(static_cast<const double*>(src)[i]);
+        else if (from == AGCA_F64 && to == AGCA_F64)
+            static_cast<double*>(dst)[i] = static_cast<const double*>(src)[i];
+        else if (from == AGCA_F32 && to == AGCA_F32)
+            static_cast<float*>(dst)[i] = static_cast<const float*>(src)[i];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_zero_boundary(int ncomp, int n, T* __restrict__ x) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= N) return;
+    const int xx = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    if (xx == 0 || y == 0 || z == 0 || xx == n || y == n || z == n)
+        for (int c = 0; c < ncomp; ++c) x[c * N + p] = T(0);
+}
+
+__global__ void __launch_bounds__(NT)
+k_count_invalid(const double* __restrict__ v, int64_t n, int* __restrict__ counter) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
+        const double a = v[i];
+        if (!(a > 0.0) || !isfinite(a)) ++bad;
+    }
+    if (bad) atomicAdd(counter, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint gradient g_e = -w_e^T A_e u_e = -(nu_e h/6) * energy(u_e, w_e), one
+// thread per cell (6 simplices, 6 consecutive outputs).
+// ---------------------------------------------------------------------------
+template <int NC>
+__global__ void __launch_bounds__(NT)
+k_grad(int n, const double* __restrict__ nu, double scale, const double* __restrict__ u,
+       const double* __restrict__ w, double* __restrict__ g) {
+    const int64_t cells = (int64_t)n * n * n;
+    const int64_t cell = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (cell >= cells) return;
+    const int cx = (int)(cell % n), cy = (int)((cell / n) % n), cz = (int)(cell / ((int64_t)n * n));
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    double U[8][NC], W[8][NC];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int x = cx + (k & 1), y = cy + ((k >> 1) & 1), z = cz + ((k >> 2) & 1);
+        const bool bd = x == 0 || y == 0 || z == 0 || x == n || y == n || z == n;
+        const int64_t p = x + n1 * (y + n1 * (int64_t)z);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            U[k][c] = bd ? 0.0 : u[c * N + p];
+            W[k][c] = bd ? 0.0 : w[c * N + p];
+        }
+    }
+    double e[6];
+    cell_energy<NC, double>(U, W, e);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) g[6 * cell + s] = -nu[6 * cell + s] * scale * e[s];
+}
+
+// b_i = sum over the simplices containing node i of f_e |e| / 4 (per component)
+template <int NC>
+__global__ void __launch_bounds__(NT)
+k_load_vector(int n, const double* __restrict__ f, double vol4, double* __restrict__ b) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1, E = 6LL * n * n * n;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= N) return;
+    const int x = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    const bool bd = x == 0 || y == 0 || z == 0 || x == n || y == n || z == n;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    if (!bd) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int cx = x - (k & 1), cy = y - ((k >> 1) & 1), cz = z - ((k >> 2) & 1);
+            const int64_t cell = cx + (int64_t)n * (cy + (int64_t)n * cz);
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const bool on = k == 0 || k == 7 || k == path_corner(s, 1) || k == path_corner(s, 2);
+                if (on)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[c] += f[c * E + 6 * cell + s];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) b[c * N + p] = acc[c] * vol4;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+inline unsigned grid_stride(int64_t n) {
+    int64_t g = (n + NT - 1) / NT;
+    return (unsigned)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_restrict(int ncomp, int n_fine, const T* rf, T* rc, hipStream_t st) {
+    if (!rf || !rc || n_fine < 4) return hipErrorInvalidValue;
+    const int nc = n_fine / 2;
+    const int64_t Nc = (int64_t)(nc + 1) * (nc + 1) * (nc + 1);
+    hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(Nc)), dim3(NT), 0, st, ncomp, nc, rf, rc);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_prolong_add(int ncomp, int n_fine, const T* ec, T* xf, hipStream_t st) {
+    if (!ec || !xf || n_fine < 4) return hipErrorInvalidValue;
+    const int64_t Nf = (int64_t)(n_fine + 1) * (n_fine + 1) * (n_fine + 1);
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(Nf)), dim3(NT), 0, st, ncomp, n_fine, ec, xf);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_coarse_solve(int ncomp, const double* ainv, const T* b, T* x, hipStream_t st) {
+    if (!ainv || !b || !x) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(128), 0, st, ncomp, ainv, b, x);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_dot_partial(const T* x, const T* y, int64_t n, double* partial, int nblocks,
+                              hipStream_t st) {
+    if (!x || !y || !partial) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(nblocks), dim3(NT), 0, st, x, y, n, partial);
+    return hipGetLastError();
+}
+hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(NT), 0, st, partial, nblocks, out);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!x || !y) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_axpby<T>, dim3(grid_stride(n)), dim3(NT), 0, st, n, a, x, b, y);
+    return hipGetLastError();
+}
+hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!src || !dst) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cast, dim3(grid_stride(n)), dim3(NT), 0, st, from, to, src, dst, n);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_zero_boundary(int ncomp, int n, T* x, hipStream_t st) {
+    if (!x) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_zero_boundary<T>, dim3(grid_for(N)), dim3(NT), 0, st, ncomp, n, x);
+    return hipGetLastError();
+}
+hipError_t launch_count_invalid(const double* v, int64_t n, int* counter, hipStream_t st) {
+    if (!v || !counter) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_count_invalid, dim3(grid_stride(n)), dim3(NT), 0, st, v, n, counter);
+    return hipGetLastError();
+}
+hipError_t launch_grad(int ncomp, int n, const double* nu, double scale, const double* u,
+                       const double* w, double* g, hipStream_t st) {
+    if (!nu || !u || !w || !g) return hipErrorInvalidValue;
+    const int64_t cells = (int64_t)n * n * n;
+    if (ncomp == 1)
+        hipLaunchKernelGGL(k_grad<1>, dim3(grid_for(cells)), dim3(NT), 0, st, n, nu, scale, u, w, g);
+    else
+        hipLaunchKernelGGL(k_grad<3>, dim3(grid_for(cells)), dim3(NT), 0, st, n, nu, scale, u, w, g);
+    return hipGetLastError();
+}
+hipError_t launch_load_vector(int ncomp, int n, const double* f, double vol4, double* b,
+                              hipStream_t st) {
+    if (!f || !b) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    if (ncomp == 1)
+        hipLaunchKernelGGL(k_load_vector<1>, dim3(grid_for(N)), dim3(NT), 0, st, n, f, vol4, b);
+    else
+        hipLaunchKernelGGL(k_load_vector<3>, dim3(grid_for(N)), dim3(NT), 0, st, n, f, vol4, b);
+    return hipGetLastError();
+}
+
+#define AGCA_INST(T)                                                                           \
+    template hipError_t launch_restrict<T>(int, int, const T*, T*, hipStream_t);               \
+    template hipError_t launch_prolong_add<T>(int, int, const T*, T*, hipStream_t);            \
+    template hipError_t launch_coarse_solve<T>(int, const double*, const T*, T*, hipStream_t); \
+    template hipError_t launch_dot_partial<T>(const T*, const T*, int64_t, double*, int,       \
+                                              hipStream_t);                                    \
+    template hipError_t launch_axpby<T>(int64_t, double, const T*, double, T*, hipStream_t);   \
+    template hipError_t launch_zero_boundary<T>(int, int, T*, hipStream_t);
+AGCA_INST(double)
+AGCA_INST(float)
+#undef AGCA_INST
+
+}  // namespace agca

@@ -199,10 +199,19 @@ def test_mixed_precision_fcg_reaches_fp64_residual():
         lv = H.levels[H.L]
         f = field_for("sinkers", H.L).force(mesh.centroids_canonical(lv), 3)
         b = _dev(fem.load_vector(lv, f, 3))
+        m = interior_full(H, H.L)
+        bn = b.cpu().numpy()[m]
+        ref_fcg = mg.fcg(H.A[H.L], bn, lambda r: mg.vcycle(H, r), 1e-8).iterations
         for GG in (G, G2):
-            for solver in ("fcg", "ir"):
-                x, st = GG.solve(b, solver=solver, tol=1e-8, max_iter=300)
-                assert st["converged"] and st["rel_residual"] <= 1e-8, (solver, st["rel_residual"])
+            # the stationary iteration (x += B r) needs ~430 FP64 V-cycles here
+            for solver, cap in (("fcg", 300), ("ir", 1500)):
+                x, st = GG.solve(b, solver=solver, tol=1e-8, max_iter=cap, raise_on_noconv=False)
+                print(solver, GG.cfg.mg_nu_dtype, st["iterations"], st["rel_residual"], flush=True)
+                assert st["converged"] and st["rel_residual"] <= 1e-8, (solver, st["iterations"],
+                                                                        st["rel_residual"])
+                if solver == "fcg":
+                    # an FP32 V-cycle costs at most a few extra outer iterations
+                    assert st["iterations"] <= ref_fcg + 5, (st["iterations"], ref_fcg)
         # FP32 level apply against the oracle at FP32 accuracy
         rng = np.random.default_rng(7)
         u = rand_full(H, H.L, rng)
@@ -251,6 +260,8 @@ def test_cast_round_to_nearest_even():
         m, e = np.frexp(x)
         ref = np.ldexp(np.round(m * 256.0), e - 8)
         assert np.array_equal(back, ref)
-        assert back[-4] == 1.0 and back[-3] == 1.0 + 2 ** -6 and back[-1] == 1.0 + 2 ** -7
+        # ties go to the even neighbour; anything above a tie rounds up
+        assert back[-4] == 1.0 and back[-3] == 1.0 and back[-2] == 1.0 + 2 ** -6
+        assert back[-1] == 1.0 + 2 ** -7
     finally:
         G.close()

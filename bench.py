@@ -83,6 +83,28 @@ def cpu_baseline(name: str, L_sample: int = 4, seconds: float = 12.0) -> dict:
                       f"assembly ({t_asm:.1f} s) excluded"}
 
 
+def profile_apply(name: str, dev) -> None:
+    """Driver for hardware-counter passes: 5 FP64 fine applies, then a 256 MiB copy
+    (three times) whose known size calibrates the byte counters."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy
+    w, nu, _, _ = make_inputs(name)
+    nus = [torch.from_numpy(v).to(dev) for v in nu]
+    H = Hierarchy(w.L, w.ncomp, nus[w.L], nus[:w.L], mg_dtype="f64")
+    n = 2 ** (w.L + 1)
+    u = torch.randn(w.ncomp * (n + 1) ** 3, dtype=torch.float64, device=dev)
+    v = torch.empty_like(u)
+    for _ in range(5):
+        H.apply(w.L, u, v)
+    a = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.float64, device=dev).normal_()
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    H.close()
+    print("profile-apply done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +114,8 @@ def main():
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mg-nu", default="bf16", choices=["bf16", "f32"])
+    ap.add_argument("--profile-apply", action="store_true",
+                    help="only run 5 FP64 fine applies and a 256 MiB copy (counter passes)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -104,6 +128,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_apply:
+        profile_apply(args.workload, dev)
+        return
     w, nu, f, t_gen = make_inputs(args.workload)
     L, nc = w.L, w.ncomp
     nus = [torch.from_numpy(v).to(dev) for v in nu]
@@ -143,6 +170,10 @@ def main():
             rec["it32"].append(s32["iterations"])
             rec["res64"].append(s64["rel_residual"])
             rec["res32"].append(s32["rel_residual"])
+            rec.setdefault("stat64", []).append({k: s64[k] for k in ("converged", "floor_limited",
+                                                 "replacements", "recursive_rel_residual")})
+            rec.setdefault("stat32", []).append({k: s32[k] for k in ("converged", "floor_limited",
+                                                 "replacements", "recursive_rel_residual")})
             print(f"[step] setup {t_setup*1e3:.1f} ms, apply {rec['apply_ms'][-1]*1e3:.1f} us, "
                   f"FP64-MG PCG {s64['iterations']} it {s64['seconds']*1e3:.1f} ms "
                   f"(res {s64['rel_residual']:.2e}), FP32-MG FCG {s32['iterations']} it "
@@ -176,6 +207,7 @@ def main():
                                                                  np.median(rec["t32"])), 3)},
         "iterations": {"fp64_mg_pcg": int(np.median(rec["it64"])), "fp32_mg_fcg": int(np.median(rec["it32"]))},
         "final_rel_residual_fp64": {"fp64_mg": max(rec["res64"]), "fp32_mg": max(rec["res32"])},
+        "solve_status": {"fp64_mg": rec["stat64"][-1], "fp32_mg": rec["stat32"][-1]},
         "setup_s": round(float(np.median(rec["setup_s"])), 5),
         "flagged_per_level": [H64.query(l)["flagged"] for l in range(L)],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

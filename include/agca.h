@@ -179,15 +179,24 @@ typedef struct {
 #define AGCA_MAX_HISTORY 1024
 typedef struct {
     int32_t iterations;
-    int32_t converged;
+    int32_t converged;       /* the true FP64 residual of x is <= tol                       */
+    int32_t floor_limited;   /* the recurrence reached tol but the true residual stagnated
+                                above it after residual replacement: FP64 cannot represent
+                                an x with a smaller residual (rounding floor)               */
+    int32_t replacements;    /* restarts from the true residual                             */
     double rel_residual;     /* final ||b - A x|| / ||b|| in FP64 with FP64 coefficients    */
+    double recursive_rel_residual; /* the Krylov recurrence's last residual estimate        */
     double seconds;          /* wall time of the solve (after setup)                        */
-    double history[AGCA_MAX_HISTORY];
+    double history[AGCA_MAX_HISTORY]; /* recurrence residuals, one per iteration           */
 } agca_solve_stats;
 
 /* Solve A_L x = b with the AGCA V-cycle as preconditioner inside an FP64 outer
  * loop (PCG for an FP64 V-cycle; FCG(1) or iterative refinement around an FP32
- * V-cycle; stationary V-cycle iteration).  b, x: device FP64 level vectors. */
+ * V-cycle; stationary V-cycle iteration).  b, x: device FP64 level vectors.
+ * Stopping: when the recurrence's residual reaches tol the true residual
+ * b - A x is recomputed; if it is above tol the iteration restarts from it
+ * (at most 3 times, while it keeps halving).  Returns AGCA_OK when converged or
+ * floor_limited, AGCA_E_NOCONV when max_iter is reached first. */
 int32_t agca_solve(agca_hier* h, const agca_solve_opts* opts, const double* b, double* x,
                    agca_solve_stats* stats);
 

@@ -6,7 +6,7 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libagca.so")
+LIB_PATH = os.environ.get("AGCA_LIBRARY") or os.path.join(_PKG, "libagca.so")
 
 AGCA_OK, AGCA_E_INVALID, AGCA_E_OOM, AGCA_E_HIP, AGCA_E_NOCONV, AGCA_E_NUMERIC, AGCA_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
@@ -38,8 +38,10 @@ class SolveOpts(C.Structure):
 
 
 class SolveStats(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double),
-                ("seconds", C.c_double), ("history", C.c_double * MAX_HISTORY)]
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("floor_limited", C.c_int32),
+                ("replacements", C.c_int32), ("rel_residual", C.c_double),
+                ("recursive_rel_residual", C.c_double), ("seconds", C.c_double),
+                ("history", C.c_double * MAX_HISTORY)]
 
 
 # name -> (restype, argtypes); every symbol include/agca.h declares

@@ -217,7 +217,9 @@ class Hierarchy:
         st = _lib.SolveStats()
         rc = self._lib.agca_solve(self._h, C.byref(opts), _ptr(b), _ptr(x), C.byref(st))
         stats = {"iterations": st.iterations, "converged": bool(st.converged),
-                 "rel_residual": st.rel_residual, "seconds": st.seconds,
+                 "floor_limited": bool(st.floor_limited), "replacements": st.replacements,
+                 "rel_residual": st.rel_residual,
+                 "recursive_rel_residual": st.recursive_rel_residual, "seconds": st.seconds,
                  "history": list(st.history[:min(st.iterations + 1, _lib.MAX_HISTORY)])
                  if record_history else [], "status": rc}
         if rc != _lib.AGCA_OK and (rc != _lib.AGCA_E_NOCONV or raise_on_noconv):

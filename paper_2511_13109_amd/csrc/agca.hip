@@ -2,6 +2,7 @@
 // operations, V-cycle and FP64 outer solvers (declared in include/agca.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -26,15 +27,19 @@ int32_t fail(int32_t code, const std::string& msg) {
 struct Level {
     int n = 0;
     int64_t nodes = 0, elems = 0;
+    // per-element coefficient arrays use the internal layout of kuhn.h (elem_slot)
     double* nu64 = nullptr;      // finest: nu_L; coarse: DCA coefficient of this level
     float* nu32 = nullptr;       // FP32 copy (FP32 V-cycle)
     uint16_t* nubf = nullptr;    // BF16 copy of the finest coefficient (FP32 V-cycle option)
-    int32_t* flag = nullptr;
-    int32_t* blk = nullptr;
+    int32_t* flag = nullptr;     // by element id
+    int32_t* blk = nullptr;      // by element id: stored block index or -1
+    int32_t* blk_soa = nullptr;  // the same in the internal layout (element loop)
     int32_t* ids = nullptr;
     int64_t nflag = 0;
     double* blocks64 = nullptr;
     float* blocks32 = nullptr;
+    double* yblk64 = nullptr;    // per-flagged-element block products (scratch)
+    float* yblk32 = nullptr;
     double* diag = nullptr;
     double* dinv64 = nullptr;
     float* dinv32 = nullptr;
@@ -131,8 +136,11 @@ LevelOp<double> level_op<double>(const agca_hier* h, int l) {
     op.n = L.n;
     op.nu = L.nu64;
     op.nu_kind = AGCA_F64;
-    op.blk = (l < h->cfg.L && L.nflag > 0) ? L.blk : nullptr;
+    op.blk = (l < h->cfg.L && L.nflag > 0) ? L.blk_soa : nullptr;
+    op.ids = L.ids;
+    op.nflag = L.nflag;
     op.blocks = L.blocks64;
+    op.yblk = L.yblk64;
     op.dinv = L.dinv64;
     return op;
 }
@@ -148,8 +156,11 @@ LevelOp<float> level_op<float>(const agca_hier* h, int l) {
         op.nu = L.nu32;
         op.nu_kind = AGCA_F32;
     }
-    op.blk = (l < h->cfg.L && L.nflag > 0) ? L.blk : nullptr;
+    op.blk = (l < h->cfg.L && L.nflag > 0) ? L.blk_soa : nullptr;
+    op.ids = L.ids;
+    op.nflag = L.nflag;
     op.blocks = L.blocks32;
+    op.yblk = L.yblk32;
     op.dinv = L.dinv32;
     return op;
 }
@@ -194,28 +205,58 @@ int32_t do_smooth(agca_hier* h, int l, int sweeps, double omega, const T* b, T* 
     return AGCA_OK;
 }
 
+// One V(pre,post)-cycle from a zero initial guess.  The first pre-smoothing sweep
+// from zero is the elementwise x = omega D^-1 b; the remaining sweeps ping-pong
+// between the level's two buffers, and on the finest level the starting buffer
+// is chosen so that the last sweep lands in the caller's x (no copies).
 template <typename T>
 int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
     const int L = h->cfg.L, nc = h->cfg.ncomp;
-    const double om = h->cfg.omega;
+    const T om = T(h->cfg.omega);
+    const int pre = h->cfg.pre_sweeps, post = h->cfg.post_sweeps;
+    std::vector<T*> xcur(L + 1, nullptr), xalt(L + 1, nullptr);
     for (int l = L; l >= 1; --l) {
+        const int64_t cnt = (int64_t)nc * h->lv[l].nodes;
         const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
-        T* xl = (l == L) ? xL : static_cast<T*>(h->lv[l].x);
-        HIPCHK(h, hipMemsetAsync(xl, 0, sizeof(T) * nc * h->lv[l].nodes, h->st));
-        TRY(do_smooth<T>(h, l, h->cfg.pre_sweeps, om, bl, xl));
+        T* home = (l == L) ? xL : static_cast<T*>(h->lv[l].x);
+        T* other = static_cast<T*>(h->lv[l].t);
+        // Jacobi launches that will write this level's iterate after the first sweep
+        const int launches = (pre > 0 ? pre - 1 : 0) + post;
+        T* cur = (launches % 2 == 0) ? home : other;
+        T* alt = (cur == home) ? other : home;
+        const LevelOp<T> op = level_op<T>(h, l);
+        if (pre > 0) {
+            HIPCHK(h, launch_first_sweep<T>(cnt, om, op.dinv, bl, cur, h->st));
+            for (int i = 1; i < pre; ++i) {
+                TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, om));
+                std::swap(cur, alt);
+            }
+        } else {
+            HIPCHK(h, launch_fill<T>(cnt, T(0), cur, h->st));
+        }
+        xcur[l] = cur;
+        xalt[l] = alt;
         T* rl = static_cast<T*>(h->lv[l].r);
-        TRY(do_cube<T>(h, l, MODE_RESIDUAL, xl, bl, rl, T(0)));
+        TRY(do_cube<T>(h, l, MODE_RESIDUAL, cur, bl, rl, T(0)));
         HIPCHK(h, launch_restrict<T>(nc, h->lv[l].n, rl, static_cast<T*>(h->lv[l - 1].b), h->st));
     }
     HIPCHK(h, launch_coarse_solve<T>(nc, h->ainv0, static_cast<const T*>(h->lv[0].b),
                                      static_cast<T*>(h->lv[0].x), h->st));
+    xcur[0] = static_cast<T*>(h->lv[0].x);
     for (int l = 1; l <= L; ++l) {
         const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
-        T* xl = (l == L) ? xL : static_cast<T*>(h->lv[l].x);
-        HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, static_cast<const T*>(h->lv[l - 1].x), xl,
-                                        h->st));
-        TRY(do_smooth<T>(h, l, h->cfg.post_sweeps, om, bl, xl));
+        T* cur = xcur[l];
+        T* alt = xalt[l];
+        HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, xcur[l - 1], cur, h->st));
+        for (int i = 0; i < post; ++i) {
+            TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, om));
+            std::swap(cur, alt);
+        }
+        xcur[l] = cur;
     }
+    if (xcur[L] != xL)  // only when pre = post = 0 parity cannot place it
+        HIPCHK(h, hipMemcpyAsync(xL, xcur[L], sizeof(T) * nc * h->lv[L].nodes,
+                                 hipMemcpyDeviceToDevice, h->st));
     return AGCA_OK;
 }
 
@@ -297,7 +338,7 @@ int32_t build_coarsest(agca_hier* h) {
                     if (blk[e] >= 0)
                         v = blocks[(size_t)blk[e] * M * M + (4 * c + a) * M + 4 * d + a];
                     else
-                        v = nu[e] * scale * elem_entry(nc, s, c, a, d, a);
+                        v = nu[elem_slot(s, cell, 8)] * scale * elem_entry(nc, s, c, a, d, a);
                     A[c][d] += v;
                 }
         }
@@ -332,8 +373,7 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
     for (int l = 0; l <= L; ++l) {
         const double* src = (l == L) ? nu_fine : nu_coarse[l];
         if (!src) return fail(AGCA_E_INVALID, "null coefficient pointer for level " + std::to_string(l));
-        HIPCHK(h, hipMemcpyAsync(h->lv[l].nu64, src, sizeof(double) * h->lv[l].elems,
-                                 hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(h, launch_to_internal(h->lv[l].elems / 6, src, h->lv[l].nu64, h->st));
     }
     for (int l = 0; l <= L; ++l) {
         int bad = 0;
@@ -386,8 +426,8 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
                 e = launch_flag(h->lv[l].elems, mn[cur], mx[cur], h->cfg.flag_ratio, h->cfg.flag_mode,
                                 h->lv[l].flag, h->st);
             if (e == hipSuccess)
-                e = launch_compact(h->lv[l].elems, h->lv[l].flag, h->lv[l].blk, h->lv[l].ids,
-                                   cnt_dev + l, scratch, sbytes, h->st);
+                e = launch_compact(h->lv[l].elems, h->lv[l].flag, h->lv[l].blk, h->lv[l].blk_soa,
+                                   h->lv[l].ids, cnt_dev + l, scratch, sbytes, h->st);
             if (e != hipSuccess) {
                 release();
                 h->error = true;
@@ -412,7 +452,11 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
         lv.blocks32 = nullptr;
         if (lv.nflag > 0) {
             TRY(alloc_t(h, &lv.blocks64, (size_t)lv.nflag * M * M, &lv.bytes));
-            if (mg32(h)) TRY(alloc_t(h, &lv.blocks32, (size_t)lv.nflag * M * M, &lv.bytes));
+            TRY(alloc_t(h, &lv.yblk64, (size_t)lv.nflag * M, &lv.bytes));
+            if (mg32(h)) {
+                TRY(alloc_t(h, &lv.blocks32, (size_t)lv.nflag * M * M, &lv.bytes));
+                TRY(alloc_t(h, &lv.yblk32, (size_t)lv.nflag * M, &lv.bytes));
+            }
         }
     }
     // Galerkin blocks, bottom-up (eq. (2.7))
@@ -508,7 +552,7 @@ void free_all(agca_hier* h) {
 int32_t free_blocks(agca_hier* h) {
     // blocks are re-sized on every rebuild: drop the old ones from the allocation list
     for (auto& lv : h->lv) {
-        for (void* p : {(void*)lv.blocks64, (void*)lv.blocks32}) {
+        for (void* p : {(void*)lv.blocks64, (void*)lv.blocks32, (void*)lv.yblk64, (void*)lv.yblk32}) {
             if (!p) continue;
             for (size_t i = 0; i < h->allocs.size(); ++i)
                 if (h->allocs[i] == p) {
@@ -519,11 +563,15 @@ int32_t free_blocks(agca_hier* h) {
         }
         const int M = 4 * h->cfg.ncomp;
         const int64_t freed = (lv.blocks64 ? lv.nflag * M * M * (int64_t)sizeof(double) : 0) +
-                              (lv.blocks32 ? lv.nflag * M * M * (int64_t)sizeof(float) : 0);
+                              (lv.blocks32 ? lv.nflag * M * M * (int64_t)sizeof(float) : 0) +
+                              (lv.yblk64 ? lv.nflag * M * (int64_t)sizeof(double) : 0) +
+                              (lv.yblk32 ? lv.nflag * M * (int64_t)sizeof(float) : 0);
         h->bytes -= freed;
         lv.bytes -= freed;
         lv.blocks64 = nullptr;
         lv.blocks32 = nullptr;
+        lv.yblk64 = nullptr;
+        lv.yblk32 = nullptr;
         lv.nflag = 0;
     }
     return AGCA_OK;
@@ -588,6 +636,7 @@ int32_t agca_create(const agca_config* cfg, const double* nu_fine, const double*
             rc = alloc_t(h, &lv.nubf, lv.elems, &lv.bytes);
         if (rc == AGCA_OK && l < L) rc = alloc_t(h, &lv.flag, lv.elems, &lv.bytes);
         if (rc == AGCA_OK && l < L) rc = alloc_t(h, &lv.blk, lv.elems, &lv.bytes);
+        if (rc == AGCA_OK && l < L) rc = alloc_t(h, &lv.blk_soa, lv.elems, &lv.bytes);
         if (rc == AGCA_OK && l < L) rc = alloc_t(h, &lv.ids, lv.elems, &lv.bytes);
         if (rc == AGCA_OK) rc = alloc_t(h, &lv.diag, nv, &lv.bytes);
         if (rc == AGCA_OK && mg32(h)) rc = alloc_t(h, &lv.dinv32, nv, &lv.bytes);
@@ -824,12 +873,12 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[L].nodes;
     double *r = h->s_r, *z = h->s_z, *p = h->s_p, *q = h->s_q, *ro = h->s_ro;
     auto t0 = std::chrono::steady_clock::now();
-    if (!o->use_x0) HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * cnt, h->st));
+    if (!o->use_x0) HIPCHK(h, launch_fill<double>(cnt, 0.0, x, h->st));
     HIPCHK(h, launch_zero_boundary<double>(h->cfg.ncomp, h->lv[L].n, x, h->st));
     double bb = 0.0;
     TRY(do_dot<double>(h, b, b, cnt, &bb));
     const double bn = std::sqrt(bb);
-    if (!(bn >= 0.0) || !std::isfinite(bn)) return fail(AGCA_E_NUMERIC, "non-finite right-hand side");
+    if (!std::isfinite(bn)) return fail(AGCA_E_NUMERIC, "non-finite right-hand side");
     TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
     double rr = 0.0;
     TRY(do_dot<double>(h, r, r, cnt, &rr));
@@ -839,19 +888,43 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
         if (o->record_history && hist_n < AGCA_MAX_HISTORY) stats->history[hist_n++] = v;
     };
     record(rel);
-    int it = 0;
+    int it = 0, replacements = 0;
+    bool floor_limited = false;
+    double last_true = rel;
     int32_t status = AGCA_OK;
+    // called when the recurrence reached tol: recompute the true residual into r and decide
+    // whether to stop (returns true) or to restart from it
+    auto true_check = [&](bool* stop) -> int32_t {
+        TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
+        TRY(do_dot<double>(h, r, r, cnt, &rr));
+        const double rel_true = std::sqrt(rr) / bn;
+        *stop = true;
+        if (rel_true <= o->tol) return AGCA_OK;
+        if (replacements >= 3 || rel_true > 0.5 * last_true) {
+            floor_limited = true;
+            return AGCA_OK;
+        }
+        last_true = rel_true;
+        ++replacements;
+        *stop = false;
+        return AGCA_OK;
+    };
+    double rec_rel = rel;
     if (bn == 0.0) {
-        HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * cnt, h->st));
-        rel = 0.0;
+        HIPCHK(h, launch_fill<double>(cnt, 0.0, x, h->st));
+        rel = rec_rel = 0.0;
     } else if (rel > o->tol) {
         if (o->solver == AGCA_SOLVER_PCG || o->solver == AGCA_SOLVER_FCG) {
-            TRY(precondition(h, r, z));
+            const bool flex = o->solver == AGCA_SOLVER_FCG;
             double rz = 0.0;
-            TRY(do_dot<double>(h, r, z, cnt, &rz));
-            HIPCHK(h, hipMemcpyAsync(p, z, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
-            int replacements = 0;
+            bool restart = true;
             while (it < o->max_iter) {
+                if (restart) {
+                    TRY(precondition(h, r, z));
+                    TRY(do_dot<double>(h, r, z, cnt, &rz));
+                    HIPCHK(h, hipMemcpyAsync(p, z, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
+                    restart = false;
+                }
                 if (!(rz > 0.0) || !std::isfinite(rz)) {
                     status = fail(AGCA_E_NUMERIC, "preconditioned residual is not positive");
                     break;
@@ -865,37 +938,29 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                 }
                 const double alpha = rz / pq;
                 HIPCHK(h, launch_axpby<double>(cnt, alpha, p, 1.0, x, h->st));
-                if (o->solver == AGCA_SOLVER_FCG)
+                if (flex)
                     HIPCHK(h, hipMemcpyAsync(ro, r, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
                 HIPCHK(h, launch_axpby<double>(cnt, -alpha, q, 1.0, r, h->st));
                 ++it;
                 TRY(do_dot<double>(h, r, r, cnt, &rr));
-                rel = std::sqrt(rr) / bn;
+                rel = rec_rel = std::sqrt(rr) / bn;
                 record(rel);
                 if (!std::isfinite(rel) || rel > 1e30) {
                     status = fail(AGCA_E_NUMERIC, "residual diverged");
                     break;
                 }
-                bool restart = false;
                 if (rel <= o->tol) {
-                    // the recurrence says converged: confirm with the true residual and, if
-                    // rounding has opened a gap, restart from it (residual replacement)
-                    TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
-                    TRY(do_dot<double>(h, r, r, cnt, &rr));
-                    rel = std::sqrt(rr) / bn;
-                    if (rel <= o->tol || ++replacements > 4) break;
+                    bool stop = false;
+                    TRY(true_check(&stop));
+                    if (stop) break;
                     restart = true;
-                }
-                TRY(precondition(h, r, z));
-                if (restart) {
-                    TRY(do_dot<double>(h, r, z, cnt, &rz));
-                    HIPCHK(h, hipMemcpyAsync(p, z, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
                     continue;
                 }
+                TRY(precondition(h, r, z));
                 double rz_new = 0.0;
                 TRY(do_dot<double>(h, r, z, cnt, &rz_new));
                 double beta;
-                if (o->solver == AGCA_SOLVER_FCG) {
+                if (flex) {
                     double zro = 0.0;
                     TRY(do_dot<double>(h, z, ro, cnt, &zro));
                     beta = (rz_new - zro) / rz;
@@ -906,14 +971,14 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                 HIPCHK(h, launch_axpby<double>(cnt, 1.0, z, beta, p, h->st));
             }
         } else {
-            // iterative refinement / stationary: x += B r, r = b - A x
+            // iterative refinement / stationary: x += B r, r = b - A x (the residual is exact)
             while (it < o->max_iter) {
                 TRY(precondition(h, r, z));
                 HIPCHK(h, launch_axpby<double>(cnt, 1.0, z, 1.0, x, h->st));
                 TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
                 ++it;
                 TRY(do_dot<double>(h, r, r, cnt, &rr));
-                rel = std::sqrt(rr) / bn;
+                rel = rec_rel = std::sqrt(rr) / bn;
                 record(rel);
                 if (!std::isfinite(rel) || rel > 1e30) {
                     status = fail(AGCA_E_NUMERIC, "residual diverged");
@@ -927,11 +992,15 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
     TRY(do_dot<double>(h, r, r, cnt, &rr));
     stats->rel_residual = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+    stats->recursive_rel_residual = rec_rel;
     stats->iterations = it;
-    stats->converged = stats->rel_residual <= o->tol * (1.0 + 1e-12) || bn == 0.0;
+    stats->replacements = replacements;
+    stats->converged = stats->rel_residual <= o->tol || bn == 0.0;
+    stats->floor_limited = (!stats->converged && floor_limited) ? 1 : 0;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (status != AGCA_OK) return status;
-    if (!stats->converged) return fail(AGCA_E_NOCONV, "no convergence within max_iter");
+    if (!stats->converged && !stats->floor_limited)
+        return fail(AGCA_E_NOCONV, "no convergence within max_iter");
     return AGCA_OK;
 }
 

@@ -22,7 +22,9 @@
 #if defined(__HIPCC__)
 #define AGCA_HD __host__ __device__ __forceinline__
 #else
+#include <cmath>
 #define AGCA_HD inline
+using std::fma;
 #endif
 
 namespace agca {
@@ -32,13 +34,13 @@ AGCA_HD void tet_dca(const T (&U)[8][NC], T w, T (&F)[8][NC]) {
     constexpr int a1 = axis1(S), a2 = axis2(S), a3 = axis3(S);
     constexpr int k0 = 0, k1 = 1 << a1, k2 = (1 << a1) | (1 << a2), k3 = 7;
     if constexpr (NC == 1) {
-        const T g1 = w * (U[k1][0] - U[k0][0]);
-        const T g2 = w * (U[k2][0] - U[k1][0]);
-        const T g3 = w * (U[k3][0] - U[k2][0]);
-        F[k0][0] -= g1;
-        F[k1][0] += g1 - g2;
-        F[k2][0] += g2 - g3;
-        F[k3][0] += g3;
+        const T d1 = U[k1][0] - U[k0][0];
+        const T d2 = U[k2][0] - U[k1][0];
+        const T d3 = U[k3][0] - U[k2][0];
+        F[k0][0] = fma(-w, d1, F[k0][0]);
+        F[k1][0] = fma(w, d1 - d2, F[k1][0]);
+        F[k2][0] = fma(w, d2 - d3, F[k2][0]);
+        F[k3][0] = fma(w, d3, F[k3][0]);
     } else {
         constexpr int A[3] = {a1, a2, a3};
         T d[3][3];  // d[j][c]
@@ -48,17 +50,21 @@ AGCA_HD void tet_dca(const T (&U)[8][NC], T w, T (&F)[8][NC]) {
             d[1][c] = U[k2][c] - U[k1][c];
             d[2][c] = U[k3][c] - U[k2][c];
         }
-        T q[3][3];  // q[j][physical component]
+        // symmetric s[i][j] = d_j[a_i] + d_i[a_j]; the flux of path step j in component a_i
+        // is w s[i][j]
+        T sm[3][3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i) sm[i][i] = d[i][A[i]] + d[i][A[i]];
+        sm[0][1] = sm[1][0] = d[1][A[0]] + d[0][A[1]];
+        sm[0][2] = sm[2][0] = d[2][A[0]] + d[0][A[2]];
+        sm[1][2] = sm[2][1] = d[2][A[1]] + d[1][A[2]];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) q[j][A[i]] = w * (d[j][A[i]] + d[i][A[j]]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            F[k0][c] -= q[0][c];
-            F[k1][c] += q[0][c] - q[1][c];
-            F[k2][c] += q[1][c] - q[2][c];
-            F[k3][c] += q[2][c];
+        for (int i = 0; i < 3; ++i) {
+            const int c = A[i];
+            F[k0][c] = fma(-w, sm[i][0], F[k0][c]);
+            F[k1][c] = fma(w, sm[i][0] - sm[i][1], F[k1][c]);
+            F[k2][c] = fma(w, sm[i][1] - sm[i][2], F[k2][c]);
+            F[k3][c] = fma(w, sm[i][2], F[k3][c]);
         }
     }
 }
@@ -92,25 +98,35 @@ AGCA_HD void cell_dca(const T (&U)[8][NC], const T (&w)[6], T (&F)[8][NC]) {
     tet_dca<5, NC, T>(U, w[5], F);
 }
 
-template <int S, int NC, typename T, typename BT>
-AGCA_HD void tet_mixed(const T (&U)[8][NC], T w, int32_t bi, const BT* __restrict__ blocks,
+// add a precomputed local product y = B u_e (layout 4c + a) to the simplex's corners
+template <int S, int NC, typename T>
+AGCA_HD void tet_add_product(const T* __restrict__ y, T (&F)[8][NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) F[path_corner(S, a)][c] += y[4 * c + a];
+}
+
+template <int S, int NC, typename T>
+AGCA_HD void tet_mixed(const T (&U)[8][NC], T w, int32_t bi, const T* __restrict__ yblk,
                        T (&F)[8][NC]) {
     if (bi >= 0)
-        tet_block<S, NC, T, BT>(U, blocks + (int64_t)bi * (16 * NC * NC), F);
+        tet_add_product<S, NC, T>(yblk + (int64_t)bi * (4 * NC), F);
     else
         tet_dca<S, NC, T>(U, w, F);
 }
 
-// cell with per-simplex choice: stored block where bi[s] >= 0, DCA otherwise
-template <int NC, typename T, typename BT>
+// cell with per-simplex choice: the stored block's product (computed beforehand for every
+// flagged simplex) where bi[s] >= 0, DCA otherwise
+template <int NC, typename T>
 AGCA_HD void cell_mixed(const T (&U)[8][NC], const T (&w)[6], const int32_t (&bi)[6],
-                        const BT* __restrict__ blocks, T (&F)[8][NC]) {
-    tet_mixed<0, NC, T, BT>(U, w[0], bi[0], blocks, F);
-    tet_mixed<1, NC, T, BT>(U, w[1], bi[1], blocks, F);
-    tet_mixed<2, NC, T, BT>(U, w[2], bi[2], blocks, F);
-    tet_mixed<3, NC, T, BT>(U, w[3], bi[3], blocks, F);
-    tet_mixed<4, NC, T, BT>(U, w[4], bi[4], blocks, F);
-    tet_mixed<5, NC, T, BT>(U, w[5], bi[5], blocks, F);
+                        const T* __restrict__ yblk, T (&F)[8][NC]) {
+    tet_mixed<0, NC, T>(U, w[0], bi[0], yblk, F);
+    tet_mixed<1, NC, T>(U, w[1], bi[1], yblk, F);
+    tet_mixed<2, NC, T>(U, w[2], bi[2], yblk, F);
+    tet_mixed<3, NC, T>(U, w[3], bi[3], yblk, F);
+    tet_mixed<4, NC, T>(U, w[4], bi[4], yblk, F);
+    tet_mixed<5, NC, T>(U, w[5], bi[5], yblk, F);
 }
 
 }  // namespace agca

@@ -15,10 +15,13 @@ namespace agca {
 template <typename T>
 struct LevelOp {
     int n = 0;                 // cells per axis
-    const void* nu = nullptr;  // 6 n^3 coefficients (T, or uint16 bf16 bits on the finest level)
+    const void* nu = nullptr;  // 6 n^3 coefficients, internal layout (T, or uint16 bf16 bits)
     int nu_kind = 0;           // AGCA_F64 / AGCA_F32 / AGCA_BF16 storage of nu
-    const int32_t* blk = nullptr;  // per element: index of its stored block or -1 (coarse levels)
+    const int32_t* blk = nullptr;  // per element (internal layout): stored block index or -1
+    const int32_t* ids = nullptr;  // sorted ids of the flagged elements
+    int64_t nflag = 0;
     const T* blocks = nullptr;     // flagged x (4 ncomp)^2 entries
+    T* yblk = nullptr;             // scratch: flagged x 4 ncomp products B u_e
     const T* dinv = nullptr;       // inverse Jacobi diagonal, level vector (0 on the boundary)
 };
 
@@ -49,7 +52,13 @@ hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStre
 hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_zero_boundary(int ncomp, int n, T* x, hipStream_t st);
+template <typename T>
+hipError_t launch_first_sweep(int64_t n, T omega, const T* dinv, const T* b, T* x, hipStream_t st);
+template <typename T>
+hipError_t launch_fill(int64_t n, T value, T* x, hipStream_t st);
 hipError_t launch_count_invalid(const double* v, int64_t n, int* counter, hipStream_t st);
+// element-id order (e = s + 6 cell) -> internal per-element layout (kuhn.h elem_slot)
+hipError_t launch_to_internal(int64_t cells, const double* by_id, double* internal, hipStream_t st);
 
 // setup kernels (Sections 2.2-2.3)
 hipError_t launch_minmax_from_fine(int n_coarse, const double* nu_fine, double* mn, double* mx,
@@ -59,8 +68,8 @@ hipError_t launch_minmax_up(int n_coarse, const double* mn_f, const double* mx_f
 hipError_t launch_flag(int64_t ne, const double* mn, const double* mx, double tau, int mode,
                        int32_t* flag, hipStream_t st);
 // exclusive scan of flags -> blk index (or -1) and total count (device int64)
-hipError_t launch_compact(int64_t ne, const int32_t* flag, int32_t* blk, int32_t* ids,
-                          int64_t* count_dev, void* scratch, size_t scratch_bytes,
+hipError_t launch_compact(int64_t ne, const int32_t* flag, int32_t* blk, int32_t* blk_soa,
+                          int32_t* ids, int64_t* count_dev, void* scratch, size_t scratch_bytes,
                           hipStream_t st);
 hipError_t compact_scratch_bytes(int64_t ne, size_t* bytes);
 

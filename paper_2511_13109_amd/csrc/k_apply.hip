@@ -15,14 +15,18 @@
 // suffices.  Every output node is written once, with coalesced stores.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "cube_math.h"
 #include "internal.h"
 
 namespace agca {
 namespace {
 
+// 16 x 16 cells per workgroup (15 x 15 finalised); a 16-lane DPP row is one tile row.
 constexpr int TX = 16;
 constexpr int TY = 16;
+constexpr int NTHREADS = TX * TY;
 
 template <typename T>
 __device__ __forceinline__ T shr1_row(T v) {
@@ -41,61 +45,215 @@ __device__ __forceinline__ T shr1_row(T v) {
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void load_nu6(const double* __restrict__ p, T (&w)[6], T scale) {
-    const double2* q = reinterpret_cast<const double2*>(p);
-    const double2 a = q[0], b = q[1], c = q[2];
-    w[0] = T(a.x) * scale; w[1] = T(a.y) * scale; w[2] = T(b.x) * scale;
-    w[3] = T(b.y) * scale; w[4] = T(c.x) * scale; w[5] = T(c.y) * scale;
-}
-template <typename T>
-__device__ __forceinline__ void load_nu6(const float* __restrict__ p, T (&w)[6], T scale) {
-    const float2* q = reinterpret_cast<const float2*>(p);
-    const float2 a = q[0], b = q[1], c = q[2];
-    w[0] = T(a.x) * scale; w[1] = T(a.y) * scale; w[2] = T(b.x) * scale;
-    w[3] = T(b.y) * scale; w[4] = T(c.x) * scale; w[5] = T(c.y) * scale;
-}
+// the 6 coefficients of a cell in the internal per-element layout: one contiguous
+// 6-value run (vector loads) or six planes `stride` apart
 __device__ __forceinline__ float bf16_to_float(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 template <typename T>
-__device__ __forceinline__ void load_nu6(const uint16_t* __restrict__ p, T (&w)[6], T scale) {
-    const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
-    const uint32_t a = q[0], b = q[1], c = q[2];
-    w[0] = T(bf16_to_float(a & 0xffffu)) * scale; w[1] = T(bf16_to_float(a >> 16)) * scale;
-    w[2] = T(bf16_to_float(b & 0xffffu)) * scale; w[3] = T(bf16_to_float(b >> 16)) * scale;
-    w[4] = T(bf16_to_float(c & 0xffffu)) * scale; w[5] = T(bf16_to_float(c >> 16)) * scale;
+__device__ __forceinline__ void load_nu6(const double* __restrict__ p, int64_t stride, T (&w)[6],
+                                         T scale) {
+    if constexpr (AGCA_ELEM_SOA) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) w[s] = T(p[s * stride]) * scale;
+    } else {
+        const double2* q = reinterpret_cast<const double2*>(p);
+        const double2 a = q[0], b = q[1], c = q[2];
+        w[0] = T(a.x) * scale; w[1] = T(a.y) * scale; w[2] = T(b.x) * scale;
+        w[3] = T(b.y) * scale; w[4] = T(c.x) * scale; w[5] = T(c.y) * scale;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void load_nu6(const float* __restrict__ p, int64_t stride, T (&w)[6],
+                                         T scale) {
+    if constexpr (AGCA_ELEM_SOA) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) w[s] = T(p[s * stride]) * scale;
+    } else {
+        const float2* q = reinterpret_cast<const float2*>(p);
+        const float2 a = q[0], b = q[1], c = q[2];
+        w[0] = T(a.x) * scale; w[1] = T(a.y) * scale; w[2] = T(b.x) * scale;
+        w[3] = T(b.y) * scale; w[4] = T(c.x) * scale; w[5] = T(c.y) * scale;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void load_nu6(const uint16_t* __restrict__ p, int64_t stride, T (&w)[6],
+                                         T scale) {
+    if constexpr (AGCA_ELEM_SOA) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) w[s] = T(bf16_to_float(p[s * stride])) * scale;
+    } else {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+        const uint32_t a = q[0], b = q[1], c = q[2];
+        w[0] = T(bf16_to_float(a & 0xffffu)) * scale; w[1] = T(bf16_to_float(a >> 16)) * scale;
+        w[2] = T(bf16_to_float(b & 0xffffu)) * scale; w[3] = T(bf16_to_float(b >> 16)) * scale;
+        w[4] = T(bf16_to_float(c & 0xffffu)) * scale; w[5] = T(bf16_to_float(c >> 16)) * scale;
+    }
 }
 
+// Workgroup -> tile mapping.  Consecutive workgroups are dispatched round-robin
+// to the 8 XCDs, each with its own L2; remapping the linear id so that every XCD
+// receives one contiguous range of tiles (x fastest, then y, then z chunks)
+// keeps the halo rows that neighbouring tiles share in the same L2.
+__device__ __forceinline__ void tile_of(int gx, int gy, int gz, int& bx, int& by, int& bz) {
+    const int total = gx * gy * gz;
+    const int b = blockIdx.x;
+    int lin = b;
+    if (gz > 0) {
+        const int q = total >> 3, r = total & 7;
+        const int xcd = b & 7, j = b >> 3;
+        lin = xcd * q + min(xcd, r) + j;
+    }
+    gz = gz > 0 ? gz : -gz;
+    bx = lin % gx;
+    by = (lin / gx) % gy;
+    bz = lin / (gx * gy);
+}
+
+#ifndef AGCA_CUBE_PREFETCH_NODE
+#define AGCA_CUBE_PREFETCH_NODE 1
+#endif
+#ifndef AGCA_CUBE_WAVES_F64V
+#define AGCA_CUBE_WAVES_F64V 3
+#endif
+
+// occupancy target handed to the register allocator (0: compiler's choice)
+template <int NC, typename T>
+struct CubeWaves {
+    static constexpr int value = (NC == 3 && sizeof(T) == 8) ? AGCA_CUBE_WAVES_F64V : 0;
+};
+// prefetch the next node's right-hand side and diagonal one step ahead (costs registers;
+// off for the FP64 vector kernel, whose occupancy is register-bound)
+#ifndef AGCA_CUBE_PREFETCH_NODE_F64V
+#define AGCA_CUBE_PREFETCH_NODE_F64V 0
+#endif
+template <int NC, typename T>
+struct CubePrefetchNode {
+    static constexpr bool value = (NC == 3 && sizeof(T) == 8) ? AGCA_CUBE_PREFETCH_NODE_F64V
+                                                              : AGCA_CUBE_PREFETCH_NODE;
+};
+
 template <int NC, typename T, typename NT, int MODE, bool BLK>
-__global__ void __launch_bounds__(TX * TY)
-k_cube(const int n, const int zc, const T* __restrict__ u, const NT* __restrict__ nu,
-       const int32_t* __restrict__ blk, const T* __restrict__ blocks, const T* __restrict__ b,
-       const T* __restrict__ dinv, T* __restrict__ out, const T scale, const T omega) {
+__global__ void __launch_bounds__(NTHREADS)
+__attribute__((amdgpu_waves_per_eu(CubeWaves<NC, T>::value > 0 ? CubeWaves<NC, T>::value : 1)))
+k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
+       const T* __restrict__ u, const NT* __restrict__ nu, const int32_t* __restrict__ blk,
+       const T* __restrict__ yblk, const T* __restrict__ b, const T* __restrict__ dinv,
+       T* __restrict__ out, const T scale, const T omega) {
     __shared__ T ubuf[2][NC][TY + 1][TX + 1];
     __shared__ T ybuf[2][NC][2][TY][TX];
 
+    int bx, by, bz;
+    tile_of(gx, gy, gz, bx, by, bz);
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int X0 = blockIdx.x * (TX - 1), Y0 = blockIdx.y * (TY - 1), Z0 = blockIdx.z * zc;
+    const int tid = tx + TX * ty;
+    const int X0 = bx * (TX - 1), Y0 = by * (TY - 1), Z0 = bz * zc;
     const int cx = X0 - 1 + tx, cy = Y0 - 1 + ty;
     const int64_t n1 = n + 1;
     const int64_t N = n1 * n1 * n1;
+    const int64_t layer = n1 * n1;          // nodes per z layer
+    const int64_t cells = (int64_t)n * n * n;
+    const int64_t clayer = (int64_t)n * n;  // cells per z layer
     const int zend = min(Z0 + zc - 1, n);
 
-    auto uval = [&](int x, int y, int z, int c) -> T {
-        if (x <= 0 || y <= 0 || z <= 0 || x >= n || y >= n || z >= n) return T(0);
-        return u[c * N + x + n1 * (y + n1 * (int64_t)z)];
+    // All loads are unconditional: addresses are clamped into the arrays and values
+    // outside the interior are replaced by zero afterwards, so the loop has no
+    // divergent branches around memory accesses.
+    // u tile (TX+1) x (TY+1) per layer: entry tid for every thread, entry NTHREADS + tid
+    // for the first wavefronts (duplicates of the last entry write the same value).
+    constexpr int TW = TX + 1;
+    constexpr int TE = (TX + 1) * (TY + 1);
+    constexpr int NB = ((TE - NTHREADS + 63) / 64) * 64;  // whole wavefronts
+    const int qa = tid;
+    const int qb = min(NTHREADS + tid, TE - 1);
+    const bool has_b = tid < NB;
+    auto tile_ptr = [&](int q, bool& in_xy) -> const T* {
+        const int x = X0 - 1 + q % TW, y = Y0 - 1 + q / TW;
+        in_xy = x > 0 && x < n && y > 0 && y < n;
+        const int xc = min(max(x, 0), n), yc = min(max(y, 0), n);
+        return u + xc + n1 * yc;
     };
-    auto fill = [&](int buf, int z) {
+    bool ina, inb;
+    const T* pa = tile_ptr(qa, ina);
+    const T* pb = tile_ptr(qb, inb);
+    auto load_tile = [&](int z, T (&va)[NC], T (&vb)[NC]) {
+        const bool zin = z > 0 && z < n;
+        const int64_t off = (int64_t)min(max(z, 0), n) * layer;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            ubuf[buf][c][ty][tx] = uval(cx, cy, z, c);
-            if (tx == TX - 1) ubuf[buf][c][ty][TX] = uval(cx + 1, cy, z, c);
-            if (ty == TY - 1) ubuf[buf][c][TY][tx] = uval(cx, cy + 1, z, c);
-            if (tx == TX - 1 && ty == TY - 1) ubuf[buf][c][TY][TX] = uval(cx + 1, cy + 1, z, c);
+            const T a = pa[c * N + off];
+            va[c] = (ina && zin) ? a : T(0);
+            if (has_b) {
+                const T bb = pb[c * N + off];
+                vb[c] = (inb && zin) ? bb : T(0);
+            }
+        }
+    };
+    auto store_tile = [&](int buf, const T (&va)[NC], const T (&vb)[NC]) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            (&ubuf[buf][c][0][0])[qa] = va[c];
+            if (has_b) (&ubuf[buf][c][0][0])[qb] = vb[c];
         }
     };
 
-    fill((Z0 + 1) & 1, Z0 - 1);
-    fill(Z0 & 1, Z0);
+    const bool col_ok = cx >= 0 && cx < n && cy >= 0 && cy < n;
+    const bool writer = tx >= 1 && ty >= 1 && cx <= n && cy <= n;
+    const bool xin = cx > 0 && cx < n && cy > 0 && cy < n;
+    constexpr bool NEEDS_B = MODE != MODE_APPLY;
+    // cell and node columns of this thread, clamped
+    const int64_t cellcol = min(max(cx, 0), n - 1) + (int64_t)n * min(max(cy, 0), n - 1);
+    const NT* pnu = nu + elem_slot(0, cellcol, cells);
+    const int32_t* pblk = blk ? blk + elem_slot(0, cellcol, cells) : nullptr;
+    constexpr int64_t kSlotsPerCell = AGCA_ELEM_SOA ? 1 : 6;  // z-layer stride factor
+    const int64_t col = min(max(cx, 0), n) + n1 * min(max(cy, 0), n);
+
+    auto load_cell = [&](int z, T (&w)[6], int32_t (&bi)[6]) {
+        const bool ok = col_ok && z >= 0 && z < n;
+        const int64_t off = (int64_t)min(max(z, 0), n - 1) * clayer * kSlotsPerCell;
+        T tmp[6];
+        load_nu6(pnu + off, cells, tmp, scale);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) w[s] = ok ? tmp[s] : T(0);
+        if constexpr (BLK) {
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const int32_t v = pblk[off + elem_slot(s, 0, cells)];
+                bi[s] = ok ? v : -1;
+            }
+        }
+    };
+    auto load_node = [&](int z, T (&bq)[NC], T (&dq)[NC]) {
+        if constexpr (NEEDS_B) {
+            const bool ok = writer && xin && z > 0 && z < n && z >= Z0 && z <= zend;
+            const int64_t p = col + (int64_t)min(max(z, 0), n) * layer;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const T bv = b[c * N + p];
+                bq[c] = ok ? bv : T(0);
+                if constexpr (MODE == MODE_JACOBI) {
+                    const T dv = dinv[c * N + p];
+                    dq[c] = ok ? dv : T(0);
+                } else {
+                    dq[c] = T(0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) bq[c] = dq[c] = T(0);
+        }
+    };
+
+    {
+        T va[NC], vb[NC];
+        load_tile(Z0 - 1, va, vb);
+        store_tile((Z0 + 1) & 1, va, vb);
+        load_tile(Z0, va, vb);
+        store_tile(Z0 & 1, va, vb);
+    }
+    T w_cur[6];
+    int32_t bi_cur[6];
+    load_cell(Z0 - 1, w_cur, bi_cur);
+    T bq[NC], dq[NC];
+    load_node(Z0 - 1, bq, dq);
     __syncthreads();
     T Ulo[4][NC];
 #pragma unroll
@@ -108,10 +266,6 @@ k_cube(const int n, const int zc, const T* __restrict__ u, const NT* __restrict_
 #pragma unroll
     for (int c = 0; c < NC; ++c) carry[c] = T(0);
 
-    const bool col_ok = cx >= 0 && cx < n && cy >= 0 && cy < n;
-    const bool writer = tx >= 1 && ty >= 1 && cx <= n && cy <= n;
-    const bool xin = cx > 0 && cx < n && cy > 0 && cy < n;
-
     for (int z = Z0 - 1; z <= zend; ++z) {
         const int cur = (z + 1) & 1;  // buffer holding layer z+1
         T U[8][NC];
@@ -122,37 +276,25 @@ k_cube(const int n, const int zc, const T* __restrict__ u, const NT* __restrict_
                 U[k][c] = Ulo[k][c];
                 U[k + 4][c] = ubuf[cur][c][ty + (k >> 1)][tx + (k & 1)];
             }
-        // next layer's values, written after this step's compute
-        T nxt[NC], nxt_x[NC], nxt_y[NC], nxt_xy[NC];
-        const bool need_next = z + 2 <= zend + 1;
-        if (need_next) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                nxt[c] = uval(cx, cy, z + 2, c);
-                if (tx == TX - 1) nxt_x[c] = uval(cx + 1, cy, z + 2, c);
-                if (ty == TY - 1) nxt_y[c] = uval(cx, cy + 1, z + 2, c);
-                if (tx == TX - 1 && ty == TY - 1) nxt_xy[c] = uval(cx + 1, cy + 1, z + 2, c);
-            }
-        }
+        // issue the next step's loads first so that they overlap this step's work
+        const bool need_next = z + 2 <= zend + 1;  // block-uniform
+        T va[NC], vb[NC];
+        if (need_next) load_tile(z + 2, va, vb);
+        T w_nxt[6];
+        int32_t bi_nxt[6];
+        load_cell(z + 1 <= zend ? z + 1 : -1, w_nxt, bi_nxt);
+        T bq_n[NC], dq_n[NC];
+        if constexpr (CubePrefetchNode<NC, T>::value) load_node(z + 1, bq_n, dq_n);
 
         T F[8][NC];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
             for (int c = 0; c < NC; ++c) F[k][c] = T(0);
-        if (col_ok && z >= 0 && z < n) {
-            const int64_t cell = cx + (int64_t)n * (cy + (int64_t)n * z);
-            T w[6];
-            load_nu6(nu + 6 * cell, w, scale);
-            if constexpr (BLK) {
-                int32_t bi[6];
-#pragma unroll
-                for (int s = 0; s < 6; ++s) bi[s] = blk[6 * cell + s];
-                cell_mixed<NC, T, T>(U, w, bi, blocks, F);
-            } else {
-                cell_dca<NC, T>(U, w, F);
-            }
-        }
+        if constexpr (BLK)
+            cell_mixed<NC, T>(U, w_cur, bi_cur, yblk, F);
+        else
+            cell_dca<NC, T>(U, w_cur, F);
 
         // x: add the left neighbour's dx=1 corners to my dx=0 corners -> P[dy][dz]
         T P[2][2][NC];
@@ -171,16 +313,7 @@ k_cube(const int n, const int zc, const T* __restrict__ u, const NT* __restrict_
             ybuf[yb][c][0][ty][tx] = P[1][0][c];
             ybuf[yb][c][1][ty][tx] = P[1][1][c];
         }
-        if (need_next) {
-            const int nb = z & 1;  // buffer of layer z+2 (it held layer z, read one step ago)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                ubuf[nb][c][ty][tx] = nxt[c];
-                if (tx == TX - 1) ubuf[nb][c][ty][TX] = nxt_x[c];
-                if (ty == TY - 1) ubuf[nb][c][TY][tx] = nxt_y[c];
-                if (tx == TX - 1 && ty == TY - 1) ubuf[nb][c][TY][TX] = nxt_xy[c];
-            }
-        }
+        if (need_next) store_tile(z & 1, va, vb);  // buffer of layer z+2 held layer z
         __syncthreads();
 
         if (writer) {
@@ -191,8 +324,9 @@ k_cube(const int n, const int zc, const T* __restrict__ u, const NT* __restrict_
                 s1[c] = P[0][1][c] + ybuf[yb][c][1][ty - 1][tx];
             }
             if (z >= Z0) {
-                const int64_t p = cx + n1 * (cy + n1 * (int64_t)z);
+                const int64_t p = col + (int64_t)z * layer;
                 const bool interior = xin && z > 0 && z < n;
+                if constexpr (!CubePrefetchNode<NC, T>::value) load_node(z, bq, dq);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const T av = carry[c] + s0[c];
@@ -200,10 +334,9 @@ k_cube(const int n, const int zc, const T* __restrict__ u, const NT* __restrict_
                     if constexpr (MODE == MODE_APPLY) {
                         o = av;
                     } else if constexpr (MODE == MODE_RESIDUAL) {
-                        o = interior ? b[c * N + p] - av : T(0);
+                        o = bq[c] - av;
                     } else {
-                        o = interior ? Ulo[0][c] + omega * dinv[c * N + p] * (b[c * N + p] - av)
-                                     : T(0);
+                        o = Ulo[0][c] + omega * dq[c] * (bq[c] - av);
                     }
                     out[c * N + p] = interior ? o : T(0);
                 }
@@ -215,14 +348,71 @@ k_cube(const int n, const int zc, const T* __restrict__ u, const NT* __restrict_
         for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int c = 0; c < NC; ++c) Ulo[k][c] = U[k + 4][c];
+#pragma unroll
+        for (int s2 = 0; s2 < 6; ++s2) {
+            w_cur[s2] = w_nxt[s2];
+            bi_cur[s2] = bi_nxt[s2];
+        }
+        if constexpr (CubePrefetchNode<NC, T>::value) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                bq[c] = bq_n[c];
+                dq[c] = dq_n[c];
+            }
+        }
     }
 }
 
+// Products y_f = B_f u_e of the stored Galerkin blocks of all flagged simplices of a
+// level, one thread per (flagged simplex, block row); the element loop then adds
+// y_f to the simplex's corners.  Reads each block once, coalesced by rows.
+template <int NC, typename T>
+__global__ void __launch_bounds__(256)
+k_block_products(const int n, const int64_t nflag, const int32_t* __restrict__ ids,
+                 const T* __restrict__ blocks, const T* __restrict__ u, T* __restrict__ y) {
+    constexpr int M = 4 * NC;
+    const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (t >= nflag * M) return;
+    const int64_t f = t / M;
+    const int r = (int)(t % M);
+    const int64_t e = ids[f];
+    const int s = (int)(e % 6);
+    int64_t cell = e / 6;
+    const int cx = (int)(cell % n);
+    cell /= n;
+    const int cy = (int)(cell % n);
+    const int cz = (int)(cell / n);
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int k1 = 1 << axis1(s), k2 = k1 | (1 << axis2(s));
+    const int corner[4] = {0, k1, k2, 7};
+    T xv[M];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int k = corner[a];
+        const int x = cx + (k & 1), yy = cy + ((k >> 1) & 1), z = cz + ((k >> 2) & 1);
+        const bool bd = x == 0 || yy == 0 || z == 0 || x == n || yy == n || z == n;
+        const int64_t p = x + n1 * (yy + n1 * (int64_t)z);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xv[4 * c + a] = bd ? T(0) : u[c * N + p];
+    }
+    const T* row = blocks + f * (M * M) + r * M;
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc += row[c] * xv[c];
+    y[t] = acc;
+}
+
 int pick_zc(int n) {
-    const int g = (n + 1 + TX - 2) / (TX - 1);
-    const int cols = g * g;
-    int zc = 64;
-    while (zc > 4 && (int64_t)cols * ((n + 1 + zc - 1) / zc) < 2048) zc /= 2;
+    static const int forced = [] {
+        const char* e = getenv("AGCA_CUBE_ZC");
+        return e ? atoi(e) : 0;
+    }();
+    if (forced > 0) return forced;
+    // chunks of 16 z layers amortise the one halo layer each chunk recomputes; small
+    // levels use shorter chunks to expose more workgroups
+    const int cols = ((n + 1 + TX - 2) / (TX - 1)) * ((n + 1 + TY - 2) / (TY - 1));
+    int zc = 16;
+    while (zc > 2 && (int64_t)cols * ((n + 1 + zc - 1) / zc) < 512) zc /= 2;
     return zc;
 }
 
@@ -232,10 +422,26 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omeg
     const int n = op.n;
     const int zc = pick_zc(n);
     dim3 block(TX, TY, 1);
-    dim3 grid((n + 1 + TX - 2) / (TX - 1), (n + 1 + TY - 2) / (TY - 1), (n + 1 + zc - 1) / zc);
+    const int gx = (n + 1 + TX - 2) / (TX - 1), gy = (n + 1 + TY - 2) / (TY - 1),
+              gz = (n + 1 + zc - 1) / zc;
+    dim3 grid((unsigned)(gx * gy * gz), 1, 1);
     const T scale = T(1.0 / (6.0 * n));
-    hipLaunchKernelGGL((k_cube<NC, T, NT, MODE, BLK>), grid, block, 0, st, n, zc, u,
-                       reinterpret_cast<const NT*>(op.nu), op.blk, op.blocks, b, op.dinv, out,
+    if constexpr (BLK) {
+        if (op.nflag > 0) {
+            const int64_t threads = op.nflag * 4 * NC;
+            hipLaunchKernelGGL((k_block_products<NC, T>), dim3((unsigned)((threads + 255) / 256)),
+                               dim3(256), 0, st, n, op.nflag, op.ids, op.blocks, u, op.yblk);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    static const bool xcd_map = [] {
+        const char* e = getenv("AGCA_CUBE_XCD");
+        return e ? atoi(e) != 0 : true;
+    }();
+    hipLaunchKernelGGL((k_cube<NC, T, NT, MODE, BLK>), grid, block, 0, st, n, zc, gx, gy,
+                       xcd_map ? gz : -gz, u,
+                       reinterpret_cast<const NT*>(op.nu), op.blk, op.yblk, b, op.dinv, out,
                        scale, omega);
     return hipGetLastError();
 }
@@ -246,7 +452,7 @@ hipError_t dispatch_nu(const LevelOp<T>& op, const T* u, const T* b, T* out, T o
     if (!op.nu || !u || !out || op.n < 2) return hipErrorInvalidValue;
     if (MODE != MODE_APPLY && !b) return hipErrorInvalidValue;
     if (MODE == MODE_JACOBI && !op.dinv) return hipErrorInvalidValue;
-    if (op.blk && !op.blocks) return hipErrorInvalidValue;
+    if (op.blk && (!op.blocks || !op.ids || !op.yblk || op.nflag <= 0)) return hipErrorInvalidValue;
     const bool blk = op.blk != nullptr;
     if constexpr (sizeof(T) == 8) {
         if (op.nu_kind != AGCA_F64) return hipErrorInvalidValue;

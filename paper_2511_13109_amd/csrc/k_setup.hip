@@ -26,10 +26,11 @@ k_minmax_from_fine(int n, const double* __restrict__ nu_fine, double* __restrict
     const int64_t ne = 6LL * n * n * n;
     const int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (e >= ne) return;
+    const int64_t cells_f = 8LL * n * n * n;
     double a = INFINITY, b = -INFINITY;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const double v = nu_fine[child_id(n, e, k)];
+        const double v = nu_fine[elem_index(child_id(n, e, k), cells_f)];
         a = fmin(a, v);
         b = fmax(b, v);
     }
@@ -67,12 +68,14 @@ k_flag(int64_t ne, const double* __restrict__ mn, const double* __restrict__ mx,
 
 __global__ void __launch_bounds__(NT)
 k_scatter_ids(int64_t ne, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
-              int32_t* __restrict__ blk, int32_t* __restrict__ ids, int64_t* __restrict__ count) {
+              int32_t* __restrict__ blk, int32_t* __restrict__ blk_soa, int32_t* __restrict__ ids,
+              int64_t* __restrict__ count) {
     const int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (e >= ne) return;
     const int32_t f = flag[e];
     const int32_t p = pos[e];
     blk[e] = f ? p : -1;
+    blk_soa[elem_index(e, ne / 6)] = f ? p : -1;  // internal layout
     if (f) ids[p] = (int32_t)e;
     if (e == ne - 1) *count = (int64_t)p + f;
 }
@@ -104,6 +107,7 @@ k_gca_fused2(int ncomp, int n, const double* __restrict__ nu_fine, double w_scal
     const int cd = (int)(t % ncc);
     const int c = cd / ncomp, d = cd % ncomp;
     const int M = 4 * ncomp;
+    const int64_t cells_f = 64LL * n * n * n;
     double Ge[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) Ge[i] = 0.0;
@@ -115,7 +119,7 @@ k_gca_fused2(int ncomp, int n, const double* __restrict__ nu_fine, double w_scal
         for (int kk = 0; kk < 8; ++kk) {
             const int64_t ge = child_id(2 * n, ce, kk);
             double K[16];
-            fine_block(ncomp, (int)(ge % 6), c, d, nu_fine[ge] * w_scale, K);
+            fine_block(ncomp, (int)(ge % 6), c, d, nu_fine[elem_index(ge, cells_f)] * w_scale, K);
             add_ptkp(kk, K, Gc);
         }
         const int32_t bc = blk_child[ce];
@@ -138,13 +142,14 @@ k_gca_from_fine(int ncomp, int n, int64_t nflag, const int32_t* __restrict__ ids
     const int c = cd / ncomp, d = cd % ncomp;
     const int M = 4 * ncomp;
     const int64_t e = ids[i];
+    const int64_t cells_f = 8LL * n * n * n;
     double G[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) G[q] = 0.0;
     for (int k = 0; k < 8; ++k) {
         const int64_t ge = child_id(n, e, k);
         double K[16];
-        fine_block(ncomp, (int)(ge % 6), c, d, nu_fine[ge] * w_scale, K);
+        fine_block(ncomp, (int)(ge % 6), c, d, nu_fine[elem_index(ge, cells_f)] * w_scale, K);
         add_ptkp(k, K, G);
     }
     store_block(blocks + i * M * M, M, c, d, G);
@@ -194,6 +199,7 @@ k_diagonal(int n, const double* __restrict__ nu, double scale, const int32_t* __
     const int x = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
     const bool bd = x == 0 || y == 0 || z == 0 || x == n || y == n || z == n;
     constexpr int M = 4 * NC;
+    const int64_t cells = (int64_t)n * n * n;
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
@@ -213,7 +219,7 @@ k_diagonal(int n, const double* __restrict__ nu, double scale, const int32_t* __
                     if (bi >= 0)
                         acc[c] += blocks[(int64_t)bi * M * M + (4 * c + a) * M + 4 * c + a];
                     else
-                        acc[c] += nu[e] * scale * (double)elem_entry(NC, s, c, a, c, a);
+                        acc[c] += nu[elem_slot(s, cell, cells)] * scale * (double)elem_entry(NC, s, c, a, c, a);
                 }
             }
         }
@@ -262,8 +268,10 @@ hipError_t compact_scratch_bytes(int64_t ne, size_t* bytes) {
     *bytes = tmp + (size_t)ne * sizeof(int32_t) + 256;
     return err;
 }
-hipError_t launch_compact(int64_t ne, const int32_t* flag, int32_t* blk, int32_t* ids,
-                          int64_t* count_dev, void* scratch, size_t scratch_bytes, hipStream_t st) {
+hipError_t launch_compact(int64_t ne, const int32_t* flag, int32_t* blk, int32_t* blk_soa,
+                          int32_t* ids, int64_t* count_dev, void* scratch, size_t scratch_bytes,
+                          hipStream_t st) {
+    if (!flag || !blk || !blk_soa || !ids || !count_dev || !scratch) return hipErrorInvalidValue;
     // scratch: [pos (ne int32, 256-aligned)] [cub temp]
     int32_t* pos = static_cast<int32_t*>(scratch);
     size_t off = (((size_t)ne * sizeof(int32_t)) + 255) & ~(size_t)255;
@@ -271,8 +279,8 @@ hipError_t launch_compact(int64_t ne, const int32_t* flag, int32_t* blk, int32_t
     size_t tmp_bytes = scratch_bytes - off;
     hipError_t err = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, pos, (int)ne, st);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_scatter_ids, dim3(grid_for(ne)), dim3(NT), 0, st, ne, flag, pos, blk, ids,
-                       count_dev);
+    hipLaunchKernelGGL(k_scatter_ids, dim3(grid_for(ne)), dim3(NT), 0, st, ne, flag, pos, blk, blk_soa,
+                       ids, count_dev);
     return hipGetLastError();
 }
 hipError_t launch_gca_fused2(int ncomp, int n, const double* nu_fine, double h_fine,

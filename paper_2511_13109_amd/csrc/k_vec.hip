@@ -162,6 +162,22 @@ k_cast(int from, int to, const void* __restrict__ src, void* __restrict__ dst, i
     }
 }
 
+// first damped-Jacobi sweep from a zero initial guess: x = omega D^-1 b
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_first_sweep(int64_t n, T omega, const T* __restrict__ dinv, const T* __restrict__ b,
+              T* __restrict__ x) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride)
+        x[i] = omega * dinv[i] * b[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_fill(int64_t n, T value, T* __restrict__ x) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) x[i] = value;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT) k_zero_boundary(int ncomp, int n, T* __restrict__ x) {
     const int64_t n1 = n + 1, N = n1 * n1 * n1;
@@ -211,7 +227,14 @@ k_grad(int n, const double* __restrict__ nu, double scale, const double* __restr
     double e[6];
     cell_energy<NC, double>(U, W, e);
 #pragma unroll
-    for (int s = 0; s < 6; ++s) g[6 * cell + s] = -nu[6 * cell + s] * scale * e[s];
+    for (int s = 0; s < 6; ++s) g[6 * cell + s] = -nu[elem_slot(s, cell, cells)] * scale * e[s];
+}
+
+__global__ void __launch_bounds__(NT)
+k_to_internal(int64_t cells, const double* __restrict__ by_id, double* __restrict__ internal) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < 6 * cells; i += stride)
+        internal[elem_index(i, cells)] = by_id[i];
 }
 
 // b_i = sum over the simplices containing node i of f_e |e| / 4 (per component)
@@ -298,6 +321,20 @@ hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, 
     return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_first_sweep(int64_t n, T omega, const T* dinv, const T* b, T* x, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!dinv || !b || !x) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_first_sweep<T>, dim3(grid_stride(n)), dim3(NT), 0, st, n, omega, dinv, b, x);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_fill(int64_t n, T value, T* x, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!x) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_stride(n)), dim3(NT), 0, st, n, value, x);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_zero_boundary(int ncomp, int n, T* x, hipStream_t st) {
     if (!x) return hipErrorInvalidValue;
     const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
@@ -307,6 +344,13 @@ hipError_t launch_zero_boundary(int ncomp, int n, T* x, hipStream_t st) {
 hipError_t launch_count_invalid(const double* v, int64_t n, int* counter, hipStream_t st) {
     if (!v || !counter) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_count_invalid, dim3(grid_stride(n)), dim3(NT), 0, st, v, n, counter);
+    return hipGetLastError();
+}
+hipError_t launch_to_internal(int64_t cells, const double* by_id, double* internal, hipStream_t st) {
+    if (cells <= 0) return hipSuccess;
+    if (!by_id || !internal) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_to_internal, dim3(grid_stride(6 * cells)), dim3(NT), 0, st, cells, by_id,
+                       internal);
     return hipGetLastError();
 }
 hipError_t launch_grad(int ncomp, int n, const double* nu, double scale, const double* u,
@@ -337,7 +381,9 @@ hipError_t launch_load_vector(int ncomp, int n, const double* f, double vol4, do
     template hipError_t launch_dot_partial<T>(const T*, const T*, int64_t, double*, int,       \
                                               hipStream_t);                                    \
     template hipError_t launch_axpby<T>(int64_t, double, const T*, double, T*, hipStream_t);   \
-    template hipError_t launch_zero_boundary<T>(int, int, T*, hipStream_t);
+    template hipError_t launch_zero_boundary<T>(int, int, T*, hipStream_t);                    \
+    template hipError_t launch_first_sweep<T>(int64_t, T, const T*, const T*, T*, hipStream_t);  \
+    template hipError_t launch_fill<T>(int64_t, T, T*, hipStream_t);
 AGCA_INST(double)
 AGCA_INST(float)
 #undef AGCA_INST

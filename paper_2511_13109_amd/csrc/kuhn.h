@@ -122,6 +122,20 @@ AGCA_HDC inline int64_t node_id(int64_t n, int64_t x, int64_t y, int64_t z) {
 AGCA_HDC inline int64_t elem_id(int64_t n, int64_t cx, int64_t cy, int64_t cz, int s) {
     return s + 6 * (cx + n * (cy + n * cz));
 }
+// Internal storage of per-element data.  Element-id order (slot 6 cell + s) keeps the
+// six coefficients of a cell in one contiguous 48-byte run, which streams better along
+// the element loop's z march than six separate planes (slot s cells + cell); the
+// plane layout stays available at compile time for measurements.
+#ifndef AGCA_ELEM_SOA
+#define AGCA_ELEM_SOA 0
+#endif
+AGCA_HDC inline int64_t elem_slot(int s, int64_t cell, int64_t cells) {
+    return AGCA_ELEM_SOA ? s * cells + cell : 6 * cell + s;
+}
+AGCA_HDC inline int64_t elem_index(int64_t e, int64_t cells) {
+    return elem_slot((int)(e % 6), e / 6, cells);
+}
+
 // id of child k of element e on a level with n cells (children on the level with 2n cells)
 AGCA_HDC inline int64_t child_id(int64_t n, int64_t e, int k) {
     const int s = (int)(e % 6);

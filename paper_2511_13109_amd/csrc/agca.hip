@@ -58,7 +58,8 @@ struct agca_hier {
     std::vector<Level> lv;
     double* ainv0 = nullptr;
     double* partial = nullptr;
-    int nb_partial = 1024;
+    int nb_partial = 1024;       // workgroups of the grid-stride reduction kernels
+    int partial_cap = 0;
     double* red = nullptr;       // reduction results (device)
     int* counter = nullptr;      // invalid-coefficient counter (device)
     double* red_host = nullptr;  // pinned host mirror
@@ -267,6 +268,19 @@ int32_t do_dot(agca_hier* h, const T* x, const T* y, int64_t count, double* out)
     HIPCHK(h, hipMemcpyAsync(h->red_host, h->red, sizeof(double), hipMemcpyDeviceToHost, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     *out = h->red_host[0];
+    return AGCA_OK;
+}
+
+// sum nb partials into red[slot] (device)
+int32_t reduce_to(agca_hier* h, const double* partial, int nb, int slot) {
+    HIPCHK(h, launch_sum_partials(partial, nb, h->red + slot, h->st));
+    return AGCA_OK;
+}
+// copy red[0..k) to the host and wait
+int32_t fetch(agca_hier* h, int k, double* out) {
+    HIPCHK(h, hipMemcpyAsync(h->red_host, h->red, sizeof(double) * k, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    for (int i = 0; i < k; ++i) out[i] = h->red_host[i];
     return AGCA_OK;
 }
 
@@ -647,7 +661,10 @@ int32_t agca_create(const agca_config* cfg, const double* nu_fine, const double*
         if (rc == AGCA_OK && l > 0) rc = dev_alloc(h, &lv.r, nv * ts, &lv.bytes);
     }
     if (rc == AGCA_OK) rc = alloc_t(h, &h->ainv0, 9);
-    if (rc == AGCA_OK) rc = alloc_t(h, &h->partial, h->nb_partial);
+    if (rc == AGCA_OK) {
+        h->partial_cap = std::max(2 * h->nb_partial, cube_grid_blocks(h->lv[L].n));
+        rc = alloc_t(h, &h->partial, h->partial_cap);
+    }
     if (rc == AGCA_OK) rc = alloc_t(h, &h->red, 16);
     if (rc == AGCA_OK) rc = alloc_t(h, &h->counter, 4);
     if (rc == AGCA_OK) {
@@ -918,10 +935,14 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
             const bool flex = o->solver == AGCA_SOLVER_FCG;
             double rz = 0.0;
             bool restart = true;
+            double tmp[2];
             while (it < o->max_iter) {
                 if (restart) {
                     TRY(precondition(h, r, z));
-                    TRY(do_dot<double>(h, r, z, cnt, &rz));
+                    HIPCHK(h, launch_dot2(cnt, z, r, nullptr, h->partial, h->nb_partial, h->st));
+                    TRY(reduce_to(h, h->partial, h->nb_partial, 0));
+                    TRY(fetch(h, 1, tmp));
+                    rz = tmp[0];
                     HIPCHK(h, hipMemcpyAsync(p, z, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
                     restart = false;
                 }
@@ -929,20 +950,25 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     status = fail(AGCA_E_NUMERIC, "preconditioned residual is not positive");
                     break;
                 }
-                TRY(do_cube<double>(h, L, MODE_APPLY, p, nullptr, q, 0.0));
-                double pq = 0.0;
-                TRY(do_dot<double>(h, p, q, cnt, &pq));
+                // q = A p fused with p . q
+                int nbq = 0;
+                HIPCHK(h, launch_cube_dot(h->cfg.ncomp, level_op<double>(h, L), p, q, h->partial, &nbq,
+                                          h->st));
+                TRY(reduce_to(h, h->partial, nbq, 0));
+                TRY(fetch(h, 1, tmp));
+                const double pq = tmp[0];
                 if (!(pq > 0.0) || !std::isfinite(pq)) {
                     status = fail(AGCA_E_NUMERIC, "search direction has non-positive energy");
                     break;
                 }
                 const double alpha = rz / pq;
-                HIPCHK(h, launch_axpby<double>(cnt, alpha, p, 1.0, x, h->st));
-                if (flex)
-                    HIPCHK(h, hipMemcpyAsync(ro, r, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
-                HIPCHK(h, launch_axpby<double>(cnt, -alpha, q, 1.0, r, h->st));
+                // x += alpha p, r -= alpha q (keeping the old r for FCG), fused with r . r
+                HIPCHK(h, launch_cg_update(cnt, alpha, p, q, x, r, flex ? ro : nullptr, h->partial,
+                                           h->nb_partial, h->st));
+                TRY(reduce_to(h, h->partial, h->nb_partial, 0));
+                TRY(fetch(h, 1, tmp));
+                rr = tmp[0];
                 ++it;
-                TRY(do_dot<double>(h, r, r, cnt, &rr));
                 rel = rec_rel = std::sqrt(rr) / bn;
                 record(rel);
                 if (!std::isfinite(rel) || rel > 1e30) {
@@ -957,16 +983,13 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     continue;
                 }
                 TRY(precondition(h, r, z));
-                double rz_new = 0.0;
-                TRY(do_dot<double>(h, r, z, cnt, &rz_new));
-                double beta;
-                if (flex) {
-                    double zro = 0.0;
-                    TRY(do_dot<double>(h, z, ro, cnt, &zro));
-                    beta = (rz_new - zro) / rz;
-                } else {
-                    beta = rz_new / rz;
-                }
+                // z . r and, for FCG, z . r_old in one pass
+                HIPCHK(h, launch_dot2(cnt, z, r, flex ? ro : nullptr, h->partial, h->nb_partial, h->st));
+                TRY(reduce_to(h, h->partial, h->nb_partial, 0));
+                if (flex) TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, 1));
+                TRY(fetch(h, flex ? 2 : 1, tmp));
+                const double rz_new = tmp[0];
+                const double beta = flex ? (rz_new - tmp[1]) / rz : rz_new / rz;
                 rz = rz_new;
                 HIPCHK(h, launch_axpby<double>(cnt, 1.0, z, beta, p, h->st));
             }

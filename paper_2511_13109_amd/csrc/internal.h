@@ -25,12 +25,17 @@ struct LevelOp {
     const T* dinv = nullptr;       // inverse Jacobi diagonal, level vector (0 on the boundary)
 };
 
-enum CubeMode { MODE_APPLY = 0, MODE_RESIDUAL = 1, MODE_JACOBI = 2 };
+enum CubeMode { MODE_APPLY = 0, MODE_RESIDUAL = 1, MODE_JACOBI = 2, MODE_APPLY_DOT = 3 };
 
 // v = A u / r = b - A u / x_out = x + omega D^-1 (b - A x)   (one element-loop pass)
 template <typename T>
 hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,
                        T omega, hipStream_t st);
+// v = A u and per-workgroup partial sums of u . v (FP64 only); *nblocks receives the count
+hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u, double* out,
+                           double* partial, int* nblocks, hipStream_t st);
+// number of workgroups of the element loop on a level with n cells
+int cube_grid_blocks(int n);
 
 // transfers (Section 2.1)
 template <typename T>
@@ -49,6 +54,13 @@ hipError_t launch_dot_partial(const T* x, const T* y, int64_t n, double* partial
 hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t st);
 template <typename T>
 hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStream_t st);  // y = a x + b y
+// CG update: x += alpha p, r -= alpha q (ro = r before the update if ro != null), and
+// partial sums of r . r over nblocks workgroups
+hipError_t launch_cg_update(int64_t n, double alpha, const double* p, const double* q, double* x,
+                            double* r, double* ro, double* partial, int nblocks, hipStream_t st);
+// partial sums of z . r and z . ro (two arrays of nblocks)
+hipError_t launch_dot2(int64_t n, const double* z, const double* r, const double* ro,
+                       double* partial, int nblocks, hipStream_t st);
 hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_zero_boundary(int ncomp, int n, T* x, hipStream_t st);

@@ -137,9 +137,10 @@ __attribute__((amdgpu_waves_per_eu(CubeWaves<NC, T>::value > 0 ? CubeWaves<NC, T
 k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
        const T* __restrict__ u, const NT* __restrict__ nu, const int32_t* __restrict__ blk,
        const T* __restrict__ yblk, const T* __restrict__ b, const T* __restrict__ dinv,
-       T* __restrict__ out, const T scale, const T omega) {
+       T* __restrict__ out, const T scale, const T omega, double* __restrict__ partial) {
     __shared__ T ubuf[2][NC][TY + 1][TX + 1];
     __shared__ T ybuf[2][NC][2][TY][TX];
+    double dot_acc = 0.0;  // MODE_APPLY_DOT: this thread's share of u . (A u)
 
     int bx, by, bz;
     tile_of(gx, gy, gz, bx, by, bz);
@@ -198,7 +199,7 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     const bool col_ok = cx >= 0 && cx < n && cy >= 0 && cy < n;
     const bool writer = tx >= 1 && ty >= 1 && cx <= n && cy <= n;
     const bool xin = cx > 0 && cx < n && cy > 0 && cy < n;
-    constexpr bool NEEDS_B = MODE != MODE_APPLY;
+    constexpr bool NEEDS_B = MODE == MODE_RESIDUAL || MODE == MODE_JACOBI;
     // cell and node columns of this thread, clamped
     const int64_t cellcol = min(max(cx, 0), n - 1) + (int64_t)n * min(max(cy, 0), n - 1);
     const NT* pnu = nu + elem_slot(0, cellcol, cells);
@@ -333,6 +334,9 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
                     T o;
                     if constexpr (MODE == MODE_APPLY) {
                         o = av;
+                    } else if constexpr (MODE == MODE_APPLY_DOT) {
+                        o = av;
+                        if (interior) dot_acc += (double)Ulo[0][c] * (double)av;
                     } else if constexpr (MODE == MODE_RESIDUAL) {
                         o = bq[c] - av;
                     } else {
@@ -359,6 +363,19 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
                 bq[c] = bq_n[c];
                 dq[c] = dq_n[c];
             }
+        }
+    }
+    if constexpr (MODE == MODE_APPLY_DOT) {
+        // fixed-order workgroup reduction: wavefront shuffle, then the 4 wavefronts
+        __shared__ double red[NTHREADS / 64];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) dot_acc += __shfl_down(dot_acc, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = dot_acc;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < NTHREADS / 64; ++w) sum += red[w];
+            partial[blockIdx.x] = sum;
         }
     }
 }
@@ -418,7 +435,7 @@ int pick_zc(int n) {
 
 template <int NC, typename T, typename NT, int MODE, bool BLK>
 hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omega,
-                    hipStream_t st) {
+                    hipStream_t st, double* partial = nullptr, int* nblocks = nullptr) {
     const int n = op.n;
     const int zc = pick_zc(n);
     dim3 block(TX, TY, 1);
@@ -439,10 +456,11 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omeg
         const char* e = getenv("AGCA_CUBE_XCD");
         return e ? atoi(e) != 0 : true;
     }();
+    if (nblocks) *nblocks = gx * gy * gz;
     hipLaunchKernelGGL((k_cube<NC, T, NT, MODE, BLK>), grid, block, 0, st, n, zc, gx, gy,
                        xcd_map ? gz : -gz, u,
                        reinterpret_cast<const NT*>(op.nu), op.blk, op.yblk, b, op.dinv, out,
-                       scale, omega);
+                       scale, omega, partial);
     return hipGetLastError();
 }
 
@@ -469,6 +487,27 @@ hipError_t dispatch_nu(const LevelOp<T>& op, const T* u, const T* b, T* out, T o
 }
 
 }  // namespace
+
+int cube_grid_blocks(int n) {
+    const int zc = pick_zc(n);
+    return ((n + 1 + TX - 2) / (TX - 1)) * ((n + 1 + TY - 2) / (TY - 1)) * ((n + 1 + zc - 1) / zc);
+}
+
+hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u, double* out,
+                           double* partial, int* nblocks, hipStream_t st) {
+    if (!op.nu || !u || !out || !partial || !nblocks || op.n < 2 || op.nu_kind != AGCA_F64)
+        return hipErrorInvalidValue;
+    if (op.blk && (!op.blocks || !op.ids || !op.yblk || op.nflag <= 0)) return hipErrorInvalidValue;
+    if (ncomp == 1)
+        return op.blk ? launch_t<1, double, double, MODE_APPLY_DOT, true>(op, u, nullptr, out, 0.0, st,
+                                                                           partial, nblocks)
+                      : launch_t<1, double, double, MODE_APPLY_DOT, false>(op, u, nullptr, out, 0.0, st,
+                                                                            partial, nblocks);
+    return op.blk ? launch_t<3, double, double, MODE_APPLY_DOT, true>(op, u, nullptr, out, 0.0, st,
+                                                                       partial, nblocks)
+                  : launch_t<3, double, double, MODE_APPLY_DOT, false>(op, u, nullptr, out, 0.0, st,
+                                                                        partial, nblocks);
+}
 
 template <typename T>
 hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,

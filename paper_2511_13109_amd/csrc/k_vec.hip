@@ -133,6 +133,50 @@ k_axpby(int64_t n, double a, const T* __restrict__ x, double b, T* __restrict__ 
         y[i] = ta * x[i] + tb * y[i];
 }
 
+__device__ __forceinline__ void block_sum_store(double v, double* __restrict__ out) {
+    __shared__ double red[NT / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        *out = s;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(NT)
+k_cg_update(int64_t n, double alpha, const double* __restrict__ p, const double* __restrict__ q,
+            double* __restrict__ x, double* __restrict__ r, double* __restrict__ ro,
+            double* __restrict__ partial) {
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
+        x[i] += alpha * p[i];
+        const double r0 = r[i];
+        if (ro) ro[i] = r0;
+        const double r1 = r0 - alpha * q[i];
+        r[i] = r1;
+        acc += r1 * r1;
+    }
+    block_sum_store(acc, partial + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(NT)
+k_dot2(int64_t n, const double* __restrict__ z, const double* __restrict__ r,
+       const double* __restrict__ ro, double* __restrict__ partial) {
+    double a = 0.0, b = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
+        const double zi = z[i];
+        a += zi * r[i];
+        if (ro) b += zi * ro[i];
+    }
+    block_sum_store(a, partial + blockIdx.x);
+    block_sum_store(b, partial + gridDim.x + blockIdx.x);
+}
+
 // FP64 -> BF16 with a single round-to-nearest-even: round to FP32 with
 // "round to odd" (truncate, then set the last bit if inexact), which keeps the
 // information a second rounding needs, then round that FP32 value to BF16.
@@ -312,6 +356,18 @@ hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStre
     if (n <= 0) return hipSuccess;
     if (!x || !y) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_axpby<T>, dim3(grid_stride(n)), dim3(NT), 0, st, n, a, x, b, y);
+    return hipGetLastError();
+}
+hipError_t launch_cg_update(int64_t n, double alpha, const double* p, const double* q, double* x,
+                            double* r, double* ro, double* partial, int nblocks, hipStream_t st) {
+    if (!p || !q || !x || !r || !partial || nblocks <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cg_update, dim3(nblocks), dim3(NT), 0, st, n, alpha, p, q, x, r, ro, partial);
+    return hipGetLastError();
+}
+hipError_t launch_dot2(int64_t n, const double* z, const double* r, const double* ro,
+                       double* partial, int nblocks, hipStream_t st) {
+    if (!z || !r || !partial || nblocks <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dot2, dim3(nblocks), dim3(NT), 0, st, n, z, r, ro, partial);
     return hipGetLastError();
 }
 hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st) {

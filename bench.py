@@ -9,7 +9,8 @@ f = (0, 0, -xi); synthetic inputs from the seeded generators in workloads/.
 One step = one pass over the whole hot path for the resident coefficient:
   1. rebuild both hierarchies from the resident coefficients (flags, Galerkin
      blocks of flagged elements, diagonals, coarsest inverse),
-  2. a batch of fine-grid operator applications v = A_L u (FP64),
+  2. a batch of fine-grid operator applications v = A_L u (FP64), each timed
+     with HIP events after a 512 MiB read that evicts the Infinity Cache,
   3. an FP64 solve to 1e-8 with the FP64 AGCA V-cycle (PCG),
   4. a solve to 1e-8 with the FP32 V-cycle and BF16 finest coefficient inside
      FP64 flexible CG.
@@ -24,6 +25,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -35,12 +37,145 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GDoF/s fine-grid apply; time-to-1e-8 residual, FP32-MG vs FP64-MG"
+PROFILE = os.path.join(ROOT, "profiles", "fine_apply_sinker129.md")
+# sources whose text determines the fine-apply kernel; counter traffic is only
+# reported while their hash equals the one recorded next to the counters
+KERNEL_SOURCES = ["paper_2511_13109_amd/csrc/k_apply.hip", "paper_2511_13109_amd/csrc/kuhn.h",
+                  "paper_2511_13109_amd/csrc/cube_math.h"]
+FINE_APPLY_KERNEL = "k_cube<3, double, double, 0, false>"
 
 
 def apply_bytes(L: int, ncomp: int, vec_bytes: int = 8, nu_bytes: int = 8) -> int:
     """Algorithmic bytes of one fine apply: read u, write v (all (n+1)^3 slots), read nu."""
     n = 2 ** (L + 1)
     return 2 * ncomp * vec_bytes * (n + 1) ** 3 + nu_bytes * 6 * n ** 3
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per fine-apply launch from the committed counter summary, or None when
+    the kernel sources changed after the counters were taken."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    mt = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    mh = re.search(r"^kernel_source_sha256_16: ([0-9a-f]+)$", text, re.M)
+    if not mt or not mh or mh.group(1) != kernel_hash():
+        return None
+    return int(mt.group(1))
+
+
+def _short(name: str) -> str:
+    name = name.replace("void ", "").replace("agca::(anonymous namespace)::", "")
+    depth, out = 0, []
+    for ch in name:                     # drop the argument list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out)
+
+
+def summarize_profile(d: str, command_prefix: str) -> str:
+    """Markdown summary of a profiling directory written by the three rocprofv3 runs
+    named in the text (kernel statistics, FETCH_SIZE pass, WRITE_SIZE pass)."""
+    import csv
+    lines = []
+    stats = list(csv.DictReader(open(os.path.join(d, "stats", "bench_kernel_stats.csv"))))
+    total = sum(float(r["TotalDurationNs"]) for r in stats)
+    bench = json.loads(open(os.path.join(d, "bench.json")).read())
+    L = bench["config"]["levels"] - 1
+    bytes_launch = apply_bytes(L, 3)
+    lines += ["# Fine-grid apply and solve kernels, vector viscous block on 129^3 nodes (sinker workload)",
+              "",
+              "All commands run from the repository root after `cd /tmp && export TMPDIR=/tmp`; "
+              "this file is written by `python3 bench.py --summarize-profile <dir>`.",
+              "",
+              "## Kernel statistics of one bench step",
+              "",
+              "Hierarchy rebuild (twice), 20 FP64 fine applies, FP64-MG PCG and FP32-MG FCG to 1e-8.",
+              "",
+              f"    {command_prefix}rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/stats "
+              "-o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+              "",
+              f"Total kernel time {total / 1e6:.1f} ms.  k_cube template arguments: <components, "
+              "vector type, coefficient type, mode (0 apply, 1 residual, 2 Jacobi, 3 apply with dot), "
+              "stored blocks>.",
+              "",
+              "| kernel | calls | avg us | total ms | % |",
+              "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+
+    def counter(kind):
+        rows = list(csv.DictReader(open(os.path.join(d, kind, "run_counter_collection.csv"))))
+        app = [float(r["Counter_Value"]) for r in rows if _short(r["Kernel_Name"]) == FINE_APPLY_KERNEL]
+        cp = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+              and int(r["Grid_Size"]) >= 65536]
+        cpd = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows
+               if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 65536]
+        return app[1:] or app, cp, cpd
+    fa, fc, cpd = counter("fetch")
+    wa, wc, _ = counter("write")
+    copy_kib = 256 * 1024
+    ff = copy_kib / float(np.median(fc))
+    fw = copy_kib / float(np.median(wc))
+    read_b = float(np.median(fa)) * ff * 1024
+    write_b = float(np.median(wa)) * fw * 1024
+    traffic = int(round(read_b + write_b))
+    copy_rate = 2 * copy_kib * 1024 / (float(np.median(cpd)) * 1e-9) / 1e9
+    ro = bench["roofline"]
+    fine = [r for r in stats if _short(r["Name"]) == FINE_APPLY_KERNEL]
+    if fine:
+        lines += ["", f"Fine apply `{FINE_APPLY_KERNEL}`: {fine[0]['Calls']} calls, rocprofv3 average "
+                      f"{float(fine[0]['AverageNs']) / 1e3:.2f} us (HIP events in the bench line: "
+                      f"{ro['avg_launch_us']} us)."]
+    lines += ["",
+              f"## HBM traffic of the FP64 fine-grid apply (`{FINE_APPLY_KERNEL}`), 129^3 nodes",
+              "",
+              "Two counter passes, each in a run of its own; the driver builds the hierarchy, runs 5 "
+              "FP64 fine applies, then copies a 256 MiB tensor three times to calibrate the counters:",
+              "",
+              f"    {command_prefix}rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run "
+              "-- python3 bench.py --profile-apply",
+              f"    {command_prefix}rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run "
+              "-- python3 bench.py --profile-apply",
+              "",
+              f"* calibration (256 MiB copy): FETCH_SIZE reads {np.median(fc):.0f} KiB -> factor {ff:.3f}; "
+              f"WRITE_SIZE reads {np.median(wc):.0f} KiB -> factor {fw:.3f}",
+              f"* copy kernel rate in the counter run: {copy_rate:.0f} GB/s (read + write)",
+              f"* apply (median of the warm dispatches): FETCH_SIZE {np.median(fa):.0f} KiB, "
+              f"WRITE_SIZE {np.median(wa):.0f} KiB",
+              f"* scaled traffic per launch: read {read_b / 1e6:.1f} MB + write {write_b / 1e6:.1f} MB "
+              f"= {traffic / 1e6:.1f} MB",
+              f"* algorithmic bytes per launch: {bytes_launch / 1e6:.1f} MB (u and v: 3 x 8 B x 129^3 "
+              f"each; nu: 8 B x 6 x 128^3) -> traffic / algorithmic = {traffic / bytes_launch:.3f}",
+              "",
+              "## Bench line of the same tree",
+              "",
+              f"    {command_prefix}python3 bench.py --steps 3 --warmup 1",
+              "",
+              f"* fine apply: {ro['avg_launch_us']} us per launch (HIP events), {ro['achieved']} GB/s "
+              f"= {ro['frac']:.3f} of 8000 GB/s; {bench['value']} GDoF/s",
+              f"* time to 1e-8: FP64-MG PCG {bench['time_to_1e-8_s']['fp64_mg_pcg']} s "
+              f"({bench['iterations']['fp64_mg_pcg']} it), FP32-MG FCG "
+              f"{bench['time_to_1e-8_s']['fp32_mg_fcg']} s ({bench['iterations']['fp32_mg_fcg']} it)",
+              "",
+              f"traffic_bytes_per_launch: {traffic}",
+              f"kernel_source_sha256_16: {ro.get('kernel_source_sha256_16', '(not recorded)')}",
+              ""]
+    return "\n".join(lines)
 
 
 def make_inputs(name: str):
@@ -116,7 +251,12 @@ def main():
     ap.add_argument("--mg-nu", default="bf16", choices=["bf16", "f32"])
     ap.add_argument("--profile-apply", action="store_true",
                     help="only run 5 FP64 fine applies and a 256 MiB copy (counter passes)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="print the markdown summary of a profiling directory and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        print(summarize_profile(args.summarize_profile, ""))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the AGCA path here is built and timed on a single "
@@ -144,7 +284,12 @@ def main():
     free_dofs = nc * (n - 1) ** 3
     u = torch.randn(nc * N, generator=gen, dtype=torch.float64).to(dev)
     v = torch.empty_like(u)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    # each timed apply is preceded by a read of 512 MiB, which evicts the 256 MB
+    # Infinity Cache, so the apply streams its operands from HBM
+    flush = torch.ones(512 * 1024 * 1024 // 8, dtype=torch.float64, device=dev)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.applies)]
 
     rec = {"apply_ms": [], "setup_s": [], "t64": [], "t32": [], "it64": [], "it32": [],
            "res64": [], "res32": []}
@@ -154,15 +299,16 @@ def main():
         H64.set_nu(nus[L], nus[:L])
         H32.set_nu(nus[L], nus[:L])
         t_setup = time.perf_counter() - t0
-        ev[0].record()
-        for _ in range(args.applies):
+        for e0, e1 in ev:
+            sink.add_(flush.sum())
+            e0.record()
             H64.apply(L, u, v)
-        ev[1].record()
+            e1.record()
         x64, s64 = H64.solve(b, solver="pcg", tol=w.tol, max_iter=4000, raise_on_noconv=False)
         x32, s32 = H32.solve(b, solver="fcg", tol=w.tol, max_iter=4000, raise_on_noconv=False)
         if record:
             torch.cuda.synchronize()
-            rec["apply_ms"].append(ev[0].elapsed_time(ev[1]) / args.applies)
+            rec["apply_ms"].append(float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev])))
             rec["setup_s"].append(t_setup)
             rec["t64"].append(s64["seconds"])
             rec["t32"].append(s32["seconds"])
@@ -211,9 +357,10 @@ def main():
         "setup_s": round(float(np.median(rec["setup_s"])), 5),
         "flagged_per_level": [H64.query(l)["flagged"] for l in range(L)],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
                      "kernel": "k_cube<3,double,double,APPLY> (fine-grid apply)",
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(apply_s * 1e6, 2)},
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(apply_s * 1e6, 2),
+                     "kernel_source_sha256_16": kernel_hash()},
         "input_generation_s": round(t_gen, 2),
     }
     if not args.no_cpu_baseline:

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -43,6 +44,8 @@ struct Level {
     double* diag = nullptr;
     double* dinv64 = nullptr;
     float* dinv32 = nullptr;
+    double* sten64 = nullptr;    // assembled 15-point stencil (small coarse levels only)
+    float* sten32 = nullptr;
     void* b = nullptr;  // V-cycle work vectors, mg precision
     void* x = nullptr;
     void* t = nullptr;
@@ -125,6 +128,17 @@ int32_t alloc_t(agca_hier* h, P** p, size_t count, int64_t* lb = nullptr) {
     } while (0)
 
 bool mg32(const agca_hier* h) { return h->cfg.mg_dtype == AGCA_F32; }
+
+// Coarse levels with at most this many cells per axis keep their operator as an
+// assembled stencil (latency-bound sizes; 33^3 nodes x 135 FP64 values = 39 MB).
+// AGCA_STENCIL_MAX_N overrides it (0 turns the stencils off).
+int stencil_max_n() {
+    static const int v = [] {
+        const char* e = getenv("AGCA_STENCIL_MAX_N");
+        return e ? atoi(e) : 32;
+    }();
+    return v;
+}
 size_t mg_size(const agca_hier* h) { return mg32(h) ? sizeof(float) : sizeof(double); }
 
 template <typename T>
@@ -143,6 +157,7 @@ LevelOp<double> level_op<double>(const agca_hier* h, int l) {
     op.blocks = L.blocks64;
     op.yblk = L.yblk64;
     op.dinv = L.dinv64;
+    op.sten = L.sten64;
     return op;
 }
 template <>
@@ -163,6 +178,7 @@ LevelOp<float> level_op<float>(const agca_hier* h, int l) {
     op.blocks = L.blocks32;
     op.yblk = L.yblk32;
     op.dinv = L.dinv32;
+    op.sten = L.sten32;
     return op;
 }
 
@@ -183,10 +199,27 @@ int32_t check_dtype(const agca_hier* h, int dtype, bool need_mg) {
 // ---------------------------------------------------------------------------
 // level operations (templated on the vector precision)
 // ---------------------------------------------------------------------------
+// one pass of the level operator: the assembled stencil where the level has one,
+// the element loop otherwise
 template <typename T>
-int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, T omega) {
-    HIPCHK(h, launch_cube<T>(h->cfg.ncomp, mode, level_op<T>(h, l), u, b, out, omega, h->st));
+int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, T omega,
+                const T* ec = nullptr) {
+    const LevelOp<T> op = level_op<T>(h, l);
+    if (op.sten)
+        HIPCHK(h, launch_stencil<T>(h->cfg.ncomp, mode, op.n, op.sten, u, b, op.dinv, ec, out, omega,
+                                    h->st));
+    else
+        HIPCHK(h, launch_cube<T>(h->cfg.ncomp, mode, op, u, b, out, omega, h->st, ec));
     return AGCA_OK;
+}
+
+// whether the fused first-sweep / prolongation sweeps are available on level l: the
+// element loop forms stored-block products from u before its pass, so levels that
+// use it together with stored blocks take the unfused steps
+template <typename T>
+bool fusable(const agca_hier* h, int l) {
+    const LevelOp<T> op = level_op<T>(h, l);
+    return op.sten != nullptr || op.blk == nullptr;
 }
 
 template <typename T>
@@ -206,10 +239,13 @@ int32_t do_smooth(agca_hier* h, int l, int sweeps, double omega, const T* b, T* 
     return AGCA_OK;
 }
 
-// One V(pre,post)-cycle from a zero initial guess.  The first pre-smoothing sweep
-// from zero is the elementwise x = omega D^-1 b; the remaining sweeps ping-pong
-// between the level's two buffers, and on the finest level the starting buffer
-// is chosen so that the last sweep lands in the caller's x (no copies).
+// One V(pre,post)-cycle from a zero initial guess.  The first two pre-smoothing
+// sweeps from zero are one pass (the first, x = omega D^-1 b, is formed while
+// loading), and the coarse-grid correction x += P e_c is formed while loading the
+// first post-smoothing sweep; levels whose element loop uses stored blocks take
+// these steps separately.  The remaining sweeps ping-pong between the level's two
+// buffers, and on the finest level the starting buffer is chosen so that the last
+// sweep lands in the caller's x (no copies).
 template <typename T>
 int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
     const int L = h->cfg.L, nc = h->cfg.ncomp;
@@ -221,19 +257,23 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
         const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
         T* home = (l == L) ? xL : static_cast<T*>(h->lv[l].x);
         T* other = static_cast<T*>(h->lv[l].t);
-        // Jacobi launches that will write this level's iterate after the first sweep
-        const int launches = (pre > 0 ? pre - 1 : 0) + post;
+        const bool fuse = fusable<T>(h, l);
+        // out-of-place launches that write this level's iterate after its first producer
+        // (pre-sweeps after the first pass, then every post-sweep)
+        const int first = (pre >= 2 && fuse) ? 2 : (pre > 0 ? 1 : 0);
+        const int launches = (pre - first) + post;
         T* cur = (launches % 2 == 0) ? home : other;
         T* alt = (cur == home) ? other : home;
         const LevelOp<T> op = level_op<T>(h, l);
-        if (pre > 0) {
+        if (first == 2)
+            TRY(do_cube<T>(h, l, MODE_JACOBI0, nullptr, bl, cur, om));
+        else if (first == 1)
             HIPCHK(h, launch_first_sweep<T>(cnt, om, op.dinv, bl, cur, h->st));
-            for (int i = 1; i < pre; ++i) {
-                TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, om));
-                std::swap(cur, alt);
-            }
-        } else {
+        else
             HIPCHK(h, launch_fill<T>(cnt, T(0), cur, h->st));
+        for (int i = first; i < pre; ++i) {
+            TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, om));
+            std::swap(cur, alt);
         }
         xcur[l] = cur;
         xalt[l] = alt;
@@ -248,8 +288,15 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
         const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
         T* cur = xcur[l];
         T* alt = xalt[l];
-        HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, xcur[l - 1], cur, h->st));
-        for (int i = 0; i < post; ++i) {
+        int i = 0;
+        if (post > 0 && fusable<T>(h, l)) {
+            TRY(do_cube<T>(h, l, MODE_JACOBI_P, cur, bl, alt, om, xcur[l - 1]));
+            std::swap(cur, alt);
+            i = 1;
+        } else {
+            HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, xcur[l - 1], cur, h->st));
+        }
+        for (; i < post; ++i) {
             TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, om));
             std::swap(cur, alt);
         }
@@ -549,6 +596,13 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
         } else {
             HIPCHK(h, launch_invert_diag<double>(cnt, lv.diag, lv.dinv64, h->st));
         }
+        if (lv.sten64) {
+            HIPCHK(h, launch_stencil_assemble(nc, lv.n, lv.nu64, scale, lv.nflag > 0 ? lv.blk_soa : nullptr,
+                                              lv.blocks64, lv.sten64, h->st));
+            if (lv.sten32)
+                HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, lv.sten64, lv.sten32,
+                                      (int64_t)nc * nc * 15 * lv.nodes, h->st));
+        }
     }
     TRY(build_coarsest(h));
     HIPCHK(h, hipStreamSynchronize(h->st));
@@ -655,6 +709,10 @@ int32_t agca_create(const agca_config* cfg, const double* nu_fine, const double*
         if (rc == AGCA_OK) rc = alloc_t(h, &lv.diag, nv, &lv.bytes);
         if (rc == AGCA_OK && mg32(h)) rc = alloc_t(h, &lv.dinv32, nv, &lv.bytes);
         if (rc == AGCA_OK && !mg32(h)) rc = alloc_t(h, &lv.dinv64, nv, &lv.bytes);
+        if (rc == AGCA_OK && l >= 1 && l < L && lv.n <= stencil_max_n()) {
+            rc = alloc_t(h, &lv.sten64, (size_t)nv * nc * 15, &lv.bytes);
+            if (rc == AGCA_OK && mg32(h)) rc = alloc_t(h, &lv.sten32, (size_t)nv * nc * 15, &lv.bytes);
+        }
         if (rc == AGCA_OK && l < L) rc = dev_alloc(h, &lv.b, nv * ts, &lv.bytes);
         if (rc == AGCA_OK && l < L) rc = dev_alloc(h, &lv.x, nv * ts, &lv.bytes);
         if (rc == AGCA_OK && l > 0) rc = dev_alloc(h, &lv.t, nv * ts, &lv.bytes);

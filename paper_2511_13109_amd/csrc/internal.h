@@ -23,19 +23,35 @@ struct LevelOp {
     const T* blocks = nullptr;     // flagged x (4 ncomp)^2 entries
     T* yblk = nullptr;             // scratch: flagged x 4 ncomp products B u_e
     const T* dinv = nullptr;       // inverse Jacobi diagonal, level vector (0 on the boundary)
+    const T* sten = nullptr;       // assembled stencil (k_stencil.hip layout) or null
 };
 
-enum CubeMode { MODE_APPLY = 0, MODE_RESIDUAL = 1, MODE_JACOBI = 2, MODE_APPLY_DOT = 3 };
+// MODE_JACOBI0: two sweeps from a zero guess, x_out = x1 + omega D^-1 (b - A x1) with
+//               x1 = omega D^-1 b formed on the fly (u unused)
+// MODE_JACOBI_P: one sweep from x + P ec (ec on the level with n/2 cells), the
+//               interpolated correction formed on the fly
+enum CubeMode { MODE_APPLY = 0, MODE_RESIDUAL = 1, MODE_JACOBI = 2, MODE_APPLY_DOT = 3,
+                MODE_JACOBI0 = 4, MODE_JACOBI_P = 5 };
 
 // v = A u / r = b - A u / x_out = x + omega D^-1 (b - A x)   (one element-loop pass)
 template <typename T>
 hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,
-                       T omega, hipStream_t st);
+                       T omega, hipStream_t st, const T* ec = nullptr);
 // v = A u and per-workgroup partial sums of u . v (FP64 only); *nblocks receives the count
 hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u, double* out,
                            double* partial, int* nblocks, hipStream_t st);
 // number of workgroups of the element loop on a level with n cells
 int cube_grid_blocks(int n);
+
+// assembled 15-point stencil of a coarse level (FP64): DCA on unflagged simplices,
+// stored blocks (blk in the internal element layout) on flagged ones
+hipError_t launch_stencil_assemble(int ncomp, int n, const double* nu, double scale,
+                                   const int32_t* blk, const double* blocks, double* S,
+                                   hipStream_t st);
+// apply / residual / Jacobi modes (CubeMode) with an assembled stencil
+template <typename T>
+hipError_t launch_stencil(int ncomp, int mode, int n, const T* S, const T* u, const T* b,
+                          const T* dinv, const T* ec, T* out, T omega, hipStream_t st);
 
 // transfers (Section 2.1)
 template <typename T>

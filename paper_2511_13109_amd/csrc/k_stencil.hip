@@ -1,0 +1,195 @@
+// Assembled operators of the small coarse levels.
+//
+// On a level with few nodes the element loop is bound by latency, not by
+// bandwidth: a z march of a few steps per workgroup plus a separate pass for the
+// stored-block products.  There the level operator of eq. (2.9) (DCA on unflagged
+// simplices, the stored Galerkin block on flagged ones) is assembled once per
+// coefficient into its 15-point node stencil, and apply, residual and the Jacobi
+// sweeps become one fully parallel gather per (node, component).  The stencil
+// holds exactly the sum of the element matrices, so the operator is unchanged up
+// to the order of the additions.
+//
+// Layout: S[((c * ncomp + d) * 15 + k) * N + p] couples component c of node p to
+// component d of its neighbour k (kuhn.h nbr_mask / nbr_sign), N = (n+1)^3 nodes;
+// consecutive nodes are consecutive in memory, so every load is coalesced.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "kuhn.h"
+
+namespace agca {
+namespace {
+
+constexpr int NT = 256;
+constexpr int NNB = 15;
+
+// One thread per (node, component pair c, d = blockIdx.y / NC, blockIdx.y % NC);
+// rows of boundary nodes stay zero.  Loops over the 8 cells around the node and the
+// simplices of each cell that contain it; everything that decides a neighbour index
+// is a compile-time constant after unrolling.
+template <int NC>
+__global__ void __launch_bounds__(NT)
+k_stencil_assemble(int n, const double* __restrict__ nu, double scale, const int32_t* __restrict__ blk,
+                   const double* __restrict__ blocks, double* __restrict__ S) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    const int c = blockIdx.y / NC, d = blockIdx.y % NC;
+    if (p >= N) return;
+    const int x = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    const bool interior = x > 0 && y > 0 && z > 0 && x < n && y < n && z < n;
+    constexpr int M = 4 * NC;
+    const int64_t cells = (int64_t)n * n * n;
+    double acc[NNB];
+#pragma unroll
+    for (int k = 0; k < NNB; ++k) acc[k] = 0.0;
+    if (interior) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            // the cell that has this node as its corner k
+            const int cx = x - (k & 1), cy = y - ((k >> 1) & 1), cz = z - ((k >> 2) & 1);
+            const int64_t cell = cx + (int64_t)n * (cy + (int64_t)n * cz);
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    if (path_corner(s, a) != k) continue;
+                    const int64_t slot = elem_slot(s, cell, cells);
+                    const int32_t bi = blk ? blk[slot] : -1;
+                    if (bi >= 0) {
+                        const double* row = blocks + (int64_t)bi * M * M + (4 * c + a) * M + 4 * d;
+#pragma unroll
+                        for (int bv = 0; bv < 4; ++bv) acc[nbr_of(s, a, bv)] += row[bv];
+                    } else {
+                        const double w = nu[slot] * scale;
+#pragma unroll
+                        for (int bv = 0; bv < 4; ++bv) {
+                            // the unit entry depends on the runtime component pair
+                            const int e = NC == 1 ? path_lap(a, bv) : unit_entry(s, c, a, d, bv);
+                            acc[nbr_of(s, a, bv)] += w * (double)e;
+                        }
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NNB; ++k) S[((int64_t)(c * NC + d) * NNB + k) * N + p] = acc[k];
+}
+
+// One thread per (node, component c = blockIdx.y).
+template <int NC, typename T, int MODE>
+__global__ void __launch_bounds__(NT)
+k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T* __restrict__ b,
+                const T* __restrict__ dinv, const T* __restrict__ ec, T* __restrict__ out, T omega) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    const int c = blockIdx.y;
+    if (p >= N) return;
+    const int x = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    const bool interior = x > 0 && y > 0 && z > 0 && x < n && y < n && z < n;
+    if (!interior) {
+        out[c * N + p] = T(0);
+        return;
+    }
+    const int64_t nc1 = n / 2 + 1, Nc = nc1 * nc1 * nc1;
+    T acc = T(0), self = T(0);
+#pragma unroll
+    for (int k = 0; k < NNB; ++k) {
+        const int m = nbr_mask(k), sg = nbr_sign(k);
+        const int qx = x + sg * (m & 1), qy = y + sg * ((m >> 1) & 1), qz = z + sg * (m >> 2);
+        const bool qin = qx > 0 && qy > 0 && qz > 0 && qx < n && qy < n && qz < n;
+        const int64_t q = qx + n1 * (qy + n1 * (int64_t)qz);
+        int64_t lo = 0, hi = 0;
+        bool odd = false;
+        if constexpr (MODE == MODE_JACOBI_P) {
+            const int dx = qx & 1, dy = qy & 1, dz = qz & 1;
+            lo = ((qx - dx) >> 1) + nc1 * (((qy - dy) >> 1) + nc1 * (int64_t)((qz - dz) >> 1));
+            hi = ((qx + dx) >> 1) + nc1 * (((qy + dy) >> 1) + nc1 * (int64_t)((qz + dz) >> 1));
+            odd = (dx | dy | dz) != 0;
+        }
+#pragma unroll
+        for (int d = 0; d < NC; ++d) {
+            const int64_t i = d * N + q;
+            T v;
+            if constexpr (MODE == MODE_JACOBI0) {
+                v = omega * dinv[i] * b[i];
+            } else if constexpr (MODE == MODE_JACOBI_P) {
+                const T* e = ec + d * Nc;
+                const T el = e[lo], eh = e[hi];
+                v = u[i] + (odd ? T(0.5) * (el + eh) : el);
+            } else {
+                v = u[i];
+            }
+            v = qin ? v : T(0);
+            if (k == 0 && d == c) self = v;
+            acc += S[((int64_t)(c * NC + d) * NNB + k) * N + p] * v;
+        }
+    }
+    const int64_t o = c * N + p;
+    if constexpr (MODE == MODE_APPLY) {
+        out[o] = acc;
+    } else if constexpr (MODE == MODE_RESIDUAL) {
+        out[o] = b[o] - acc;
+    } else {
+        out[o] = self + omega * dinv[o] * (b[o] - acc);
+    }
+}
+
+template <int NC, typename T, int MODE>
+hipError_t launch_mode(int n, const T* S, const T* u, const T* b, const T* dinv, const T* ec, T* out,
+                       T omega, hipStream_t st) {
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    hipLaunchKernelGGL((k_stencil_apply<NC, T, MODE>), dim3((unsigned)((N + NT - 1) / NT), NC),
+                       dim3(NT), 0, st, n, S, u, b, dinv, ec, out, omega);
+    return hipGetLastError();
+}
+
+template <int NC, typename T>
+hipError_t launch_nc(int mode, int n, const T* S, const T* u, const T* b, const T* dinv,
+                     const T* ec, T* out, T omega, hipStream_t st) {
+    switch (mode) {
+        case MODE_APPLY: return launch_mode<NC, T, MODE_APPLY>(n, S, u, b, dinv, ec, out, omega, st);
+        case MODE_RESIDUAL:
+            return launch_mode<NC, T, MODE_RESIDUAL>(n, S, u, b, dinv, ec, out, omega, st);
+        case MODE_JACOBI: return launch_mode<NC, T, MODE_JACOBI>(n, S, u, b, dinv, ec, out, omega, st);
+        case MODE_JACOBI0: return launch_mode<NC, T, MODE_JACOBI0>(n, S, u, b, dinv, ec, out, omega, st);
+        case MODE_JACOBI_P:
+            return launch_mode<NC, T, MODE_JACOBI_P>(n, S, u, b, dinv, ec, out, omega, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_stencil_assemble(int ncomp, int n, const double* nu, double scale,
+                                   const int32_t* blk, const double* blocks, double* S,
+                                   hipStream_t st) {
+    if (!nu || !S || n < 2 || (blk && !blocks)) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    const dim3 grid((unsigned)((N + NT - 1) / NT), ncomp * ncomp);
+    if (ncomp == 1)
+        hipLaunchKernelGGL(k_stencil_assemble<1>, grid, dim3(NT), 0, st, n, nu, scale, blk, blocks, S);
+    else
+        hipLaunchKernelGGL(k_stencil_assemble<3>, grid, dim3(NT), 0, st, n, nu, scale, blk, blocks, S);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stencil(int ncomp, int mode, int n, const T* S, const T* u, const T* b,
+                          const T* dinv, const T* ec, T* out, T omega, hipStream_t st) {
+    if (!S || !out || n < 2) return hipErrorInvalidValue;
+    if (mode != MODE_JACOBI0 && !u) return hipErrorInvalidValue;
+    if (mode != MODE_APPLY && !b) return hipErrorInvalidValue;
+    if ((mode == MODE_JACOBI || mode == MODE_JACOBI0 || mode == MODE_JACOBI_P) && !dinv)
+        return hipErrorInvalidValue;
+    if (mode == MODE_JACOBI_P && (!ec || n < 4)) return hipErrorInvalidValue;
+    return ncomp == 1 ? launch_nc<1, T>(mode, n, S, u, b, dinv, ec, out, omega, st)
+                      : launch_nc<3, T>(mode, n, S, u, b, dinv, ec, out, omega, st);
+}
+
+template hipError_t launch_stencil<double>(int, int, int, const double*, const double*, const double*,
+                                           const double*, const double*, double*, double, hipStream_t);
+template hipError_t launch_stencil<float>(int, int, int, const float*, const float*, const float*,
+                                          const float*, const float*, float*, float, hipStream_t);
+
+}  // namespace agca

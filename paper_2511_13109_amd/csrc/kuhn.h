@@ -115,6 +115,19 @@ AGCA_HDC constexpr int kP2(int k, int a, int i) {
     return (tab[k][a][0] == i) + (tab[k][a][1] == i);
 }
 
+// The 15 nodes coupled to a node by the simplices around it: the node itself and
+// the offsets +m and -m for the 7 non-zero cell-corner masks m (x=1, y=2, z=4).
+// Neighbour index 0 is the node, m is +m, 7 + m is -m.
+AGCA_HDC constexpr int nbr_mask(int k) { return k == 0 ? 0 : (k <= 7 ? k : k - 7); }
+AGCA_HDC constexpr int nbr_sign(int k) { return k > 7 ? -1 : 1; }
+// neighbour index of path vertex b seen from path vertex a of one simplex: the path
+// corners are nested bit sets, so their difference is +-(one corner mask)
+AGCA_HDC constexpr int nbr_of(int s, int a, int b) {
+    return a == b ? 0
+         : b > a ? (path_corner(s, b) ^ path_corner(s, a))
+                 : 7 + (path_corner(s, a) ^ path_corner(s, b));
+}
+
 // canonical ids
 AGCA_HDC inline int64_t node_id(int64_t n, int64_t x, int64_t y, int64_t z) {
     return x + (n + 1) * (y + (n + 1) * z);

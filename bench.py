@@ -179,7 +179,7 @@ def summarize_profile(d: str, command_prefix: str) -> str:
 
 
 def make_inputs(name: str):
-    from paper_2511_13109_amd.grid import element_centroids
+    from workloads.lattice import element_centroids
     from workloads import workload
     w = workload(name)
     field = w.make_field()

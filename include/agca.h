@@ -117,6 +117,13 @@ int32_t agca_destroy(agca_hier* h);
 /* Replace the coefficients and rebuild flags, blocks and diagonals. */
 int32_t agca_set_nu(agca_hier* h, const double* nu_fine, const double* const* nu_coarse);
 
+/* agca_set_nu with the finest coefficient given as log nu (device, 6 n_L^3 doubles in
+ * element-id order, exponentiated on the device); nu_coarse as in agca_create.  This
+ * is the parameterisation of the adjoint gradient (agca_grad_log_nu): the gradient is
+ * taken with respect to these values.  Errors as agca_set_nu (AGCA_E_INVALID when
+ * exp(log nu) is not finite and positive). */
+int32_t agca_set_log_nu(agca_hier* h, const double* log_nu_fine, const double* const* nu_coarse);
+
 int32_t agca_query(const agca_hier* h, int32_t level, agca_level_info* out);
 
 /* Sorted ids of the flagged elements of a coarse level (host buffer of cap

@@ -18,4 +18,7 @@ def __getattr__(name):
     if name == "autograd":
         from . import autograd
         return autograd
+    if name == "AGCASolve":
+        from .autograd import AGCASolve
+        return AGCASolve
     raise AttributeError(name)

@@ -52,6 +52,7 @@ SIGNATURES = {
                                 C.POINTER(C.c_void_p)]),
     "agca_destroy": (C.c_int32, [C.c_void_p]),
     "agca_set_nu": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "agca_set_log_nu": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "agca_query": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(LevelInfo)]),
     "agca_get_flags": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                    C.POINTER(C.c_int64)]),

@@ -83,6 +83,7 @@ class Hierarchy:
         check(self._lib.agca_create(C.byref(cfg), _ptr(nu_fine), arr,
                                     C.c_void_p(self._stream.cuda_stream), C.byref(h)), "agca_create")
         self._h = h
+        self.version = 0   # bumped by every coefficient change
 
     def _check_nu(self, nu_fine, nu_coarse):
         if len(nu_coarse) != self.L:
@@ -111,6 +112,15 @@ class Hierarchy:
         arr = (C.c_void_p * max(1, self.L))(*[t.data_ptr() for t in nu_coarse])
         check(self._lib.agca_set_nu(self._h, _ptr(nu_fine), arr), "agca_set_nu")
         self._keep = [nu_fine] + list(nu_coarse)
+        self.version += 1
+
+    def set_log_nu(self, log_nu_fine: torch.Tensor, nu_coarse: Sequence[torch.Tensor]):
+        """Rebuild from log nu on the finest level (exponentiated by the library)."""
+        self._check_nu(log_nu_fine, nu_coarse)
+        arr = (C.c_void_p * max(1, self.L))(*[t.data_ptr() for t in nu_coarse])
+        check(self._lib.agca_set_log_nu(self._h, _ptr(log_nu_fine), arr), "agca_set_log_nu")
+        self._keep = [log_nu_fine] + list(nu_coarse)
+        self.version += 1
 
     # -- sizes ------------------------------------------------------------
     def n(self, level: int) -> int:
@@ -232,6 +242,8 @@ class Hierarchy:
         return g
 
     def load_vector(self, f: torch.Tensor, b: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """b_i = sum_e f_e |e| / 4; f: component-major (ncomp, 6 n_L^3) per-element values
+        by element id, flattened."""
         b = self.vec(self.L) if b is None else b
         check(self._lib.agca_load_vector(self._h, _ptr(f.contiguous()), _ptr(b)), "agca_load_vector")
         return b

@@ -202,24 +202,22 @@ int32_t check_dtype(const agca_hier* h, int dtype, bool need_mg) {
 // one pass of the level operator: the assembled stencil where the level has one,
 // the element loop otherwise
 template <typename T>
-int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, T omega,
-                const T* ec = nullptr) {
+int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, T omega) {
     const LevelOp<T> op = level_op<T>(h, l);
     if (op.sten)
-        HIPCHK(h, launch_stencil<T>(h->cfg.ncomp, mode, op.n, op.sten, u, b, op.dinv, ec, out, omega,
-                                    h->st));
+        HIPCHK(h, launch_stencil<T>(h->cfg.ncomp, mode, op.n, op.sten, u, b, op.dinv, out, omega, h->st));
     else
-        HIPCHK(h, launch_cube<T>(h->cfg.ncomp, mode, op, u, b, out, omega, h->st, ec));
+        HIPCHK(h, launch_cube<T>(h->cfg.ncomp, mode, op, u, b, out, omega, h->st));
     return AGCA_OK;
 }
 
-// whether the fused first-sweep / prolongation sweeps are available on level l: the
-// element loop forms stored-block products from u before its pass, so levels that
-// use it together with stored blocks take the unfused steps
+// whether the first two pre-sweeps can be one pass on level l: the element loop
+// without stored blocks (whose products are formed from a stored u before the pass);
+// on stencil levels the separate first sweep measures as fast
 template <typename T>
 bool fusable(const agca_hier* h, int l) {
     const LevelOp<T> op = level_op<T>(h, l);
-    return op.sten != nullptr || op.blk == nullptr;
+    return op.sten == nullptr && op.blk == nullptr;
 }
 
 template <typename T>
@@ -239,13 +237,12 @@ int32_t do_smooth(agca_hier* h, int l, int sweeps, double omega, const T* b, T* 
     return AGCA_OK;
 }
 
-// One V(pre,post)-cycle from a zero initial guess.  The first two pre-smoothing
-// sweeps from zero are one pass (the first, x = omega D^-1 b, is formed while
-// loading), and the coarse-grid correction x += P e_c is formed while loading the
-// first post-smoothing sweep; levels whose element loop uses stored blocks take
-// these steps separately.  The remaining sweeps ping-pong between the level's two
-// buffers, and on the finest level the starting buffer is chosen so that the last
-// sweep lands in the caller's x (no copies).
+// One V(pre,post)-cycle from a zero initial guess.  On element-loop levels without
+// stored blocks the first two pre-smoothing sweeps from zero are one pass (the
+// first, x = omega D^-1 b, is formed while loading); elsewhere the first sweep is
+// the elementwise x = omega D^-1 b.  The remaining sweeps ping-pong between the
+// level's two buffers, and on the finest level the starting buffer is chosen so
+// that the last sweep lands in the caller's x (no copies).
 template <typename T>
 int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
     const int L = h->cfg.L, nc = h->cfg.ncomp;
@@ -259,7 +256,8 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
         T* other = static_cast<T*>(h->lv[l].t);
         const bool fuse = fusable<T>(h, l);
         // out-of-place launches that write this level's iterate after its first producer
-        // (pre-sweeps after the first pass, then every post-sweep)
+        // (pre-sweeps after the first pass, then every post-sweep; the prolongation
+        // adds in place)
         const int first = (pre >= 2 && fuse) ? 2 : (pre > 0 ? 1 : 0);
         const int launches = (pre - first) + post;
         T* cur = (launches % 2 == 0) ? home : other;
@@ -288,15 +286,8 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
         const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
         T* cur = xcur[l];
         T* alt = xalt[l];
-        int i = 0;
-        if (post > 0 && fusable<T>(h, l)) {
-            TRY(do_cube<T>(h, l, MODE_JACOBI_P, cur, bl, alt, om, xcur[l - 1]));
-            std::swap(cur, alt);
-            i = 1;
-        } else {
-            HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, xcur[l - 1], cur, h->st));
-        }
-        for (; i < post; ++i) {
+        HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, xcur[l - 1], cur, h->st));
+        for (int i = 0; i < post; ++i) {
             TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, om));
             std::swap(cur, alt);
         }
@@ -428,13 +419,15 @@ int32_t build_coarsest(agca_hier* h) {
     return AGCA_OK;
 }
 
-int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const* nu_coarse) {
+// log_fine: nu_fine holds log nu (exponentiated while it is copied)
+int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const* nu_coarse,
+                        bool log_fine = false) {
     const int L = h->cfg.L, nc = h->cfg.ncomp, M = 4 * nc;
     // coefficients
     for (int l = 0; l <= L; ++l) {
         const double* src = (l == L) ? nu_fine : nu_coarse[l];
         if (!src) return fail(AGCA_E_INVALID, "null coefficient pointer for level " + std::to_string(l));
-        HIPCHK(h, launch_to_internal(h->lv[l].elems / 6, src, h->lv[l].nu64, h->st));
+        HIPCHK(h, launch_to_internal(h->lv[l].elems / 6, src, h->lv[l].nu64, l == L && log_fine, h->st));
     }
     for (int l = 0; l <= L; ++l) {
         int bad = 0;
@@ -749,6 +742,14 @@ int32_t agca_set_nu(agca_hier* h, const double* nu_fine, const double* const* nu
     HIPCHK(h, hipStreamSynchronize(h->st));
     free_blocks(h);
     return build_operators(h, nu_fine, nu_coarse);
+}
+
+int32_t agca_set_log_nu(agca_hier* h, const double* log_nu_fine, const double* const* nu_coarse) {
+    TRY(check_level(h, 0));
+    if (!log_nu_fine || !nu_coarse) return fail(AGCA_E_INVALID, "null coefficient pointer");
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    free_blocks(h);
+    return build_operators(h, log_nu_fine, nu_coarse, true);
 }
 
 int32_t agca_query(const agca_hier* h, int32_t level, agca_level_info* out) {

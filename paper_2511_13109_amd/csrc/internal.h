@@ -27,16 +27,14 @@ struct LevelOp {
 };
 
 // MODE_JACOBI0: two sweeps from a zero guess, x_out = x1 + omega D^-1 (b - A x1) with
-//               x1 = omega D^-1 b formed on the fly (u unused)
-// MODE_JACOBI_P: one sweep from x + P ec (ec on the level with n/2 cells), the
-//               interpolated correction formed on the fly
+//               x1 = omega D^-1 b formed on the fly (u unused; element loop only)
 enum CubeMode { MODE_APPLY = 0, MODE_RESIDUAL = 1, MODE_JACOBI = 2, MODE_APPLY_DOT = 3,
-                MODE_JACOBI0 = 4, MODE_JACOBI_P = 5 };
+                MODE_JACOBI0 = 4 };
 
 // v = A u / r = b - A u / x_out = x + omega D^-1 (b - A x)   (one element-loop pass)
 template <typename T>
 hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,
-                       T omega, hipStream_t st, const T* ec = nullptr);
+                       T omega, hipStream_t st);
 // v = A u and per-workgroup partial sums of u . v (FP64 only); *nblocks receives the count
 hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u, double* out,
                            double* partial, int* nblocks, hipStream_t st);
@@ -48,10 +46,10 @@ int cube_grid_blocks(int n);
 hipError_t launch_stencil_assemble(int ncomp, int n, const double* nu, double scale,
                                    const int32_t* blk, const double* blocks, double* S,
                                    hipStream_t st);
-// apply / residual / Jacobi modes (CubeMode) with an assembled stencil
+// apply / residual / Jacobi (MODE_APPLY, MODE_RESIDUAL, MODE_JACOBI) with an assembled stencil
 template <typename T>
 hipError_t launch_stencil(int ncomp, int mode, int n, const T* S, const T* u, const T* b,
-                          const T* dinv, const T* ec, T* out, T omega, hipStream_t st);
+                          const T* dinv, T* out, T omega, hipStream_t st);
 
 // transfers (Section 2.1)
 template <typename T>
@@ -86,7 +84,9 @@ template <typename T>
 hipError_t launch_fill(int64_t n, T value, T* x, hipStream_t st);
 hipError_t launch_count_invalid(const double* v, int64_t n, int* counter, hipStream_t st);
 // element-id order (e = s + 6 cell) -> internal per-element layout (kuhn.h elem_slot)
-hipError_t launch_to_internal(int64_t cells, const double* by_id, double* internal, hipStream_t st);
+// (exponentiate: the input holds log nu)
+hipError_t launch_to_internal(int64_t cells, const double* by_id, double* internal, bool exponentiate,
+                              hipStream_t st);
 
 // setup kernels (Sections 2.2-2.3)
 hipError_t launch_minmax_from_fine(int n_coarse, const double* nu_fine, double* mn, double* mx,

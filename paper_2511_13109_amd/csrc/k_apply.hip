@@ -1,9 +1,7 @@
 // Matrix-free element loop on the refined Kuhn lattice (paper eq. (2.3) on the
 // finest level, eq. (2.9) on coarser levels): apply, residual and damped-Jacobi sweep.
-// Two Jacobi variants fold the neighbouring V-cycle steps into the sweep's input:
-// MODE_JACOBI0 starts from the first sweep from zero (u = omega D^-1 b, formed while
-// loading), MODE_JACOBI_P from x + P e_c (the coarse-grid correction of Section 2.1,
-// interpolated while loading), so neither intermediate vector is stored.
+// MODE_JACOBI0 folds the first sweep from a zero guess (u = omega D^-1 b, formed
+// while loading) into the second, so the first iterate is never stored.
 //
 // Layout of the work: a 16 x 16 workgroup owns a 16 x 16 column of lattice
 // cells and marches up through a chunk of z layers.  At every step a thread
@@ -141,8 +139,7 @@ __attribute__((amdgpu_waves_per_eu(CubeWaves<NC, T>::value > 0 ? CubeWaves<NC, T
 k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
        const T* __restrict__ u, const NT* __restrict__ nu, const int32_t* __restrict__ blk,
        const T* __restrict__ yblk, const T* __restrict__ b, const T* __restrict__ dinv,
-       const T* __restrict__ ec, T* __restrict__ out, const T scale, const T omega,
-       double* __restrict__ partial) {
+       T* __restrict__ out, const T scale, const T omega, double* __restrict__ partial) {
     __shared__ T ubuf[2][NC][TY + 1][TX + 1];
     __shared__ T ybuf[2][NC][2][TY][TX];
     double dot_acc = 0.0;  // MODE_APPLY_DOT: this thread's share of u . (A u)
@@ -172,31 +169,19 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     const int qb = min(NTHREADS + tid, TE - 1);
     const bool has_b = tid < NB;
     // Tile node q of this thread: offset x + (n+1) y of the clamped node within a z layer.
-    // JACOBI_P also needs the two coarse interpolation sources of the node: on the
-    // level with n/2 cells, a fine node with odd-coordinate indicator d takes the mean
-    // of the coarse nodes (X - d)/2 and (X + d)/2 (the node itself when d = 0).
-    const int nc1 = n / 2 + 1;
-    const int64_t Nc = (int64_t)nc1 * nc1 * nc1;
-    int at_a, at_b, lo_a = 0, lo_b = 0, hi_a = 0, hi_b = 0;
-    bool ina, inb, odd_a = false, odd_b = false;
-    auto tile_node = [&](int q, int& at, int& lo, int& hi, bool& in_xy, bool& odd) {
+    int at_a, at_b;
+    bool ina, inb;
+    auto tile_node = [&](int q, int& at, bool& in_xy) {
         const int x = X0 - 1 + q % TW, y = Y0 - 1 + q / TW;
         in_xy = x > 0 && x < n && y > 0 && y < n;
         const int xc = min(max(x, 0), n), yc = min(max(y, 0), n);
         at = xc + (n + 1) * yc;
-        if constexpr (MODE == MODE_JACOBI_P) {
-            const int dx = xc & 1, dy = yc & 1;
-            lo = ((xc - dx) >> 1) + nc1 * ((yc - dy) >> 1);
-            hi = ((xc + dx) >> 1) + nc1 * ((yc + dy) >> 1);
-            odd = (dx | dy) != 0;
-        }
     };
-    tile_node(qa, at_a, lo_a, hi_a, ina, odd_a);
-    tile_node(qb, at_b, lo_b, hi_b, inb, odd_b);
+    tile_node(qa, at_a, ina);
+    tile_node(qb, at_b, inb);
     auto load_tile = [&](int z, T (&va)[NC], T (&vb)[NC]) {
         const bool zin = z > 0 && z < n;
-        const int zz = min(max(z, 0), n);
-        const int64_t off = (int64_t)zz * layer;
+        const int64_t off = (int64_t)min(max(z, 0), n) * layer;
         if constexpr (MODE == MODE_JACOBI0) {
             // the first sweep from zero, x1 = omega D^-1 b
             const T* pd = dinv + off;
@@ -207,24 +192,6 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
                 va[c] = (ina && zin) ? a : T(0);
                 if (has_b) {
                     const T bb = omega * pd[c * N + at_b] * pbv[c * N + at_b];
-                    vb[c] = (inb && zin) ? bb : T(0);
-                }
-            }
-        } else if constexpr (MODE == MODE_JACOBI_P) {
-            // x + P e_c
-            const int dz = zz & 1;
-            const int64_t zl = (int64_t)((zz - dz) >> 1) * nc1 * nc1;
-            const int64_t zh = (int64_t)((zz + dz) >> 1) * nc1 * nc1;
-            const T* pu = u + off;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const T* e = ec + c * Nc;
-                const T la = e[zl + lo_a], ha = e[zh + hi_a];
-                const T a = pu[c * N + at_a] + ((odd_a || dz) ? T(0.5) * (la + ha) : la);
-                va[c] = (ina && zin) ? a : T(0);
-                if (has_b) {
-                    const T lb = e[zl + lo_b], hb = e[zh + hi_b];
-                    const T bb = pu[c * N + at_b] + ((odd_b || dz) ? T(0.5) * (lb + hb) : lb);
                     vb[c] = (inb && zin) ? bb : T(0);
                 }
             }
@@ -252,7 +219,7 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     const bool col_ok = cx >= 0 && cx < n && cy >= 0 && cy < n;
     const bool writer = tx >= 1 && ty >= 1 && cx <= n && cy <= n;
     const bool xin = cx > 0 && cx < n && cy > 0 && cy < n;
-    constexpr bool IS_JACOBI = MODE == MODE_JACOBI || MODE == MODE_JACOBI0 || MODE == MODE_JACOBI_P;
+    constexpr bool IS_JACOBI = MODE == MODE_JACOBI || MODE == MODE_JACOBI0;
     constexpr bool NEEDS_B = MODE == MODE_RESIDUAL || IS_JACOBI;
     // cell and node columns of this thread, clamped
     const int64_t cellcol = min(max(cx, 0), n - 1) + (int64_t)n * min(max(cy, 0), n - 1);
@@ -489,8 +456,7 @@ int pick_zc(int n) {
 
 template <int NC, typename T, typename NT, int MODE, bool BLK>
 hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omega,
-                    hipStream_t st, double* partial = nullptr, int* nblocks = nullptr,
-                    const T* ec = nullptr) {
+                    hipStream_t st, double* partial = nullptr, int* nblocks = nullptr) {
     const int n = op.n;
     const int zc = pick_zc(n);
     dim3 block(TX, TY, 1);
@@ -498,7 +464,7 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omeg
               gz = (n + 1 + zc - 1) / zc;
     dim3 grid((unsigned)(gx * gy * gz), 1, 1);
     const T scale = T(1.0 / (6.0 * n));
-    if constexpr (BLK && MODE != MODE_JACOBI0 && MODE != MODE_JACOBI_P) {
+    if constexpr (BLK && MODE != MODE_JACOBI0) {
         if (op.nflag > 0) {
             const int64_t threads = op.nflag * 4 * NC;
             hipLaunchKernelGGL((k_block_products<NC, T>), dim3((unsigned)((threads + 255) / 256)),
@@ -514,39 +480,36 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omeg
     if (nblocks) *nblocks = gx * gy * gz;
     hipLaunchKernelGGL((k_cube<NC, T, NT, MODE, BLK>), grid, block, 0, st, n, zc, gx, gy,
                        xcd_map ? gz : -gz, u,
-                       reinterpret_cast<const NT*>(op.nu), op.blk, op.yblk, b, op.dinv, ec,
-                       out, scale, omega, partial);
+                       reinterpret_cast<const NT*>(op.nu), op.blk, op.yblk, b, op.dinv, out,
+                       scale, omega, partial);
     return hipGetLastError();
 }
 
 template <int NC, typename T, int MODE>
 hipError_t dispatch_nu(const LevelOp<T>& op, const T* u, const T* b, T* out, T omega,
-                       hipStream_t st, const T* ec) {
+                       hipStream_t st) {
     if (!op.nu || !out || op.n < 2) return hipErrorInvalidValue;
     if (MODE != MODE_JACOBI0 && !u) return hipErrorInvalidValue;
     if (MODE != MODE_APPLY && !b) return hipErrorInvalidValue;
-    if ((MODE == MODE_JACOBI || MODE == MODE_JACOBI0 || MODE == MODE_JACOBI_P) && !op.dinv)
-        return hipErrorInvalidValue;
-    if (MODE == MODE_JACOBI_P && (!ec || op.n < 4)) return hipErrorInvalidValue;
+    if ((MODE == MODE_JACOBI || MODE == MODE_JACOBI0) && !op.dinv) return hipErrorInvalidValue;
     if (op.blk && (!op.blocks || !op.ids || !op.yblk || op.nflag <= 0)) return hipErrorInvalidValue;
-    // the fused modes read u through their own formula, so stored-block products
-    // (formed from u before the element loop) are not available to them
-    if ((MODE == MODE_JACOBI0 || MODE == MODE_JACOBI_P) && op.blk) return hipErrorInvalidValue;
-    constexpr bool FUSED = MODE == MODE_JACOBI0 || MODE == MODE_JACOBI_P;
+    // the stored-block products are formed from u before the element loop, which
+    // MODE_JACOBI0 never stores
+    if (MODE == MODE_JACOBI0 && op.blk) return hipErrorInvalidValue;
     const bool blk = op.blk != nullptr;
     if constexpr (sizeof(T) == 8) {
         if (op.nu_kind != AGCA_F64) return hipErrorInvalidValue;
-        if constexpr (!FUSED)
+        if constexpr (MODE != MODE_JACOBI0)
             if (blk) return launch_t<NC, T, double, MODE, true>(op, u, b, out, omega, st);
-        return launch_t<NC, T, double, MODE, false>(op, u, b, out, omega, st, nullptr, nullptr, ec);
+        return launch_t<NC, T, double, MODE, false>(op, u, b, out, omega, st);
     } else {
         if (op.nu_kind == AGCA_F32) {
-            if constexpr (!FUSED)
+            if constexpr (MODE != MODE_JACOBI0)
                 if (blk) return launch_t<NC, T, float, MODE, true>(op, u, b, out, omega, st);
-            return launch_t<NC, T, float, MODE, false>(op, u, b, out, omega, st, nullptr, nullptr, ec);
+            return launch_t<NC, T, float, MODE, false>(op, u, b, out, omega, st);
         }
         if (op.nu_kind == AGCA_BF16 && !blk)
-            return launch_t<NC, T, uint16_t, MODE, false>(op, u, b, out, omega, st, nullptr, nullptr, ec);
+            return launch_t<NC, T, uint16_t, MODE, false>(op, u, b, out, omega, st);
         return hipErrorInvalidValue;
     }
 }
@@ -576,27 +539,26 @@ hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u
 
 template <int NC, typename T>
 hipError_t launch_cube_nc(int mode, const LevelOp<T>& op, const T* u, const T* b, T* out, T omega,
-                          hipStream_t st, const T* ec) {
+                          hipStream_t st) {
     switch (mode) {
-        case MODE_APPLY: return dispatch_nu<NC, T, MODE_APPLY>(op, u, b, out, omega, st, ec);
-        case MODE_RESIDUAL: return dispatch_nu<NC, T, MODE_RESIDUAL>(op, u, b, out, omega, st, ec);
-        case MODE_JACOBI: return dispatch_nu<NC, T, MODE_JACOBI>(op, u, b, out, omega, st, ec);
-        case MODE_JACOBI0: return dispatch_nu<NC, T, MODE_JACOBI0>(op, u, b, out, omega, st, ec);
-        case MODE_JACOBI_P: return dispatch_nu<NC, T, MODE_JACOBI_P>(op, u, b, out, omega, st, ec);
+        case MODE_APPLY: return dispatch_nu<NC, T, MODE_APPLY>(op, u, b, out, omega, st);
+        case MODE_RESIDUAL: return dispatch_nu<NC, T, MODE_RESIDUAL>(op, u, b, out, omega, st);
+        case MODE_JACOBI: return dispatch_nu<NC, T, MODE_JACOBI>(op, u, b, out, omega, st);
+        case MODE_JACOBI0: return dispatch_nu<NC, T, MODE_JACOBI0>(op, u, b, out, omega, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
 hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,
-                       T omega, hipStream_t st, const T* ec) {
-    return ncomp == 1 ? launch_cube_nc<1, T>(mode, op, u, b, out, omega, st, ec)
-                      : launch_cube_nc<3, T>(mode, op, u, b, out, omega, st, ec);
+                       T omega, hipStream_t st) {
+    return ncomp == 1 ? launch_cube_nc<1, T>(mode, op, u, b, out, omega, st)
+                      : launch_cube_nc<3, T>(mode, op, u, b, out, omega, st);
 }
 
 template hipError_t launch_cube<double>(int, int, const LevelOp<double>&, const double*,
-                                        const double*, double*, double, hipStream_t, const double*);
+                                        const double*, double*, double, hipStream_t);
 template hipError_t launch_cube<float>(int, int, const LevelOp<float>&, const float*,
-                                       const float*, float*, float, hipStream_t, const float*);
+                                       const float*, float*, float, hipStream_t);
 
 }  // namespace agca

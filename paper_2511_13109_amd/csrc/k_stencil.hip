@@ -80,7 +80,7 @@ k_stencil_assemble(int n, const double* __restrict__ nu, double scale, const int
 template <int NC, typename T, int MODE>
 __global__ void __launch_bounds__(NT)
 k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T* __restrict__ b,
-                const T* __restrict__ dinv, const T* __restrict__ ec, T* __restrict__ out, T omega) {
+                const T* __restrict__ dinv, T* __restrict__ out, T omega) {
     const int64_t n1 = n + 1, N = n1 * n1 * n1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     const int c = blockIdx.y;
@@ -91,38 +91,18 @@ k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T
         out[c * N + p] = T(0);
         return;
     }
-    const int64_t nc1 = n / 2 + 1, Nc = nc1 * nc1 * nc1;
-    T acc = T(0), self = T(0);
+    T acc = T(0);
 #pragma unroll
     for (int k = 0; k < NNB; ++k) {
         const int m = nbr_mask(k), sg = nbr_sign(k);
         const int qx = x + sg * (m & 1), qy = y + sg * ((m >> 1) & 1), qz = z + sg * (m >> 2);
+        // boundary values of u are ignored (treated as zero)
         const bool qin = qx > 0 && qy > 0 && qz > 0 && qx < n && qy < n && qz < n;
         const int64_t q = qx + n1 * (qy + n1 * (int64_t)qz);
-        int64_t lo = 0, hi = 0;
-        bool odd = false;
-        if constexpr (MODE == MODE_JACOBI_P) {
-            const int dx = qx & 1, dy = qy & 1, dz = qz & 1;
-            lo = ((qx - dx) >> 1) + nc1 * (((qy - dy) >> 1) + nc1 * (int64_t)((qz - dz) >> 1));
-            hi = ((qx + dx) >> 1) + nc1 * (((qy + dy) >> 1) + nc1 * (int64_t)((qz + dz) >> 1));
-            odd = (dx | dy | dz) != 0;
-        }
 #pragma unroll
         for (int d = 0; d < NC; ++d) {
-            const int64_t i = d * N + q;
-            T v;
-            if constexpr (MODE == MODE_JACOBI0) {
-                v = omega * dinv[i] * b[i];
-            } else if constexpr (MODE == MODE_JACOBI_P) {
-                const T* e = ec + d * Nc;
-                const T el = e[lo], eh = e[hi];
-                v = u[i] + (odd ? T(0.5) * (el + eh) : el);
-            } else {
-                v = u[i];
-            }
-            v = qin ? v : T(0);
-            if (k == 0 && d == c) self = v;
-            acc += S[((int64_t)(c * NC + d) * NNB + k) * N + p] * v;
+            const T v = u[d * N + q];
+            acc += S[((int64_t)(c * NC + d) * NNB + k) * N + p] * (qin ? v : T(0));
         }
     }
     const int64_t o = c * N + p;
@@ -131,30 +111,26 @@ k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T
     } else if constexpr (MODE == MODE_RESIDUAL) {
         out[o] = b[o] - acc;
     } else {
-        out[o] = self + omega * dinv[o] * (b[o] - acc);
+        out[o] = u[o] + omega * dinv[o] * (b[o] - acc);
     }
 }
 
 template <int NC, typename T, int MODE>
-hipError_t launch_mode(int n, const T* S, const T* u, const T* b, const T* dinv, const T* ec, T* out,
-                       T omega, hipStream_t st) {
+hipError_t launch_mode(int n, const T* S, const T* u, const T* b, const T* dinv, T* out, T omega,
+                       hipStream_t st) {
     const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
     hipLaunchKernelGGL((k_stencil_apply<NC, T, MODE>), dim3((unsigned)((N + NT - 1) / NT), NC),
-                       dim3(NT), 0, st, n, S, u, b, dinv, ec, out, omega);
+                       dim3(NT), 0, st, n, S, u, b, dinv, out, omega);
     return hipGetLastError();
 }
 
 template <int NC, typename T>
-hipError_t launch_nc(int mode, int n, const T* S, const T* u, const T* b, const T* dinv,
-                     const T* ec, T* out, T omega, hipStream_t st) {
+hipError_t launch_nc(int mode, int n, const T* S, const T* u, const T* b, const T* dinv, T* out,
+                     T omega, hipStream_t st) {
     switch (mode) {
-        case MODE_APPLY: return launch_mode<NC, T, MODE_APPLY>(n, S, u, b, dinv, ec, out, omega, st);
-        case MODE_RESIDUAL:
-            return launch_mode<NC, T, MODE_RESIDUAL>(n, S, u, b, dinv, ec, out, omega, st);
-        case MODE_JACOBI: return launch_mode<NC, T, MODE_JACOBI>(n, S, u, b, dinv, ec, out, omega, st);
-        case MODE_JACOBI0: return launch_mode<NC, T, MODE_JACOBI0>(n, S, u, b, dinv, ec, out, omega, st);
-        case MODE_JACOBI_P:
-            return launch_mode<NC, T, MODE_JACOBI_P>(n, S, u, b, dinv, ec, out, omega, st);
+        case MODE_APPLY: return launch_mode<NC, T, MODE_APPLY>(n, S, u, b, dinv, out, omega, st);
+        case MODE_RESIDUAL: return launch_mode<NC, T, MODE_RESIDUAL>(n, S, u, b, dinv, out, omega, st);
+        case MODE_JACOBI: return launch_mode<NC, T, MODE_JACOBI>(n, S, u, b, dinv, out, omega, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -176,20 +152,17 @@ hipError_t launch_stencil_assemble(int ncomp, int n, const double* nu, double sc
 
 template <typename T>
 hipError_t launch_stencil(int ncomp, int mode, int n, const T* S, const T* u, const T* b,
-                          const T* dinv, const T* ec, T* out, T omega, hipStream_t st) {
-    if (!S || !out || n < 2) return hipErrorInvalidValue;
-    if (mode != MODE_JACOBI0 && !u) return hipErrorInvalidValue;
+                          const T* dinv, T* out, T omega, hipStream_t st) {
+    if (!S || !u || !out || n < 2) return hipErrorInvalidValue;
     if (mode != MODE_APPLY && !b) return hipErrorInvalidValue;
-    if ((mode == MODE_JACOBI || mode == MODE_JACOBI0 || mode == MODE_JACOBI_P) && !dinv)
-        return hipErrorInvalidValue;
-    if (mode == MODE_JACOBI_P && (!ec || n < 4)) return hipErrorInvalidValue;
-    return ncomp == 1 ? launch_nc<1, T>(mode, n, S, u, b, dinv, ec, out, omega, st)
-                      : launch_nc<3, T>(mode, n, S, u, b, dinv, ec, out, omega, st);
+    if (mode == MODE_JACOBI && !dinv) return hipErrorInvalidValue;
+    return ncomp == 1 ? launch_nc<1, T>(mode, n, S, u, b, dinv, out, omega, st)
+                      : launch_nc<3, T>(mode, n, S, u, b, dinv, out, omega, st);
 }
 
 template hipError_t launch_stencil<double>(int, int, int, const double*, const double*, const double*,
-                                           const double*, const double*, double*, double, hipStream_t);
+                                           const double*, double*, double, hipStream_t);
 template hipError_t launch_stencil<float>(int, int, int, const float*, const float*, const float*,
-                                          const float*, const float*, float*, float, hipStream_t);
+                                          const float*, float*, float, hipStream_t);
 
 }  // namespace agca

@@ -275,10 +275,13 @@ k_grad(int n, const double* __restrict__ nu, double scale, const double* __restr
 }
 
 __global__ void __launch_bounds__(NT)
-k_to_internal(int64_t cells, const double* __restrict__ by_id, double* __restrict__ internal) {
+k_to_internal(int64_t cells, const double* __restrict__ by_id, double* __restrict__ internal,
+              int exponentiate) {
     const int64_t stride = (int64_t)gridDim.x * NT;
-    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < 6 * cells; i += stride)
-        internal[elem_index(i, cells)] = by_id[i];
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < 6 * cells; i += stride) {
+        const double v = by_id[i];
+        internal[elem_index(i, cells)] = exponentiate ? exp(v) : v;
+    }
 }
 
 // b_i = sum over the simplices containing node i of f_e |e| / 4 (per component)
@@ -402,11 +405,12 @@ hipError_t launch_count_invalid(const double* v, int64_t n, int* counter, hipStr
     hipLaunchKernelGGL(k_count_invalid, dim3(grid_stride(n)), dim3(NT), 0, st, v, n, counter);
     return hipGetLastError();
 }
-hipError_t launch_to_internal(int64_t cells, const double* by_id, double* internal, hipStream_t st) {
+hipError_t launch_to_internal(int64_t cells, const double* by_id, double* internal, bool exponentiate,
+                              hipStream_t st) {
     if (cells <= 0) return hipSuccess;
     if (!by_id || !internal) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_to_internal, dim3(grid_stride(6 * cells)), dim3(NT), 0, st, cells, by_id,
-                       internal);
+                       internal, exponentiate ? 1 : 0);
     return hipGetLastError();
 }
 hipError_t launch_grad(int ncomp, int n, const double* nu, double scale, const double* u,

@@ -212,6 +212,47 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* opts, const double* b, d
  * u, w: device FP64 level vectors on level L; g: device, 6 n_L^3 doubles. */
 int32_t agca_grad_log_nu(agca_hier* h, const double* u, const double* w, double* g);
 
+/* ---- Generalized Stokes (Section 3.1, eqs. (3.1)-(3.5)) --------------------------
+ * Velocity: this hierarchy's finest level L (ncomp = 3, P1-iso-P2); pressure: P1 on
+ * every node of level L-1 (no pressure boundary condition), (n_{L-1}+1)^3 doubles.
+ * B = -integral psi_k div Phi_j (the sign that makes [[A, B^T], [B, 0]] symmetric),
+ * formed as -P^T B_L: psi_k is linear on each level-L simplex, so its integral
+ * against the constant divergence is |d| times its mean vertex value.  All
+ * pointers are device FP64 vectors; velocity boundary slots are ignored on input
+ * and written as 0.  Errors: AGCA_E_INVALID for ncomp != 3 or L < 2. */
+
+/* q = B u (u: velocity level vector; q: pressure vector). */
+int32_t agca_stokes_div(agca_hier* h, const double* u, double* q);
+
+/* v = B^T p (p: pressure vector; v: velocity level vector, overwritten). */
+int32_t agca_stokes_grad(agca_hier* h, const double* p, double* v);
+
+/* m = lumped pressure mass weighted by 1/nu: m_k = sum_d |d| / nu_d psi_k(centroid_d),
+ * d over the level-L simplices (the pressure block of the preconditioner). */
+int32_t agca_stokes_mass(agca_hier* h, double* m);
+
+typedef enum { AGCA_STOKES_FGMRES = 0, AGCA_STOKES_MINRES = 1 } agca_stokes_solver;
+typedef struct {
+    int32_t solver;          /* agca_stokes_solver                                          */
+    int32_t restart;         /* FGMRES restart length, 1..126                              */
+    int32_t max_iter;
+    int32_t record_history;
+    double tol;              /* stop when ||r||_2 <= tol ||(f, g)||_2 (eq. (4.3))           */
+} agca_stokes_opts;
+
+/* Solve [[A, B^T], [B, 0]] (u, p) = (f, g) in FP64 with the block-diagonal
+ * preconditioner diag(one AGCA V-cycle of A, diag(m)^-1): FGMRES(restart), right
+ * preconditioned with modified Gram-Schmidt (any mg_dtype: the FP32 V-cycle makes the
+ * preconditioner non-linear), or MINRES (mg_dtype F64 only: it needs a fixed SPD
+ * preconditioner; its true residual is checked every step).  The returned p has
+ * zero mean over the pressure nodes.  Work space: 2 restart + 5 (FGMRES) or 10
+ * (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy.
+ * Returns AGCA_OK when converged, AGCA_E_NOCONV (u, p, stats filled) otherwise;
+ * stats->history holds the FGMRES residual estimates (true residual at restarts)
+ * or the MINRES true residuals. */
+int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* opts, const double* f,
+                          const double* g, double* u, double* p, agca_solve_stats* stats);
+
 /* b = load vector of a per-element constant source: b_i = sum_e f_e |e| / 4 on
  * level L.  f: device, ncomp blocks of 6 n_L^3 doubles; b: device FP64 level vector. */
 int32_t agca_load_vector(agca_hier* h, const double* f, double* b);

@@ -37,6 +37,14 @@ class SolveOpts(C.Structure):
                 ("use_x0", C.c_int32), ("record_history", C.c_int32)]
 
 
+class StokesOpts(C.Structure):
+    _fields_ = [("solver", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32),
+                ("record_history", C.c_int32), ("tol", C.c_double)]
+
+
+STOKES_FGMRES, STOKES_MINRES = 0, 1
+
+
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("floor_limited", C.c_int32),
                 ("replacements", C.c_int32), ("rel_residual", C.c_double),
@@ -73,6 +81,11 @@ SIGNATURES = {
                                C.POINTER(SolveStats)]),
     "agca_grad_log_nu": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "agca_load_vector": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "agca_stokes_div": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "agca_stokes_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "agca_stokes_mass": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "agca_stokes_solve": (C.c_int32, [C.c_void_p, C.POINTER(StokesOpts), C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.POINTER(SolveStats)]),
     "agca_device_bytes": (C.c_int64, [C.c_void_p]),
     "agca_last_error": (C.c_char_p, []),
 }

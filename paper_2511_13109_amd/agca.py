@@ -249,6 +249,56 @@ class Hierarchy:
         return b
 
 
+class Stokes:
+    """Generalized Stokes on a vector Hierarchy (Section 3.1): velocity on level L,
+    pressure P1 on every node of level L-1."""
+
+    def __init__(self, H: Hierarchy):
+        if H.ncomp != 3:
+            raise ValueError("Stokes needs the vector hierarchy")
+        self.H = H
+        self.np = H.nodes(H.L - 1)
+
+    def pvec(self) -> torch.Tensor:
+        return torch.zeros(self.np, dtype=torch.float64, device=self.H.device)
+
+    def div(self, u: torch.Tensor, q: Optional[torch.Tensor] = None) -> torch.Tensor:
+        q = self.pvec() if q is None else q
+        check(self.H._lib.agca_stokes_div(self.H._h, _ptr(u), _ptr(q)), "agca_stokes_div")
+        return q
+
+    def grad(self, p: torch.Tensor, v: Optional[torch.Tensor] = None) -> torch.Tensor:
+        v = self.H.vec(self.H.L) if v is None else v
+        check(self.H._lib.agca_stokes_grad(self.H._h, _ptr(p), _ptr(v)), "agca_stokes_grad")
+        return v
+
+    def mass(self) -> torch.Tensor:
+        m = self.pvec()
+        check(self.H._lib.agca_stokes_mass(self.H._h, _ptr(m)), "agca_stokes_mass")
+        return m
+
+    def solve(self, f: torch.Tensor, g: Optional[torch.Tensor] = None, solver: str = "fgmres",
+              restart: int = 30, tol: float = 1e-8, max_iter: int = 1000, record_history: bool = True,
+              raise_on_noconv: bool = True):
+        opts = _lib.StokesOpts()
+        opts.solver = {"fgmres": _lib.STOKES_FGMRES, "minres": _lib.STOKES_MINRES}[solver]
+        opts.restart, opts.max_iter, opts.tol = restart, max_iter, tol
+        opts.record_history = 1 if record_history else 0
+        g = self.pvec() if g is None else g
+        u = self.H.vec(self.H.L)
+        p = self.pvec()
+        st = _lib.SolveStats()
+        rc = self.H._lib.agca_stokes_solve(self.H._h, C.byref(opts), _ptr(f), _ptr(g), _ptr(u), _ptr(p),
+                                           C.byref(st))
+        stats = {"iterations": st.iterations, "converged": bool(st.converged),
+                 "rel_residual": st.rel_residual, "seconds": st.seconds, "status": rc,
+                 "history": list(st.history[:min(st.iterations + 1, _lib.MAX_HISTORY)])
+                 if record_history else []}
+        if rc != _lib.AGCA_OK and (rc != _lib.AGCA_E_NOCONV or raise_on_noconv):
+            check(rc, "agca_stokes_solve")
+        return u, p, stats
+
+
 def coefficients_from_field(field, L: int, device="cuda") -> List[torch.Tensor]:
     """Sample a coefficient field at the element centroids of every level 0..L (host evaluation)."""
     from .grid import element_centroids

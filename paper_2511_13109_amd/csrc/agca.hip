@@ -75,12 +75,24 @@ struct agca_hier {
     float* s_r32 = nullptr;
     float* s_z32 = nullptr;
     double* trans[2] = {nullptr, nullptr};
+    // Stokes (velocity: finest level, pressure: level L-1)
+    int64_t nu_version = 0;      // bumped by every coefficient rebuild
+    int64_t mass_version = -1;   // nu_version the pressure mass was formed for
+    double* st_mass = nullptr;   // lumped 1/nu pressure mass (level L-1, all nodes)
+    double* st_pf = nullptr;     // fine-level scalar scratch (interpolated pressure)
+    double* st_qf = nullptr;     // fine-level scalar scratch (fine divergence)
+    double* st_work = nullptr;   // Krylov vectors, st_work_vecs of them
+    int64_t st_work_vecs = 0;
     std::vector<void*> allocs;
     int64_t bytes = 0;
     bool error = false;
 };
 
 namespace {
+
+// device reduction slots (and their pinned host mirror): Krylov coefficients of one
+// Arnoldi step at the largest Stokes restart length
+constexpr int AGCA_RED_SLOTS = 128;
 
 int64_t nodes_of(int n) { return (int64_t)(n + 1) * (n + 1) * (n + 1); }
 int64_t elems_of(int n) { return 6LL * n * n * n; }
@@ -423,6 +435,7 @@ int32_t build_coarsest(agca_hier* h) {
 int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const* nu_coarse,
                         bool log_fine = false) {
     const int L = h->cfg.L, nc = h->cfg.ncomp, M = 4 * nc;
+    ++h->nu_version;
     // coefficients
     for (int l = 0; l <= L; ++l) {
         const double* src = (l == L) ? nu_fine : nu_coarse[l];
@@ -716,10 +729,10 @@ int32_t agca_create(const agca_config* cfg, const double* nu_fine, const double*
         h->partial_cap = std::max(2 * h->nb_partial, cube_grid_blocks(h->lv[L].n));
         rc = alloc_t(h, &h->partial, h->partial_cap);
     }
-    if (rc == AGCA_OK) rc = alloc_t(h, &h->red, 16);
+    if (rc == AGCA_OK) rc = alloc_t(h, &h->red, AGCA_RED_SLOTS);
     if (rc == AGCA_OK) rc = alloc_t(h, &h->counter, 4);
     if (rc == AGCA_OK) {
-        hipError_t e = hipHostMalloc((void**)&h->red_host, 16 * sizeof(double));
+        hipError_t e = hipHostMalloc((void**)&h->red_host, AGCA_RED_SLOTS * sizeof(double));
         if (e != hipSuccess) rc = fail(AGCA_E_OOM, "hipHostMalloc failed");
     }
     if (rc != AGCA_OK) return bail(rc);
@@ -1086,4 +1099,338 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     return AGCA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Stokes: K = [[A, B^T], [B, 0]], velocity on level L (this hierarchy's operator),
+// pressure on every node of level L-1.  Krylov vectors are contiguous [u | p].
+// ---------------------------------------------------------------------------
+struct StokesDims {
+    int64_t nu = 0, np = 0, tot = 0;
+    int nf = 0, nc = 0;
+};
+
+static StokesDims stokes_dims(const agca_hier* h) {
+    StokesDims d;
+    const int L = h->cfg.L;
+    d.nf = h->lv[L].n;
+    d.nc = h->lv[L - 1].n;
+    d.nu = 3 * h->lv[L].nodes;
+    d.np = h->lv[L - 1].nodes;
+    d.tot = d.nu + d.np;
+    return d;
+}
+
+static int32_t stokes_ready(agca_hier* h) {
+    TRY(check_level(h, 0));
+    if (h->cfg.ncomp != 3) return fail(AGCA_E_INVALID, "Stokes needs the vector hierarchy (ncomp = 3)");
+    if (h->cfg.L < 2) return fail(AGCA_E_INVALID, "Stokes needs L >= 2");
+    const StokesDims d = stokes_dims(h);
+    if (!h->st_mass) {
+        TRY(alloc_t(h, &h->st_mass, (size_t)d.np));
+        TRY(alloc_t(h, &h->st_pf, (size_t)h->lv[h->cfg.L].nodes));
+        TRY(alloc_t(h, &h->st_qf, (size_t)h->lv[h->cfg.L].nodes));
+    }
+    if (h->mass_version != h->nu_version) {
+        HIPCHK(h, launch_stokes_mass_fine(d.nf, h->lv[h->cfg.L].nu64, h->st_qf, h->st));
+        HIPCHK(h, launch_restrict_all(d.nc, h->st_qf, h->st_mass, h->st));
+        h->mass_version = h->nu_version;
+    }
+    return AGCA_OK;
+}
+
+static int32_t stokes_work(agca_hier* h, int64_t vecs) {
+    if (h->st_work_vecs >= vecs) return AGCA_OK;
+    if (h->st_work) {
+        for (size_t i = 0; i < h->allocs.size(); ++i)
+            if (h->allocs[i] == h->st_work) {
+                hipFree(h->st_work);
+                h->allocs.erase(h->allocs.begin() + i);
+                h->bytes -= h->st_work_vecs * stokes_dims(h).tot * (int64_t)sizeof(double);
+                break;
+            }
+        h->st_work = nullptr;
+        h->st_work_vecs = 0;
+    }
+    TRY(alloc_t(h, &h->st_work, (size_t)(vecs * stokes_dims(h).tot)));
+    h->st_work_vecs = vecs;
+    return AGCA_OK;
+}
+
+// q (pressure) = B u
+static int32_t stokes_div(agca_hier* h, const double* u, double* q) {
+    const StokesDims d = stokes_dims(h);
+    HIPCHK(h, launch_stokes_div_fine(d.nf, u, h->st_qf, h->st));
+    HIPCHK(h, launch_restrict_all(d.nc, h->st_qf, q, h->st));
+    return AGCA_OK;
+}
+// v (velocity) += B^T p
+static int32_t stokes_grad_add(agca_hier* h, const double* p, double* v) {
+    const StokesDims d = stokes_dims(h);
+    HIPCHK(h, launch_prolong_all(d.nf, p, h->st_pf, h->st));
+    HIPCHK(h, launch_stokes_grad_fine_add(d.nf, h->st_pf, v, h->st));
+    return AGCA_OK;
+}
+// y = K x
+static int32_t stokes_apply(agca_hier* h, const double* x, double* y) {
+    const StokesDims d = stokes_dims(h);
+    TRY(do_cube<double>(h, h->cfg.L, MODE_APPLY, x, nullptr, y, 0.0));
+    TRY(stokes_grad_add(h, x + d.nu, y));
+    TRY(stokes_div(h, x, y + d.nu));
+    return AGCA_OK;
+}
+// z = diag(V-cycle, mass^-1) r
+static int32_t stokes_precond(agca_hier* h, const double* r, double* z) {
+    const StokesDims d = stokes_dims(h);
+    TRY(precondition(h, r, z));
+    HIPCHK(h, launch_div_elementwise(d.np, r + d.nu, h->st_mass, z + d.nu, h->st));
+    return AGCA_OK;
+}
+static int32_t stokes_norm(agca_hier* h, const double* x, double* out) {
+    double v = 0.0;
+    TRY(do_dot<double>(h, x, x, stokes_dims(h).tot, &v));
+    *out = std::sqrt(v);
+    return AGCA_OK;
+}
+// r = b - K x
+static int32_t stokes_residual(agca_hier* h, const double* b, const double* x, double* r) {
+    const int64_t tot = stokes_dims(h).tot;
+    TRY(stokes_apply(h, x, r));
+    HIPCHK(h, launch_axpby<double>(tot, 1.0, b, -1.0, r, h->st));
+    return AGCA_OK;
+}
+
+// Right-preconditioned flexible GMRES(m), modified Gram-Schmidt; the Arnoldi
+// coefficients stay on the device during orthogonalisation (one read-back per step).
+static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const double* b, double* x,
+                             double bn, double* rel_out, int* it_out, std::vector<double>& hist) {
+    const int64_t tot = stokes_dims(h).tot;
+    const int m = o->restart;
+    TRY(stokes_work(h, 2 * (int64_t)m + 3));
+    double* V = h->st_work;                 // m + 1 vectors
+    double* Z = V + (int64_t)(m + 1) * tot; // m vectors
+    double* w = Z + (int64_t)m * tot;
+    double* r = w + tot;
+    auto vec = [&](double* base, int i) { return base + (int64_t)i * tot; };
+    HIPCHK(h, launch_fill<double>(tot, 0.0, x, h->st));
+    HIPCHK(h, launch_axpby<double>(tot, 1.0, b, 0.0, r, h->st));
+    double rel = 0.0;
+    TRY(stokes_norm(h, r, &rel));
+    rel /= bn;
+    hist.push_back(rel);
+    int it = 0;
+    std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), col(m + 2);
+    auto Hm = [&](int i, int k) -> double& { return H[(size_t)i * m + k]; };
+    while (it < o->max_iter) {
+        double beta = 0.0;
+        TRY(stokes_norm(h, r, &beta));
+        HIPCHK(h, launch_axpby<double>(tot, 1.0 / beta, r, 0.0, vec(V, 0), h->st));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k_done = 0;
+        for (int k = 0; k < m; ++k) {
+            TRY(stokes_precond(h, vec(V, k), vec(Z, k)));
+            TRY(stokes_apply(h, vec(Z, k), w));
+            for (int i = 0; i <= k; ++i) {
+                HIPCHK(h, launch_dot_partial<double>(w, vec(V, i), tot, h->partial, h->nb_partial, h->st));
+                TRY(reduce_to(h, h->partial, h->nb_partial, i));
+                HIPCHK(h, launch_axpy_dev(tot, h->red + i, -1.0, vec(V, i), w, h->st));
+            }
+            HIPCHK(h, launch_dot_partial<double>(w, w, tot, h->partial, h->nb_partial, h->st));
+            TRY(reduce_to(h, h->partial, h->nb_partial, k + 1));
+            TRY(fetch(h, k + 2, col.data()));
+            for (int i = 0; i <= k; ++i) Hm(i, k) = col[i];
+            Hm(k + 1, k) = std::sqrt(col[k + 1]);
+            if (Hm(k + 1, k) > 0.0)
+                HIPCHK(h, launch_axpby<double>(tot, 1.0 / Hm(k + 1, k), w, 0.0, vec(V, k + 1), h->st));
+            for (int i = 0; i < k; ++i) {
+                const double t = cs[i] * Hm(i, k) + sn[i] * Hm(i + 1, k);
+                Hm(i + 1, k) = -sn[i] * Hm(i, k) + cs[i] * Hm(i + 1, k);
+                Hm(i, k) = t;
+            }
+            const double dd = std::hypot(Hm(k, k), Hm(k + 1, k));
+            cs[k] = Hm(k, k) / dd;
+            sn[k] = Hm(k + 1, k) / dd;
+            Hm(k, k) = dd;
+            Hm(k + 1, k) = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            ++it;
+            k_done = k + 1;
+            hist.push_back(std::fabs(g[k + 1]) / bn);
+            if (!std::isfinite(hist.back())) return fail(AGCA_E_NUMERIC, "FGMRES breakdown");
+            if (hist.back() <= o->tol || it >= o->max_iter) break;
+        }
+        // y = H^-1 g (upper triangular), x += Z y
+        std::vector<double> y(k_done);
+        for (int i = k_done - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int j = i + 1; j < k_done; ++j) t -= Hm(i, j) * y[j];
+            y[i] = t / Hm(i, i);
+        }
+        for (int i = 0; i < k_done; ++i) HIPCHK(h, launch_axpby<double>(tot, y[i], vec(Z, i), 1.0, x, h->st));
+        TRY(stokes_residual(h, b, x, r));
+        TRY(stokes_norm(h, r, &rel));
+        rel /= bn;
+        hist.back() = rel;
+        if (rel <= o->tol) break;
+    }
+    *rel_out = rel;
+    *it_out = it;
+    return AGCA_OK;
+}
+
+// Preconditioned MINRES (Paige-Saunders) with the true residual checked every step.
+static int32_t stokes_minres(agca_hier* h, const agca_stokes_opts* o, const double* b, double* x,
+                             double bn, double* rel_out, int* it_out, std::vector<double>& hist) {
+    const int64_t tot = stokes_dims(h).tot;
+    TRY(stokes_work(h, 8));
+    double* buf[8];
+    for (int i = 0; i < 8; ++i) buf[i] = h->st_work + (int64_t)i * tot;
+    double *r1 = buf[0], *r2 = buf[1], *y = buf[2], *v = buf[3], *w = buf[4], *w1 = buf[5],
+           *w2 = buf[6], *res = buf[7];
+    HIPCHK(h, launch_fill<double>(tot, 0.0, x, h->st));
+    HIPCHK(h, launch_axpby<double>(tot, 1.0, b, 0.0, r1, h->st));
+    TRY(stokes_precond(h, r1, y));
+    double t = 0.0;
+    TRY(do_dot<double>(h, r1, y, tot, &t));
+    const double beta1 = std::sqrt(t);
+    hist.push_back(1.0);
+    double rel = 1.0;
+    int it = 0;
+    if (beta1 == 0.0) {
+        *rel_out = 0.0;
+        *it_out = 0;
+        return AGCA_OK;
+    }
+    double oldb = 0.0, beta = beta1, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
+    HIPCHK(h, launch_fill<double>(tot, 0.0, w, h->st));
+    HIPCHK(h, launch_fill<double>(tot, 0.0, w2, h->st));
+    HIPCHK(h, launch_axpby<double>(tot, 1.0, r1, 0.0, r2, h->st));
+    for (it = 1; it <= o->max_iter; ++it) {
+        HIPCHK(h, launch_axpby<double>(tot, 1.0 / beta, y, 0.0, v, h->st));
+        TRY(stokes_apply(h, v, y));
+        if (it >= 2) HIPCHK(h, launch_axpby<double>(tot, -beta / oldb, r1, 1.0, y, h->st));
+        double alfa = 0.0;
+        TRY(do_dot<double>(h, v, y, tot, &alfa));
+        HIPCHK(h, launch_axpby<double>(tot, -alfa / beta, r2, 1.0, y, h->st));
+        // r1 <- r2, r2 <- y, y <- preconditioned r2 (into the old r1 storage)
+        double* old_r1 = r1;
+        r1 = r2;
+        r2 = y;
+        y = old_r1;
+        TRY(stokes_precond(h, r2, y));
+        oldb = beta;
+        TRY(do_dot<double>(h, r2, y, tot, &t));
+        beta = std::sqrt(t);
+        const double oldeps = epsln;
+        const double delta = cs * dbar + sn * alfa;
+        const double gbar = sn * dbar - cs * alfa;
+        epsln = sn * beta;
+        dbar = -cs * beta;
+        const double gamma = std::max(std::hypot(gbar, beta), 1e-300);
+        cs = gbar / gamma;
+        sn = beta / gamma;
+        const double phi = cs * phibar;
+        phibar = sn * phibar;
+        // w1 <- w2, w2 <- w, w <- (v - oldeps w1 - delta w2) / gamma (into the old w1 storage)
+        double* old_w1 = w1;
+        w1 = w2;
+        w2 = w;
+        w = old_w1;
+        HIPCHK(h, launch_axpby<double>(tot, 1.0 / gamma, v, 0.0, w, h->st));
+        HIPCHK(h, launch_axpby<double>(tot, -oldeps / gamma, w1, 1.0, w, h->st));
+        HIPCHK(h, launch_axpby<double>(tot, -delta / gamma, w2, 1.0, w, h->st));
+        HIPCHK(h, launch_axpby<double>(tot, phi, w, 1.0, x, h->st));
+        TRY(stokes_residual(h, b, x, res));
+        TRY(stokes_norm(h, res, &rel));
+        rel /= bn;
+        hist.push_back(rel);
+        if (!std::isfinite(rel)) return fail(AGCA_E_NUMERIC, "MINRES breakdown");
+        if (rel <= o->tol) break;
+    }
+    *rel_out = rel;
+    *it_out = std::min(it, o->max_iter);
+    return AGCA_OK;
+}
+
+int32_t agca_stokes_div(agca_hier* h, const double* u, double* q) {
+    TRY(stokes_ready(h));
+    if (!u || !q) return fail(AGCA_E_INVALID, "null pointer");
+    return stokes_div(h, u, q);
+}
+
+int32_t agca_stokes_grad(agca_hier* h, const double* p, double* v) {
+    TRY(stokes_ready(h));
+    if (!p || !v) return fail(AGCA_E_INVALID, "null pointer");
+    HIPCHK(h, launch_fill<double>(stokes_dims(h).nu, 0.0, v, h->st));
+    return stokes_grad_add(h, p, v);
+}
+
+int32_t agca_stokes_mass(agca_hier* h, double* m) {
+    TRY(stokes_ready(h));
+    if (!m) return fail(AGCA_E_INVALID, "null pointer");
+    HIPCHK(h, hipMemcpyAsync(m, h->st_mass, sizeof(double) * stokes_dims(h).np,
+                             hipMemcpyDeviceToDevice, h->st));
+    return AGCA_OK;
+}
+
+int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double* f, const double* g,
+                          double* u, double* p, agca_solve_stats* stats) {
+    TRY(stokes_ready(h));
+    if (!o || !f || !g || !u || !p || !stats) return fail(AGCA_E_INVALID, "null pointer");
+    if (o->max_iter < 0 || !(o->tol >= 0.0)) return fail(AGCA_E_INVALID, "bad solve options");
+    if (o->solver != AGCA_STOKES_FGMRES && o->solver != AGCA_STOKES_MINRES)
+        return fail(AGCA_E_INVALID, "unknown Stokes solver");
+    if (o->solver == AGCA_STOKES_FGMRES && (o->restart < 1 || o->restart > AGCA_RED_SLOTS - 2))
+        return fail(AGCA_E_INVALID, "restart must be in [1, 126]");
+    if (o->solver == AGCA_STOKES_MINRES && mg32(h))
+        return fail(AGCA_E_INVALID, "MINRES needs the FP64 V-cycle (a fixed SPD preconditioner)");
+    TRY(ensure_solver_vectors(h));
+    std::memset(stats, 0, sizeof(*stats));
+    const StokesDims d = stokes_dims(h);
+    // contiguous right-hand side and solution in the last two work vectors' place
+    const int64_t kry = (o->solver == AGCA_STOKES_FGMRES) ? 2 * (int64_t)o->restart + 3 : 8;
+    TRY(stokes_work(h, kry + 2));
+    double* bvec = h->st_work + kry * d.tot;
+    double* xvec = bvec + d.tot;
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(h, hipMemcpyAsync(bvec, f, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, launch_zero_boundary<double>(3, d.nf, bvec, h->st));
+    HIPCHK(h, hipMemcpyAsync(bvec + d.nu, g, sizeof(double) * d.np, hipMemcpyDeviceToDevice, h->st));
+    double bn = 0.0;
+    TRY(stokes_norm(h, bvec, &bn));
+    if (!std::isfinite(bn)) return fail(AGCA_E_NUMERIC, "non-finite right-hand side");
+    std::vector<double> hist;
+    double rel = 0.0;
+    int it = 0;
+    if (bn == 0.0) {
+        HIPCHK(h, launch_fill<double>(d.tot, 0.0, xvec, h->st));
+        hist.push_back(0.0);
+    } else if (o->solver == AGCA_STOKES_FGMRES) {
+        TRY(stokes_fgmres(h, o, bvec, xvec, bn, &rel, &it, hist));
+    } else {
+        TRY(stokes_minres(h, o, bvec, xvec, bn, &rel, &it, hist));
+    }
+    // pressure with zero mean (the constant is the kernel of B^T on free velocities)
+    double psum = 0.0;
+    {
+        double* ones = h->st_qf;   // scratch of at least np entries
+        HIPCHK(h, launch_fill<double>(d.np, 1.0, ones, h->st));
+        TRY(do_dot<double>(h, xvec + d.nu, ones, d.np, &psum));
+        HIPCHK(h, launch_axpby<double>(d.np, -psum / (double)d.np, ones, 1.0, xvec + d.nu, h->st));
+    }
+    HIPCHK(h, hipMemcpyAsync(u, xvec, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(p, xvec + d.nu, sizeof(double) * d.np, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    stats->iterations = it;
+    stats->rel_residual = rel;
+    stats->recursive_rel_residual = hist.empty() ? rel : hist.back();
+    stats->converged = rel <= o->tol || bn == 0.0;
+    for (size_t i = 0; i < hist.size() && i < (size_t)AGCA_MAX_HISTORY; ++i)
+        if (o->record_history) stats->history[i] = hist[i];
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!stats->converged) return fail(AGCA_E_NOCONV, "no convergence within max_iter");
+    return AGCA_OK;
+}
+
 }  // extern "C"
+

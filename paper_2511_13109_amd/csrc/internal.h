@@ -123,6 +123,17 @@ hipError_t launch_diagonal(int ncomp, int n, const double* nu, double scale, con
 template <typename T>
 hipError_t launch_invert_diag(int64_t count, const double* diag, T* dinv, hipStream_t st);
 
+// Stokes pieces (k_stokes.hip): velocity on the level with n cells, pressure on n/2
+hipError_t launch_stokes_div_fine(int n, const double* u, double* q, hipStream_t st);
+hipError_t launch_stokes_grad_fine_add(int n, const double* pf, double* out, hipStream_t st);
+hipError_t launch_stokes_mass_fine(int n, const double* nu, double* mf, hipStream_t st);
+hipError_t launch_restrict_all(int n_coarse, const double* qf, double* out, hipStream_t st);
+hipError_t launch_prolong_all(int n_fine, const double* pc, double* pf, hipStream_t st);
+hipError_t launch_div_elementwise(int64_t n, const double* num, const double* den, double* out,
+                                  hipStream_t st);
+hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,
+                           hipStream_t st);
+
 // adjoint gradient and load vector (finest level)
 hipError_t launch_grad(int ncomp, int n, const double* nu, double scale, const double* u,
                        const double* w, double* g, hipStream_t st);

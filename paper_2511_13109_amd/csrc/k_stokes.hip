@@ -1,0 +1,250 @@
+// Generalized Stokes pieces (paper Section 3.1, eqs. (3.3)-(3.5)): velocity P1 on the
+// finest level L (P1-iso-P2), pressure P1 on level L-1 with every node of that level a
+// degree of freedom.
+//
+//   B = - integral psi_k div Phi_j = -P^T B_L,
+//   (B_L u)_v = sum over the simplices d containing v of |d|/4 div_d(u),
+// because psi_k is linear on every fine simplex (its mean over d is the mean of its
+// vertex values, which the interpolation P of eq. (2.4) gives).  On the Kuhn lattice
+// |d| = h^3/6 and the barycentric gradients are grad(s, a, c) / h (kuhn.h), so
+//   (B_L u)_v = h^2/24 sum_{d containing v} sum_{b, c} grad(s, b, c) u_c(b).
+// B^T p = -B_L^T (P p).  The pressure preconditioner is the lumped mass weighted by
+// 1/nu, m = P^T m_L, m_L(v) = h^3/24 sum_{d containing v} 1/nu_d.
+//
+// Every kernel gathers per node (no atomics): the simplices around a node are the
+// ones of the 8 cells sharing it whose path passes through it, and their vertices
+// are the node's 15 lattice neighbours (kuhn.h nbr_of).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "kuhn.h"
+
+namespace agca {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ void node_xyz(int64_t p, int n, int& x, int& y, int& z) {
+    const int64_t n1 = n + 1;
+    x = (int)(p % n1);
+    y = (int)((p / n1) % n1);
+    z = (int)(p / (n1 * n1));
+}
+
+// cell of node (x,y,z) that has the node as its corner k, and whether it exists
+__device__ __forceinline__ bool cell_of(int n, int x, int y, int z, int k, int64_t& cell) {
+    const int cx = x - (k & 1), cy = y - ((k >> 1) & 1), cz = z - ((k >> 2) & 1);
+    cell = cx + (int64_t)n * (cy + (int64_t)n * cz);
+    return cx >= 0 && cy >= 0 && cz >= 0 && cx < n && cy < n && cz < n;
+}
+
+// q_v = -(B_L u)_v on every fine node (velocity boundary values are zero)
+__global__ void __launch_bounds__(NT)
+k_div_fine(int n, const double* __restrict__ u, double* __restrict__ q) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= N) return;
+    int x, y, z;
+    node_xyz(p, n, x, y, z);
+    // velocity at the 15 neighbours, zero outside the interior
+    double U[15][3];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+        const int m = nbr_mask(k), sg = nbr_sign(k);
+        const int qx = x + sg * (m & 1), qy = y + sg * ((m >> 1) & 1), qz = z + sg * (m >> 2);
+        const bool in = qx > 0 && qy > 0 && qz > 0 && qx < n && qy < n && qz < n;
+        const int64_t qi = in ? qx + n1 * (qy + n1 * (int64_t)qz) : 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) U[k][c] = in ? u[c * N + qi] : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int64_t cell;
+        if (!cell_of(n, x, y, z, k, cell)) continue;
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                if (path_corner(s, a) != k) continue;
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        if (grad(s, b, c) != 0) acc += (double)grad(s, b, c) * U[nbr_of(s, a, b)][c];
+            }
+    }
+    const double h = 1.0 / n;
+    q[p] = -(h * h / 24.0) * acc;
+}
+
+// out[(c, j)] += -(B_L^T pf)_(j, c) on interior fine nodes
+__global__ void __launch_bounds__(NT)
+k_grad_fine_add(int n, const double* __restrict__ pf, double* __restrict__ out) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= N) return;
+    int x, y, z;
+    node_xyz(p, n, x, y, z);
+    if (x == 0 || y == 0 || z == 0 || x == n || y == n || z == n) return;
+    double P[15];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+        const int m = nbr_mask(k), sg = nbr_sign(k);
+        // interior node: every neighbour lies in the lattice
+        P[k] = pf[(x + sg * (m & 1)) + n1 * ((y + sg * ((m >> 1) & 1)) + n1 * (int64_t)(z + sg * (m >> 2)))];
+    }
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                if (path_corner(s, a) != k) continue;
+                double sum = 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) sum += P[nbr_of(s, a, b)];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (grad(s, a, c) != 0) acc[c] += (double)grad(s, a, c) * sum;
+            }
+    }
+    const double h = 1.0 / n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * N + p] -= (h * h / 24.0) * acc[c];
+}
+
+// m_L(v) = h^3/24 sum_{d containing v} 1/nu_d on every fine node
+__global__ void __launch_bounds__(NT)
+k_mass_fine(int n, const double* __restrict__ nu, double* __restrict__ mf) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= N) return;
+    int x, y, z;
+    node_xyz(p, n, x, y, z);
+    const int64_t cells = (int64_t)n * n * n;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int64_t cell;
+        if (!cell_of(n, x, y, z, k, cell)) continue;
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (path_corner(s, a) == k) acc += 1.0 / nu[elem_slot(s, cell, cells)];
+    }
+    const double h = 1.0 / n;
+    mf[p] = (h * h * h / 24.0) * acc;
+}
+
+// out = P^T qf over every node of the coarse level (nc cells), boundary included
+__global__ void __launch_bounds__(NT)
+k_restrict_all(int nc, const double* __restrict__ qf, double* __restrict__ out) {
+    const int64_t nc1 = nc + 1, Nc = nc1 * nc1 * nc1;
+    const int nf = 2 * nc;
+    const int64_t nf1 = nf + 1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= Nc) return;
+    int x, y, z;
+    node_xyz(p, nc, x, y, z);
+    const int X = 2 * x, Y = 2 * y, Z = 2 * z;
+    double half = 0.0;
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+        const int dx = m & 1, dy = (m >> 1) & 1, dz = m >> 2;
+#pragma unroll
+        for (int sg = -1; sg <= 1; sg += 2) {
+            const int qx = X + sg * dx, qy = Y + sg * dy, qz = Z + sg * dz;
+            if (qx >= 0 && qy >= 0 && qz >= 0 && qx <= nf && qy <= nf && qz <= nf)
+                half += qf[qx + nf1 * (qy + nf1 * (int64_t)qz)];
+        }
+    }
+    out[p] = qf[X + nf1 * (Y + nf1 * (int64_t)Z)] + 0.5 * half;
+}
+
+// pf = P pc on every node of the fine level (nf cells), boundary included
+__global__ void __launch_bounds__(NT)
+k_prolong_all(int nf, const double* __restrict__ pc, double* __restrict__ pf) {
+    const int nc = nf / 2;
+    const int64_t nc1 = nc + 1;
+    const int64_t Nf = (int64_t)(nf + 1) * (nf + 1) * (nf + 1);
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= Nf) return;
+    int x, y, z;
+    node_xyz(p, nf, x, y, z);
+    const int dx = x & 1, dy = y & 1, dz = z & 1;
+    const int64_t lo = ((x - dx) >> 1) + nc1 * (((y - dy) >> 1) + nc1 * (int64_t)((z - dz) >> 1));
+    const int64_t hi = ((x + dx) >> 1) + nc1 * (((y + dy) >> 1) + nc1 * (int64_t)((z + dz) >> 1));
+    pf[p] = (dx | dy | dz) ? 0.5 * (pc[lo] + pc[hi]) : pc[lo];
+}
+
+__global__ void __launch_bounds__(NT)
+k_div_elementwise(int64_t n, const double* __restrict__ num, const double* __restrict__ den,
+                  double* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) out[i] = num[i] / den[i];
+}
+
+// y += sign * coef[0] * x with the coefficient read from device memory
+__global__ void __launch_bounds__(NT)
+k_axpy_dev(int64_t n, const double* __restrict__ coef, double sign, const double* __restrict__ x,
+           double* __restrict__ y) {
+    const double a = sign * coef[0];
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) y[i] += a * x[i];
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+unsigned grid_stride(int64_t n) {
+    const int64_t g = (n + NT - 1) / NT;
+    return (unsigned)(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
+}  // namespace
+
+hipError_t launch_stokes_div_fine(int n, const double* u, double* q, hipStream_t st) {
+    if (!u || !q || n < 2) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_div_fine, dim3(grid_for(N)), dim3(NT), 0, st, n, u, q);
+    return hipGetLastError();
+}
+hipError_t launch_stokes_grad_fine_add(int n, const double* pf, double* out, hipStream_t st) {
+    if (!pf || !out || n < 2) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_grad_fine_add, dim3(grid_for(N)), dim3(NT), 0, st, n, pf, out);
+    return hipGetLastError();
+}
+hipError_t launch_stokes_mass_fine(int n, const double* nu, double* mf, hipStream_t st) {
+    if (!nu || !mf || n < 2) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_mass_fine, dim3(grid_for(N)), dim3(NT), 0, st, n, nu, mf);
+    return hipGetLastError();
+}
+hipError_t launch_restrict_all(int n_coarse, const double* qf, double* out, hipStream_t st) {
+    if (!qf || !out || n_coarse < 1) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n_coarse + 1) * (n_coarse + 1) * (n_coarse + 1);
+    hipLaunchKernelGGL(k_restrict_all, dim3(grid_for(N)), dim3(NT), 0, st, n_coarse, qf, out);
+    return hipGetLastError();
+}
+hipError_t launch_prolong_all(int n_fine, const double* pc, double* pf, hipStream_t st) {
+    if (!pc || !pf || n_fine < 2) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n_fine + 1) * (n_fine + 1) * (n_fine + 1);
+    hipLaunchKernelGGL(k_prolong_all, dim3(grid_for(N)), dim3(NT), 0, st, n_fine, pc, pf);
+    return hipGetLastError();
+}
+hipError_t launch_div_elementwise(int64_t n, const double* num, const double* den, double* out,
+                                  hipStream_t st) {
+    if (!num || !den || !out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_div_elementwise, dim3(grid_stride(n)), dim3(NT), 0, st, n, num, den, out);
+    return hipGetLastError();
+}
+hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,
+                           hipStream_t st) {
+    if (!coef || !x || !y) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_axpy_dev, dim3(grid_stride(n)), dim3(NT), 0, st, n, coef, sign, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace agca

@@ -129,8 +129,13 @@ __global__ void __launch_bounds__(NT)
 k_axpby(int64_t n, double a, const T* __restrict__ x, double b, T* __restrict__ y) {
     const int64_t stride = (int64_t)gridDim.x * NT;
     const T ta = T(a), tb = T(b);
-    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride)
-        y[i] = ta * x[i] + tb * y[i];
+    // b = 0 overwrites y without reading it (y may be uninitialised)
+    if (b == 0.0) {
+        for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) y[i] = ta * x[i];
+    } else {
+        for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride)
+            y[i] = ta * x[i] + tb * y[i];
+    }
 }
 
 __device__ __forceinline__ void block_sum_store(double v, double* __restrict__ out) {

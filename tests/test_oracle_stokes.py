@@ -1,0 +1,100 @@
+"""Pins of the oracle's Stokes pieces (paper Section 3.1): divergence B, lumped 1/nu
+pressure mass, and the block-preconditioned FGMRES / MINRES solves.
+
+B and m are checked against quantities fixed by calculus and by an independent
+quadrature: B^T 1 = 0 on free velocities (divergence theorem), B u = -c int psi_k
+for a linear field with constant divergence c, brute-force Gauss quadrature of
+psi_k div Phi_j with psi_k located point by point in the coarse mesh, and
+m_k = int psi_k for nu = 1.  The Krylov solutions must equal the bordered direct
+solve.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fem, mesh, mg, stokes
+
+# 4-point Gauss rule on the reference tetrahedron, exact for degree 2
+_A, _B = 0.5854101966249685, 0.1381966011250105
+_GP = np.array([[_A, _B, _B, _B], [_B, _A, _B, _B], [_B, _B, _A, _B], [_B, _B, _B, _A]])
+
+
+def _hat_integrals(lv):
+    """int psi_k over the domain: sum over elements containing k of |e| / 4."""
+    _, vol = fem.element_geometry(lv.coords[lv.tets])
+    out = np.zeros((lv.n + 1) ** 3)
+    np.add.at(out, lv.node_id[lv.tets].ravel(), np.repeat(vol / 4.0, 4))
+    return out
+
+
+def test_divergence_theorem_and_linear_fields():
+    levels = mesh.hierarchy(3)
+    c, f = levels[2], levels[3]
+    B = stokes.div_matrix(c, f)
+    nn = (f.n + 1) ** 3
+    free = fem.free_dofs(f, 3)
+    ones = np.ones(B.shape[0])
+    bt1 = (B.T @ ones)[free]
+    assert np.abs(bt1).max() <= 1e-15 * np.abs(B).max() * 10
+    X = np.zeros((nn, 3))
+    X[f.node_id] = f.coords
+    hat = _hat_integrals(c)
+    for coef, div in (((1, 0, 0), 1.0), ((1, 2, 3), 6.0), ((0, -1, 0), -1.0)):
+        u = np.concatenate([coef[k] * X[:, k] for k in range(3)])
+        assert np.allclose(B @ u, -div * hat, rtol=0, atol=1e-14)
+
+
+def test_divergence_brute_force_quadrature():
+    levels = mesh.hierarchy(1)
+    c, f = levels[0], levels[1]
+    B = stokes.div_matrix(c, f).toarray()
+    nn_c, nn_f = (c.n + 1) ** 3, (f.n + 1) ** 3
+    ref = np.zeros((nn_c, 3 * nn_f))
+    C4 = c.coords[c.tets]
+    Minv = np.linalg.inv(np.concatenate([np.ones((C4.shape[0], 1, 4)), C4.transpose(0, 2, 1)], axis=1))
+    g, vol = fem.element_geometry(f.coords[f.tets])
+    for t in range(f.tets.shape[0]):
+        x4 = f.coords[f.tets[t]]
+        for q in range(4):
+            xq = _GP[q] @ x4
+            lam = Minv @ np.concatenate([[1.0], xq])            # coarse barycentrics, all tets
+            tc = np.nonzero(np.all(lam > -1e-12, axis=1))[0][0]
+            psi = np.zeros(nn_c)
+            psi[c.node_id[c.tets[tc]]] = lam[tc]
+            for b in range(4):
+                for k in range(3):
+                    ref[:, k * nn_f + f.node_id[f.tets[t, b]]] -= vol[t] / 4.0 * psi * g[t, b, k]
+    assert np.abs(B - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_lumped_mass():
+    levels = mesh.hierarchy(3)
+    c, f = levels[2], levels[3]
+    m1 = stokes.lumped_mass(c, f, np.ones(f.tets.shape[0]))
+    assert np.allclose(m1, _hat_integrals(c), rtol=1e-13, atol=0)
+    rng = np.random.default_rng(0)
+    nu = np.exp(rng.uniform(-5, 5, f.tets.shape[0]))
+    m = stokes.lumped_mass(c, f, nu)
+    _, vol = fem.element_geometry(f.coords[f.tets])
+    assert abs(m.sum() - (vol / nu[f.elem_id]).sum()) <= 1e-13 * m.sum()
+    assert np.all(m > 0)
+
+
+@pytest.mark.parametrize("solver", ["fgmres", "minres"])
+def test_krylov_solutions_equal_direct(solver):
+    from workloads import Sinkers
+    L = 2
+    levels = mesh.hierarchy(L)
+    field = Sinkers(2, 3, radius=0.2, width=2.0 / 2 ** (L + 1), contrast=1e4)
+    nu = [field.nu(mesh.centroids_canonical(lv)) for lv in levels]
+    H = mg.build(L, nu, 3, levels=levels)
+    S = stokes.StokesSystem(H)
+    f = np.asarray(field.force(mesh.centroids_canonical(levels[L]), 3))
+    bu = fem.load_vector(levels[L], f, 3)[H.free[L]]
+    b = np.concatenate([bu, np.zeros(S.np_)])
+    x_ref = S.direct(b)
+    assert np.linalg.norm(S.K @ x_ref - b) <= 1e-10 * np.linalg.norm(b)
+    assert np.abs(x_ref[S.nu_:].mean()) <= 1e-14 * np.abs(x_ref[S.nu_:]).max()
+    res = S.solve(b, solver, tol=1e-10, restart=30, maxit=2000)
+    assert res.converged, (solver, res.iterations)
+    assert np.linalg.norm(res.x - x_ref) <= 1e-6 * np.linalg.norm(x_ref)

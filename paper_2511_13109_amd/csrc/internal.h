@@ -38,7 +38,7 @@ hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, co
 // v = A u and per-workgroup partial sums of u . v (FP64 only); *nblocks receives the count
 hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u, double* out,
                            double* partial, int* nblocks, hipStream_t st);
-// number of workgroups of the element loop on a level with n cells
+// upper bound on the workgroups of the element loop on a level with n cells
 int cube_grid_blocks(int n);
 
 // assembled 15-point stencil of a coarse level (FP64): DCA on unflagged simplices,

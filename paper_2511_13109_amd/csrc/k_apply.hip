@@ -3,18 +3,19 @@
 // MODE_JACOBI0 folds the first sweep from a zero guess (u = omega D^-1 b, formed
 // while loading) into the second, so the first iterate is never stored.
 //
-// Layout of the work: a 16 x 16 workgroup owns a 16 x 16 column of lattice
-// cells and marches up through a chunk of z layers.  At every step a thread
-// evaluates its cell's 6 simplices once (cube_math.h), producing contributions
-// to the cell's 8 corners.  Corner sums are formed without atomics:
-//   * x neighbours are lanes of the same 16-lane DPP row -> row_shr:1,
+// Layout of the work: a workgroup of 256 threads owns a TX x TY column of lattice
+// cells (32 x 8 by default) and marches up through a chunk of z layers.  At every
+// step a thread evaluates its cell's 6 simplices once (cube_math.h), producing
+// contributions to the cell's 8 corners.  Corner sums are formed without atomics:
+//   * x neighbours are adjacent lanes -> DPP wave_shr:1 (row_shr:1 for 16-wide tiles),
 //   * y neighbours go through a small LDS buffer,
 //   * the z direction is carried in registers from one step to the next.
-// Each node is therefore finalised by exactly one thread; the extra first row
-// and column of threads compute the halo cells needed by the tile's first
-// nodes (15 x 15 nodes finalised per workgroup).  The u values of the cell
-// corners come from a double-buffered LDS tile, so one barrier per z step
-// suffices.  Every output node is written once, with coalesced stores.
+// Each node is therefore finalised by exactly one thread; the first row and column
+// of threads compute the halo cells needed by the tile's first nodes ((TX-1) x (TY-1)
+// nodes finalised per workgroup).  The u values of the cell corners come from a
+// three-layer LDS ring filled a step ahead, so one barrier per z step suffices; the
+// global loads of a step are issued before its arithmetic and consumed after it.
+// Every output node is written once, with coalesced stores.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -25,11 +26,19 @@
 namespace agca {
 namespace {
 
-// 16 x 16 cells per workgroup (15 x 15 finalised); a 16-lane DPP row is one tile row.
-constexpr int TX = 16;
-constexpr int TY = 16;
+// TX x TY cells per workgroup, TX * TY = 256; 32-wide rows read 264-byte segments of
+// u per node row (16-wide ones 136 bytes), which measured faster beyond 129^3 nodes.
+#ifndef AGCA_CUBE_TX
+#define AGCA_CUBE_TX 32
+#endif
+constexpr int TX = AGCA_CUBE_TX;
+constexpr int TY = 256 / TX;
 constexpr int NTHREADS = TX * TY;
 
+// x neighbour exchange: DPP row_shr:1 within 16-lane rows when a tile row is 16 lanes,
+// wave_shr:1 across the wavefront when it is 32 or 64 lanes (the first lane of every
+// tile row is a halo column whose shifted-in value is never used)
+constexpr int kShr1 = TX == 16 ? 0x111 : 0x138;
 template <typename T>
 __device__ __forceinline__ T shr1_row(T v) {
     // value of the lane one to the left in the same 16-lane row (0 for the row's first lane)
@@ -37,59 +46,74 @@ __device__ __forceinline__ T shr1_row(T v) {
         const unsigned long long bits = __double_as_longlong(v);
         int lo = (int)(bits & 0xffffffffull);
         int hi = (int)(bits >> 32);
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xF, 0xF, true);
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xF, 0xF, true);
+        lo = __builtin_amdgcn_update_dpp(0, lo, kShr1, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_update_dpp(0, hi, kShr1, 0xF, 0xF, true);
         return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
     } else {
         int b = __float_as_int(v);
-        b = __builtin_amdgcn_update_dpp(0, b, 0x111, 0xF, 0xF, true);
+        b = __builtin_amdgcn_update_dpp(0, b, kShr1, 0xF, 0xF, true);
         return __int_as_float(b);
     }
 }
 
-// the 6 coefficients of a cell in the internal per-element layout: one contiguous
-// 6-value run (vector loads) or six planes `stride` apart
 __device__ __forceinline__ float bf16_to_float(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
-template <typename T>
-__device__ __forceinline__ void load_nu6(const double* __restrict__ p, int64_t stride, T (&w)[6],
-                                         T scale) {
-    if constexpr (AGCA_ELEM_SOA) {
+
+// The six coefficients of a cell as loaded (in their storage type), decoded only when
+// used: a select or conversion right after a load would make the wavefront wait for
+// it at once.  AoS: three 16-byte (FP64), 8-byte (FP32) or 4-byte (BF16) loads.
+template <typename NT>
+struct RawNu;
+template <>
+struct RawNu<double> {
+    double v[6];
+    __device__ __forceinline__ void load(const double* __restrict__ p, int64_t stride) {
+        if constexpr (AGCA_ELEM_SOA) {
 #pragma unroll
-        for (int s = 0; s < 6; ++s) w[s] = T(p[s * stride]) * scale;
-    } else {
-        const double2* q = reinterpret_cast<const double2*>(p);
-        const double2 a = q[0], b = q[1], c = q[2];
-        w[0] = T(a.x) * scale; w[1] = T(a.y) * scale; w[2] = T(b.x) * scale;
-        w[3] = T(b.y) * scale; w[4] = T(c.x) * scale; w[5] = T(c.y) * scale;
+            for (int s = 0; s < 6; ++s) v[s] = p[s * stride];
+        } else {
+            const double2* q = reinterpret_cast<const double2*>(p);
+            const double2 a = q[0], b = q[1], c = q[2];
+            v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y;
+        }
     }
-}
-template <typename T>
-__device__ __forceinline__ void load_nu6(const float* __restrict__ p, int64_t stride, T (&w)[6],
-                                         T scale) {
-    if constexpr (AGCA_ELEM_SOA) {
+    template <typename T>
+    __device__ __forceinline__ T get(int s) const { return T(v[s]); }
+};
+template <>
+struct RawNu<float> {
+    float v[6];
+    __device__ __forceinline__ void load(const float* __restrict__ p, int64_t stride) {
+        if constexpr (AGCA_ELEM_SOA) {
 #pragma unroll
-        for (int s = 0; s < 6; ++s) w[s] = T(p[s * stride]) * scale;
-    } else {
-        const float2* q = reinterpret_cast<const float2*>(p);
-        const float2 a = q[0], b = q[1], c = q[2];
-        w[0] = T(a.x) * scale; w[1] = T(a.y) * scale; w[2] = T(b.x) * scale;
-        w[3] = T(b.y) * scale; w[4] = T(c.x) * scale; w[5] = T(c.y) * scale;
+            for (int s = 0; s < 6; ++s) v[s] = p[s * stride];
+        } else {
+            const float2* q = reinterpret_cast<const float2*>(p);
+            const float2 a = q[0], b = q[1], c = q[2];
+            v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y;
+        }
     }
-}
-template <typename T>
-__device__ __forceinline__ void load_nu6(const uint16_t* __restrict__ p, int64_t stride, T (&w)[6],
-                                         T scale) {
-    if constexpr (AGCA_ELEM_SOA) {
+    template <typename T>
+    __device__ __forceinline__ T get(int s) const { return T(v[s]); }
+};
+template <>
+struct RawNu<uint16_t> {
+    uint32_t w[6];  // bf16 bits in the low half (SoA) or packed pairs in w[0..2] (AoS)
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ p, int64_t stride) {
+        if constexpr (AGCA_ELEM_SOA) {
 #pragma unroll
-        for (int s = 0; s < 6; ++s) w[s] = T(bf16_to_float(p[s * stride])) * scale;
-    } else {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
-        const uint32_t a = q[0], b = q[1], c = q[2];
-        w[0] = T(bf16_to_float(a & 0xffffu)) * scale; w[1] = T(bf16_to_float(a >> 16)) * scale;
-        w[2] = T(bf16_to_float(b & 0xffffu)) * scale; w[3] = T(bf16_to_float(b >> 16)) * scale;
-        w[4] = T(bf16_to_float(c & 0xffffu)) * scale; w[5] = T(bf16_to_float(c >> 16)) * scale;
+            for (int s = 0; s < 6; ++s) w[s] = p[s * stride];
+        } else {
+            const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+            w[0] = q[0]; w[1] = q[1]; w[2] = q[2];
+        }
     }
-}
+    template <typename T>
+    __device__ __forceinline__ T get(int s) const {
+        if constexpr (AGCA_ELEM_SOA) return T(bf16_to_float(w[s] & 0xffffu));
+        const uint32_t x = w[s >> 1];
+        return T(bf16_to_float((s & 1) ? (x >> 16) : (x & 0xffffu)));
+    }
+};
 
 // Workgroup -> tile mapping.  Consecutive workgroups are dispatched round-robin
 // to the 8 XCDs, each with its own L2; remapping the linear id so that every XCD
@@ -112,6 +136,20 @@ __device__ __forceinline__ void tile_of(int gx, int gy, int gz, int& bx, int& by
 
 #ifndef AGCA_CUBE_PREFETCH_NODE
 #define AGCA_CUBE_PREFETCH_NODE 1
+#endif
+// issue the u-tile loads of a layer right after the previous step's barrier (before
+// its output phase) instead of at the top of the step that stores them
+#ifndef AGCA_CUBE_EARLY_TILE
+#define AGCA_CUBE_EARLY_TILE 1
+#endif
+// right-hand side and diagonal of the step's output nodes loaded at the top of the step
+// (their use follows the step's arithmetic) instead of just before the output
+#ifndef AGCA_CUBE_NODE_EARLY
+#define AGCA_CUBE_NODE_EARLY 0
+#endif
+// coefficient loads issued this many steps ahead of their use (1 or 2)
+#ifndef AGCA_CUBE_NU_AHEAD
+#define AGCA_CUBE_NU_AHEAD 1
 #endif
 #ifndef AGCA_CUBE_WAVES_F64V
 #define AGCA_CUBE_WAVES_F64V 3
@@ -140,7 +178,11 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
        const T* __restrict__ u, const NT* __restrict__ nu, const int32_t* __restrict__ blk,
        const T* __restrict__ yblk, const T* __restrict__ b, const T* __restrict__ dinv,
        T* __restrict__ out, const T scale, const T omega, double* __restrict__ partial) {
-    __shared__ T ubuf[2][NC][TY + 1][TX + 1];
+    // node layers of u: layer j lives in buffer (j + 3) % 3, so a step reads two
+    // buffers while the third receives the layer two steps ahead
+    // (TX+1) x (TY+1) nodes per layer and component, x fastest, plus 64 slots that
+    // absorb the second tile store of the wavefronts that have no second entry
+    __shared__ T ubuf[3][NC][(TX + 1) * (TY + 1) + 64];
     __shared__ T ybuf[2][NC][2][TY][TX];
     double dot_acc = 0.0;  // MODE_APPLY_DOT: this thread's share of u . (A u)
 
@@ -161,13 +203,18 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     // outside the interior are replaced by zero afterwards, so the loop has no
     // divergent branches around memory accesses.
     // u tile (TX+1) x (TY+1) per layer: entry tid for every thread, entry NTHREADS + tid
-    // for the first wavefronts (duplicates of the last entry write the same value).
+    // for the first wavefronts.  Every thread issues the second load (the others at a
+    // clamped duplicate address, a cache hit) so that no branch surrounds the loads
+    // and the prefetched values stay in registers; only the first wavefronts store it.
     constexpr int TW = TX + 1;
     constexpr int TE = (TX + 1) * (TY + 1);
     constexpr int NB = ((TE - NTHREADS + 63) / 64) * 64;  // whole wavefronts
     const int qa = tid;
     const int qb = min(NTHREADS + tid, TE - 1);
     const bool has_b = tid < NB;
+    // stores of the second entry are unconditional (a branch would pull its loads
+    // into it): lanes without one write a per-lane slot past the tile, never read
+    const int qb_store = has_b ? qb : TE + (tid & 63);
     // Tile node q of this thread: offset x + (n+1) y of the clamped node within a z layer.
     int at_a, at_b;
     bool ina, inb;
@@ -179,40 +226,37 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     };
     tile_node(qa, at_a, ina);
     tile_node(qb, at_b, inb);
-    auto load_tile = [&](int z, T (&va)[NC], T (&vb)[NC]) {
-        const bool zin = z > 0 && z < n;
+    // The loads of a layer are issued a step before the layer is staged in LDS and are
+    // consumed (masked, scaled, written to LDS) only at the end of that step, so that
+    // their latency overlaps the step's arithmetic.
+    struct TileRaw {
+        T a[NC], b[NC];    // u (or, for MODE_JACOBI0, the right-hand side) at entries qa, qb
+        T da[NC], db[NC];  // MODE_JACOBI0: inverse diagonal at entries qa, qb
+    };
+    auto load_tile = [&](int z, TileRaw& t) {
         const int64_t off = (int64_t)min(max(z, 0), n) * layer;
-        if constexpr (MODE == MODE_JACOBI0) {
-            // the first sweep from zero, x1 = omega D^-1 b
-            const T* pd = dinv + off;
-            const T* pbv = b + off;
+        const T* pv = (MODE == MODE_JACOBI0 ? b : u) + off;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const T a = omega * pd[c * N + at_a] * pbv[c * N + at_a];
-                va[c] = (ina && zin) ? a : T(0);
-                if (has_b) {
-                    const T bb = omega * pd[c * N + at_b] * pbv[c * N + at_b];
-                    vb[c] = (inb && zin) ? bb : T(0);
-                }
-            }
-        } else {
-            const T* pu = u + off;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const T a = pu[c * N + at_a];
-                va[c] = (ina && zin) ? a : T(0);
-                if (has_b) {
-                    const T bb = pu[c * N + at_b];
-                    vb[c] = (inb && zin) ? bb : T(0);
-                }
+        for (int c = 0; c < NC; ++c) {
+            t.a[c] = pv[c * N + at_a];
+            t.b[c] = pv[c * N + at_b];
+            if constexpr (MODE == MODE_JACOBI0) {
+                t.da[c] = dinv[off + c * N + at_a];
+                t.db[c] = dinv[off + c * N + at_b];
             }
         }
     };
-    auto store_tile = [&](int buf, const T (&va)[NC], const T (&vb)[NC]) {
+    auto store_tile = [&](int buf, int z, const TileRaw& t) {
+        const bool zin = z > 0 && z < n;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            (&ubuf[buf][c][0][0])[qa] = va[c];
-            if (has_b) (&ubuf[buf][c][0][0])[qb] = vb[c];
+            T va = t.a[c], vb = t.b[c];
+            if constexpr (MODE == MODE_JACOBI0) {  // the first sweep from zero, x1 = omega D^-1 b
+                va = omega * t.da[c] * va;
+                vb = omega * t.db[c] * vb;
+            }
+            ubuf[buf][c][qa] = (ina && zin) ? va : T(0);
+            ubuf[buf][c][qb_store] = (inb && zin) ? vb : T(0);
         }
     };
 
@@ -228,19 +272,25 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     constexpr int64_t kSlotsPerCell = AGCA_ELEM_SOA ? 1 : 6;  // z-layer stride factor
     const int64_t col = min(max(cx, 0), n) + n1 * min(max(cy, 0), n);
 
-    auto load_cell = [&](int z, T (&w)[6], int32_t (&bi)[6]) {
-        const bool ok = col_ok && z >= 0 && z < n;
+    struct RawCell {
+        RawNu<NT> nu;
+        int32_t bi[6];
+        bool ok;
+    };
+    auto load_cell = [&](int z, RawCell& r) {
+        r.ok = col_ok && z >= 0 && z < n;
         const int64_t off = (int64_t)min(max(z, 0), n - 1) * clayer * kSlotsPerCell;
-        T tmp[6];
-        load_nu6(pnu + off, cells, tmp, scale);
-#pragma unroll
-        for (int s = 0; s < 6; ++s) w[s] = ok ? tmp[s] : T(0);
+        r.nu.load(pnu + off, cells);
         if constexpr (BLK) {
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                const int32_t v = pblk[off + elem_slot(s, 0, cells)];
-                bi[s] = ok ? v : -1;
-            }
+            for (int s = 0; s < 6; ++s) r.bi[s] = pblk[off + elem_slot(s, 0, cells)];
+        }
+    };
+    auto decode_cell = [&](const RawCell& r, T (&w)[6], int32_t (&bi)[6]) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            w[s] = r.ok ? r.nu.template get<T>(s) * scale : T(0);
+            if constexpr (BLK) bi[s] = r.ok ? r.bi[s] : -1;
         }
     };
     auto load_node = [&](int z, T (&bq)[NC], T (&dq)[NC]) {
@@ -264,24 +314,22 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
         }
     };
 
+    auto bidx = [](int layer) { return (layer + 3) % 3; };
     {
-        T va[NC], vb[NC];
-        load_tile(Z0 - 1, va, vb);
-        store_tile((Z0 + 1) & 1, va, vb);
-        load_tile(Z0, va, vb);
-        store_tile(Z0 & 1, va, vb);
+        TileRaw t;
+        load_tile(Z0 - 1, t);
+        store_tile(bidx(Z0 - 1), Z0 - 1, t);
+        load_tile(Z0, t);
+        store_tile(bidx(Z0), Z0, t);
     }
-    T w_cur[6];
-    int32_t bi_cur[6];
-    load_cell(Z0 - 1, w_cur, bi_cur);
+    RawCell rc;  // the cell layer of the coming step, loaded a step ahead
+    load_cell(Z0 - 1, rc);
+    RawCell rn;  // with two steps ahead: the layer after it
+    if constexpr (AGCA_CUBE_NU_AHEAD == 2) load_cell(Z0 <= zend ? Z0 : -1, rn);
+    TileRaw nxt;  // the node layer two ahead of the coming step
+    if constexpr (AGCA_CUBE_EARLY_TILE) load_tile(Z0 + 1, nxt);
     T bq[NC], dq[NC];
     load_node(Z0 - 1, bq, dq);
-    __syncthreads();
-    T Ulo[4][NC];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) Ulo[k][c] = ubuf[(Z0 + 1) & 1][c][ty + (k >> 1)][tx + (k & 1)];
     __syncthreads();
 
     T carry[NC];
@@ -289,24 +337,35 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     for (int c = 0; c < NC; ++c) carry[c] = T(0);
 
     for (int z = Z0 - 1; z <= zend; ++z) {
-        const int cur = (z + 1) & 1;  // buffer holding layer z+1
+        const int lo = bidx(z), hi = bidx(z + 1);  // buffers holding layers z and z+1
         T U[8][NC];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                U[k][c] = Ulo[k][c];
-                U[k + 4][c] = ubuf[cur][c][ty + (k >> 1)][tx + (k & 1)];
+                U[k][c] = ubuf[lo][c][(ty + (k >> 1)) * (TX + 1) + tx + (k & 1)];
+                U[k + 4][c] = ubuf[hi][c][(ty + (k >> 1)) * (TX + 1) + tx + (k & 1)];
             }
+        T w_cur[6];
+        int32_t bi_cur[6];
+        decode_cell(rc, w_cur, bi_cur);
+        T self[NC];  // u at this thread's output node (cell corner 0)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) self[c] = U[0][c];
         // issue the next step's loads first so that they overlap this step's work
-        const bool need_next = z + 2 <= zend + 1;  // block-uniform
-        T va[NC], vb[NC];
-        if (need_next) load_tile(z + 2, va, vb);
-        T w_nxt[6];
-        int32_t bi_nxt[6];
-        load_cell(z + 1 <= zend ? z + 1 : -1, w_nxt, bi_nxt);
+        // (tile addresses are clamped into the lattice, so the loads are unconditional)
+        if constexpr (!AGCA_CUBE_EARLY_TILE) load_tile(z + 2, nxt);
+        RawCell rn2;
+        if constexpr (AGCA_CUBE_NU_AHEAD == 2)
+            load_cell(z + 2 <= zend ? z + 2 : -1, rn2);
+        else
+            load_cell(z + 1 <= zend ? z + 1 : -1, rn);
+        // keep the scheduler from sinking these loads towards their uses at the end of
+        // the step, which would expose their latency
+        __builtin_amdgcn_sched_barrier(0);
         T bq_n[NC], dq_n[NC];
         if constexpr (CubePrefetchNode<NC, T>::value) load_node(z + 1, bq_n, dq_n);
+        else if constexpr (AGCA_CUBE_NODE_EARLY) load_node(z, bq, dq);
 
         T F[8][NC];
 #pragma unroll
@@ -335,8 +394,14 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
             ybuf[yb][c][0][ty][tx] = P[1][0][c];
             ybuf[yb][c][1][ty][tx] = P[1][1][c];
         }
-        if (need_next) store_tile(z & 1, va, vb);  // buffer of layer z+2 held layer z
+        // held layer z-1, read last step; after the last step nothing reads this buffer
+        // again, so the store needs no condition (a branch would pull the loads into it)
+        store_tile(bidx(z + 2), z + 2, nxt);
         __syncthreads();
+        if constexpr (AGCA_CUBE_EARLY_TILE) {
+            load_tile(z + 3, nxt);
+            __builtin_amdgcn_sched_barrier(0);
+        }
 
         if (writer) {
             T s0[NC], s1[NC];
@@ -348,7 +413,7 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
             if (z >= Z0) {
                 const int64_t p = col + (int64_t)z * layer;
                 const bool interior = xin && z > 0 && z < n;
-                if constexpr (!CubePrefetchNode<NC, T>::value) load_node(z, bq, dq);
+                if constexpr (!CubePrefetchNode<NC, T>::value && !AGCA_CUBE_NODE_EARLY) load_node(z, bq, dq);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const T av = carry[c] + s0[c];
@@ -357,11 +422,11 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
                         o = av;
                     } else if constexpr (MODE == MODE_APPLY_DOT) {
                         o = av;
-                        if (interior) dot_acc += (double)Ulo[0][c] * (double)av;
+                        if (interior) dot_acc += (double)self[c] * (double)av;
                     } else if constexpr (MODE == MODE_RESIDUAL) {
                         o = bq[c] - av;
                     } else {
-                        o = Ulo[0][c] + omega * dq[c] * (bq[c] - av);
+                        o = self[c] + omega * dq[c] * (bq[c] - av);
                     }
                     out[c * N + p] = interior ? o : T(0);
                 }
@@ -369,15 +434,8 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
 #pragma unroll
             for (int c = 0; c < NC; ++c) carry[c] = s1[c];
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) Ulo[k][c] = U[k + 4][c];
-#pragma unroll
-        for (int s2 = 0; s2 < 6; ++s2) {
-            w_cur[s2] = w_nxt[s2];
-            bi_cur[s2] = bi_nxt[s2];
-        }
+        rc = rn;
+        if constexpr (AGCA_CUBE_NU_AHEAD == 2) rn = rn2;
         if constexpr (CubePrefetchNode<NC, T>::value) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -440,25 +498,46 @@ k_block_products(const int n, const int64_t nflag, const int32_t* __restrict__ i
     y[t] = acc;
 }
 
-int pick_zc(int n) {
+int tile_columns(int n) { return ((n + 1 + TX - 2) / (TX - 1)) * ((n + 1 + TY - 2) / (TY - 1)); }
+
+// z layers per workgroup.  Chunks of about 16 layers amortise the halo layer each chunk
+// recomputes; small levels use shorter chunks to expose more workgroups; when the
+// workgroups slightly exceed what the GPU holds at once (slots), the chunks grow
+// until they fit, rather than leaving a short second round.
+int pick_zc(int n, int slots) {
     static const int forced = [] {
         const char* e = getenv("AGCA_CUBE_ZC");
         return e ? atoi(e) : 0;
     }();
     if (forced > 0) return forced;
-    // chunks of 16 z layers amortise the one halo layer each chunk recomputes; small
-    // levels use shorter chunks to expose more workgroups
-    const int cols = ((n + 1 + TX - 2) / (TX - 1)) * ((n + 1 + TY - 2) / (TY - 1));
+    const int64_t cols = tile_columns(n);
+    auto blocks = [&](int zc) { return cols * ((n + 1 + zc - 1) / zc); };
     int zc = 16;
-    while (zc > 2 && (int64_t)cols * ((n + 1 + zc - 1) / zc) < 512) zc /= 2;
+    while (zc > 2 && blocks(zc) < 512) zc /= 2;
+    if (slots > 0 && blocks(zc) > slots && blocks(zc) <= slots + slots / 4)
+        while (blocks(zc) > slots && zc < n + 1) ++zc;
     return zc;
+}
+
+// workgroups of one kernel that the GPU runs at once (occupancy x compute units)
+template <typename K>
+int resident_slots(K kernel) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, NTHREADS, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
 }
 
 template <int NC, typename T, typename NT, int MODE, bool BLK>
 hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omega,
                     hipStream_t st, double* partial = nullptr, int* nblocks = nullptr) {
     const int n = op.n;
-    const int zc = pick_zc(n);
+    static const int slots = resident_slots(k_cube<NC, T, NT, MODE, BLK>);
+    const int zc = pick_zc(n, slots);
     dim3 block(TX, TY, 1);
     const int gx = (n + 1 + TX - 2) / (TX - 1), gy = (n + 1 + TY - 2) / (TY - 1),
               gz = (n + 1 + zc - 1) / zc;
@@ -517,8 +596,7 @@ hipError_t dispatch_nu(const LevelOp<T>& op, const T* u, const T* b, T* out, T o
 }  // namespace
 
 int cube_grid_blocks(int n) {
-    const int zc = pick_zc(n);
-    return ((n + 1 + TX - 2) / (TX - 1)) * ((n + 1 + TY - 2) / (TY - 1)) * ((n + 1 + zc - 1) / zc);
+    return tile_columns(n) * (n + 1);  // upper bound: one z layer per workgroup
 }
 
 hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u, double* out,

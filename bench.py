@@ -1,6 +1,7 @@
 """Benchmark of the AGCA multigrid hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sinker129]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --workload sinker513|stokes257|adjoint129 [--level L]   (report lines)
 
 Workload (default): the vector viscous block -div(2 nu eps(u)) = f on 129^3
 nodes (7 levels), 8 tanh-smoothed sinkers of radius 0.1, contrast 1e6,
@@ -240,6 +241,176 @@ def profile_apply(name: str, dev) -> None:
     print("profile-apply done", flush=True)
 
 
+def device_inputs(w, dev, chunk: int = 1 << 25):
+    """Coefficients of every level and the forcing, evaluated on the device (inputs too
+    large for the host generators); the same seeded field as the host evaluation."""
+    import torch
+    from workloads.lattice import element_centroids_torch
+    field = w.make_field()
+    nus = []
+    for l in range(w.L + 1):
+        E = 6 * (2 ** (l + 1)) ** 3
+        out = torch.empty(E, dtype=torch.float64, device=dev)
+        for s0 in range(0, E, chunk):
+            s1 = min(E, s0 + chunk)
+            out[s0:s1] = field.nu_torch(element_centroids_torch(l, s0, s1, dev))
+        nus.append(out)
+    E = nus[-1].numel()
+    f = torch.zeros((w.ncomp, E), dtype=torch.float64, device=dev)
+    for s0 in range(0, E, chunk):
+        s1 = min(E, s0 + chunk)
+        f[-1, s0:s1] = -field.xi_torch(element_centroids_torch(w.L, s0, s1, dev))
+    return nus, f.reshape(-1)
+
+
+def cold_apply_us(H, level, u, v, reps=10):
+    """Median duration of one apply with the Infinity Cache flushed before each (HIP events)."""
+    import torch
+    flush = torch.ones(512 * 1024 * 1024 // 8, dtype=torch.float64, device=u.device)
+    sink = torch.zeros(1, dtype=torch.float64, device=u.device)
+    ts = []
+    for _ in range(reps):
+        sink.add_(flush.sum())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        H.apply(level, u, v)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    return float(np.median(ts))
+
+
+def report_large(args, dev) -> dict:
+    """513^3 vector sinkers (64 sinkers, radii in [0.02, 0.06]): FP64-MG PCG against FP32-MG
+    (BF16 coefficient) FCG to 1e-8, flagged fractions, stored-block bytes, HBM use, and the
+    cold fine-apply rate in both precisions."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy
+    from workloads import workload
+    w = workload(args.workload, L=args.level)
+    L, nc = w.L, w.ncomp
+    t0 = time.perf_counter()
+    nus, f = device_inputs(w, dev)
+    t_gen = time.perf_counter() - t0
+    out = {"report": w.name, "description": w.description, "levels": L + 1,
+           "free_dofs": nc * (2 ** (L + 1) - 1) ** 3, "input_generation_s": round(t_gen, 2)}
+    t0 = time.perf_counter()
+    H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64")
+    out["setup_fp64_s"] = round(time.perf_counter() - t0, 3)
+    b = H64.load_vector(f)
+    del f
+    x, s64 = H64.solve(b, solver="pcg", tol=w.tol, max_iter=4000, raise_on_noconv=False,
+                       record_history=False)
+    out["fp64_mg_pcg"] = {k: s64[k] for k in ("iterations", "seconds", "rel_residual", "converged",
+                                                "floor_limited")}
+    n = 2 ** (L + 1)
+    u = torch.randn(nc * (n + 1) ** 3, dtype=torch.float64, device=dev)
+    v = torch.empty_like(u)
+    t_app = cold_apply_us(H64, L, u, v)
+    byt = apply_bytes(L, nc)
+    out["fp64_apply"] = {"us": round(t_app, 1), "GDoF_s": round(out["free_dofs"] / t_app / 1e3, 2),
+                         "GB_s": round(byt / t_app / 1e3, 1), "frac_hbm_peak": round(byt / t_app / 1e3 / HBM_PEAK_GBS, 4)}
+    info = [H64.query(l) for l in range(L)]
+    out["flagged_fraction_per_level"] = [round(i["flagged"] / i["elements"], 6) for i in info]
+    out["flagged_per_level"] = [i["flagged"] for i in info]
+    out["stored_block_bytes_fp64"] = int(sum(i["block_bytes"] for i in info))
+    dev64 = H64.device_bytes()
+    t0 = time.perf_counter()
+    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype="bf16")
+    out["setup_mixed_s"] = round(time.perf_counter() - t0, 3)
+    x32, s32 = H32.solve(b, solver="fcg", tol=w.tol, max_iter=4000, raise_on_noconv=False,
+                         record_history=False)
+    out["fp32_mg_fcg"] = {k: s32[k] for k in ("iterations", "seconds", "rel_residual", "converged",
+                                                "floor_limited")}
+    u32, v32 = u.float(), torch.empty_like(u, dtype=torch.float32)
+    t32 = cold_apply_us(H32, L, u32, v32)
+    byt32 = apply_bytes(L, nc, 4, 2)
+    out["fp32_bf16_apply"] = {"us": round(t32, 1), "GDoF_s": round(out["free_dofs"] / t32 / 1e3, 2),
+                              "GB_s": round(byt32 / t32 / 1e3, 1)}
+    info32 = [H32.query(l) for l in range(L)]
+    out["stored_block_bytes_mixed"] = int(sum(i["block_bytes"] for i in info32))
+    dx = x32 - x
+    Adx, Ax = H64.apply(L, dx), H64.apply(L, x)
+    out["mixed_vs_fp64_energy_norm_rel"] = float(torch.dot(dx, Adx) / torch.dot(x, Ax)) ** 0.5
+    out["speedup_mixed_over_fp64"] = round(s64["seconds"] / s32["seconds"], 3)
+    out["device_bytes"] = {"fp64_hierarchy": dev64, "mixed_hierarchy": H32.device_bytes(),
+                           "torch_allocated": int(torch.cuda.memory_allocated(dev)),
+                           "peak_torch_allocated": int(torch.cuda.max_memory_allocated(dev))}
+    total = dev64 + H32.device_bytes() + int(torch.cuda.max_memory_allocated(dev))
+    out["hbm_fraction_used"] = round(total / 288e9, 4)
+    H64.close()
+    H32.close()
+    return out
+
+
+def report_stokes(args, dev) -> dict:
+    """Generalized Stokes, velocity 257^3 / pressure 129^3, 16 sinkers: block-diagonal
+    preconditioned FGMRES with the FP32 V-cycle against the FP64 V-cycle, and MINRES with
+    the FP64 V-cycle, to 1e-8."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy, Stokes
+    from workloads import workload
+    w = workload(args.workload, L=args.level)
+    L = w.L
+    nus, f = device_inputs(w, dev)
+    out = {"report": w.name, "description": w.description,
+           "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3}
+    for mg, solver in (("f32", "fgmres"), ("f64", "fgmres"), ("f64", "minres")):
+        H = Hierarchy(L, 3, nus[L], nus[:L], mg_dtype=mg, mg_nu_dtype=("bf16" if mg == "f32" else "f64"))
+        S = Stokes(H)
+        fu = H.load_vector(f)
+        _, _, st = S.solve(fu, solver=solver, restart=30, tol=w.tol, max_iter=args.stokes_max_iter,
+                           record_history=False, raise_on_noconv=False)
+        out[f"{solver}_{mg}_mg"] = {k: st[k] for k in ("iterations", "seconds", "rel_residual",
+                                                         "converged")}
+        print(f"[stokes] {solver} {mg}-MG: {st['iterations']} it {st['seconds']:.2f} s "
+              f"res {st['rel_residual']:.2e}", file=sys.stderr, flush=True)
+        H.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def report_adjoint(args, dev) -> dict:
+    """129^3 adjoint workload: forward solve, adjoint solve and the gradient kernel, with
+    the homogeneity identity of the gradient as a check."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy
+    from paper_2511_13109_amd.autograd import solve as dsolve
+    from workloads import workload
+    from workloads.lattice import element_centroids
+    w = workload(args.workload, L=args.level)
+    L = w.L
+    g = w.make_field()
+    cf = element_centroids(L)
+    g.calibrate(cf)
+    log_nu = torch.from_numpy(g.log_nu(cf)).to(dev)
+    nu_c = [torch.from_numpy(np.exp(g.log_nu(element_centroids(l)))).to(dev) for l in range(L)]
+    f = torch.from_numpy(np.ascontiguousarray(np.asarray(g.force(cf, 3)).T)).to(dev).reshape(-1)
+    log_obs = log_nu + torch.from_numpy(g.noise(log_nu.numel())).to(dev)
+    H = Hierarchy(L, 3, torch.exp(log_nu), nu_c)
+    b = H.load_vector(f)
+    with torch.no_grad():
+        obs = dsolve(log_obs, b, H, nu_c, tol=w.tol).clone()
+    lnu = log_nu.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = dsolve(lnu, b, H, nu_c, tol=w.tol)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    J = 0.5 * torch.sum((u - obs) ** 2)
+    t0 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    gg = lnu.grad
+    hom = -float(torch.dot(u.detach() - obs, u.detach()))
+    out = {"report": w.name, "description": w.description, "forward_s": round(t_fwd, 4),
+           "adjoint_and_gradient_s": round(t_bwd, 4), "J": float(J),
+           "homogeneity_rel_err": abs(float(gg.sum()) - hom) / abs(hom)}
+    H.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +424,8 @@ def main():
                     help="only run 5 FP64 fine applies and a 256 MiB copy (counter passes)")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print the markdown summary of a profiling directory and exit")
+    ap.add_argument("--level", type=int, default=None, help="finest level of a report workload")
+    ap.add_argument("--stokes-max-iter", type=int, default=3000)
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile, ""))
@@ -270,6 +443,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.profile_apply:
         profile_apply(args.workload, dev)
+        return
+    # the other workloads print a report line of their own (the benchmark line is the
+    # 129^3 sinker workload)
+    reports = {"sinker513": report_large, "stokes257": report_stokes, "adjoint129": report_adjoint}
+    if args.workload in reports:
+        print(json.dumps(reports[args.workload](args, dev)), flush=True)
         return
     w, nu, f, t_gen = make_inputs(args.workload)
     L, nc = w.L, w.ncomp

@@ -106,6 +106,21 @@ class Sinkers:
         f[:, -1] = -xi
         return f
 
+    def xi_torch(self, pts):
+        """xi of the same field for a (N, 3) float64 torch tensor (any device): the same
+        formula with torch operations, for inputs too large to evaluate on the host."""
+        import torch
+        keep = torch.ones(pts.shape[0], dtype=torch.float64, device=pts.device)
+        for p, r in zip(self.centres, self.radii):
+            c = torch.as_tensor(p, dtype=torch.float64, device=pts.device)
+            d = torch.sqrt(((pts - c) ** 2).sum(dim=1))
+            s = 0.5 * (1.0 - torch.tanh((d - float(r)) / self.width))
+            keep *= (1.0 - s)
+        return 1.0 - keep
+
+    def nu_torch(self, pts):
+        return self.nu_lo + (self.nu_hi - self.nu_lo) * self.xi_torch(pts)
+
 
 class GaussianLogField:
     """log nu = affine rescale of a sum of Gaussians, with contrast exp(2*half_range).

@@ -25,3 +25,21 @@ def element_centroids(level: int) -> np.ndarray:
     cz, cy, cx = np.meshgrid(c, c, c, indexing="ij")
     base = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)
     return ((base[:, None, :] + off[None, :, :]) / n).reshape(-1, 3)
+
+
+def element_centroids_torch(level: int, start: int, stop: int, device):
+    """Centroids of elements start..stop-1 (element-id order) as a torch tensor on device."""
+    import torch
+    n = 2 ** (level + 1)
+    off = torch.zeros((6, 3), dtype=torch.float64, device=device)
+    for s, axes in enumerate(_ORDERS):
+        for k, a in enumerate(axes):
+            off[s, a] = (3 - k) / 4.0
+    e = torch.arange(start, stop, dtype=torch.int64, device=device)
+    s = e % 6
+    cell = e // 6
+    cx = cell % n
+    cy = (cell // n) % n
+    cz = cell // (n * n)
+    base = torch.stack([cx, cy, cz], dim=1).to(torch.float64)
+    return (base + off[s]) / n

@@ -354,13 +354,14 @@ def report_stokes(args, dev) -> dict:
     L = w.L
     nus, f = device_inputs(w, dev)
     out = {"report": w.name, "description": w.description,
-           "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3}
+           "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3,
+           "fgmres_restart": args.stokes_restart}
     for mg, solver in (("f32", "fgmres"), ("f64", "fgmres"), ("f64", "minres")):
         H = Hierarchy(L, 3, nus[L], nus[:L], mg_dtype=mg, mg_nu_dtype=("bf16" if mg == "f32" else "f64"))
         S = Stokes(H)
         fu = H.load_vector(f)
-        _, _, st = S.solve(fu, solver=solver, restart=30, tol=w.tol, max_iter=args.stokes_max_iter,
-                           record_history=False, raise_on_noconv=False)
+        _, _, st = S.solve(fu, solver=solver, restart=args.stokes_restart, tol=w.tol,
+                           max_iter=args.stokes_max_iter, record_history=False, raise_on_noconv=False)
         out[f"{solver}_{mg}_mg"] = {k: st[k] for k in ("iterations", "seconds", "rel_residual",
                                                          "converged")}
         print(f"[stokes] {solver} {mg}-MG: {st['iterations']} it {st['seconds']:.2f} s "
@@ -398,6 +399,7 @@ def report_adjoint(args, dev) -> dict:
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     J = 0.5 * torch.sum((u - obs) ** 2)
+    J_value = float(J.detach())
     t0 = time.perf_counter()
     J.backward()
     torch.cuda.synchronize()
@@ -405,7 +407,7 @@ def report_adjoint(args, dev) -> dict:
     gg = lnu.grad
     hom = -float(torch.dot(u.detach() - obs, u.detach()))
     out = {"report": w.name, "description": w.description, "forward_s": round(t_fwd, 4),
-           "adjoint_and_gradient_s": round(t_bwd, 4), "J": float(J),
+           "adjoint_and_gradient_s": round(t_bwd, 4), "J": J_value,
            "homogeneity_rel_err": abs(float(gg.sum()) - hom) / abs(hom)}
     H.close()
     return out
@@ -426,6 +428,7 @@ def main():
                     help="print the markdown summary of a profiling directory and exit")
     ap.add_argument("--level", type=int, default=None, help="finest level of a report workload")
     ap.add_argument("--stokes-max-iter", type=int, default=3000)
+    ap.add_argument("--stokes-restart", type=int, default=126)
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile, ""))

@@ -4,8 +4,15 @@ V-cycle (paper Section 4: one V-cycle approximates the inverse of the viscous
 block): damped Jacobi smoothing with the diagonal of the level operator,
 omega = 2/3, nu1 pre- and nu2 post-sweeps, restriction = P^T, interpolation = P
 (Section 2.1), zero initial guess on every coarser level, and a dense direct
-solve on level 0.  The Chebyshev smoother and the SOR-CG coarse solver of the
-paper are replaced by damped Jacobi and a direct solve (benchmark choices).
+solve on level 0.  The SOR-CG coarse solver of the paper is replaced by a direct
+solve (level 0 has one free node).
+
+Smoothers: damped Jacobi (the benchmark's) or the Chebyshev polynomial smoother
+of Section 4 (degree nu1 / nu2): the Chebyshev iteration for D^-1 A on the
+interval [lambda_max / 10, lambda_max] with lambda_max = 1.1 times an estimate
+of the largest eigenvalue of D^-1 A; the estimate is the Rayleigh quotient
+x.Ax / x.Dx of the pencil (A, D) after 20 power steps x <- D^-1 A x / ||D^-1 A x||
+started from the alternating vector (-1)^(X+Y+Z) on the free nodes.
 
 Solvers, all starting from x0 = 0 and stopping when ||b - A x||_2 <= tol ||b||_2
 (eq. (4.3) with the benchmark's tolerance):
@@ -42,14 +49,40 @@ class Hierarchy:
     nu2: int = 2
     coarse_chol: object = None
     D: List[np.ndarray] = field(default_factory=list)
+    smoother: str = "jacobi"
+    lam: List[float] = field(default_factory=list)   # Chebyshev: eigenvalue estimates per level
 
     @property
     def L(self) -> int:
         return len(self.levels) - 1
 
 
+CHEB_RATIO = 10.0   # lambda_min = lambda_max / CHEB_RATIO
+CHEB_BOOST = 1.1    # lambda_max = CHEB_BOOST * estimate
+POWER_ITERS = 20
+
+
+def alternating_start(level, ncomp: int, free: np.ndarray) -> np.ndarray:
+    """(-1)^(X+Y+Z) at every free dof (X, Y, Z the node's lattice coordinates)."""
+    nn = (level.n + 1) ** 3
+    X = np.rint(level.coords * level.n).astype(np.int64)
+    sign = np.empty(nn)
+    sign[level.node_id] = np.where(X.sum(axis=1) % 2 == 0, 1.0, -1.0)
+    return np.tile(sign, ncomp)[free]
+
+
+def lambda_max_estimate(A, D: np.ndarray, x0: np.ndarray, iters: int = POWER_ITERS) -> float:
+    """Power steps on D^-1 A, then the Rayleigh quotient of the pencil (A, D) (a lower
+    bound of the largest eigenvalue of D^-1 A)."""
+    x = x0 / np.linalg.norm(x0)
+    for _ in range(iters):
+        z = (A @ x) / D
+        x = z / np.linalg.norm(z)
+    return float((x @ (A @ x)) / (x @ (D * x)))
+
+
 def build(L: int, nu_levels: List[np.ndarray], ncomp: int, tau: float = 10.0,
-          mode: int = _agca.FLAG_RATIO, levels=None) -> Hierarchy:
+          mode: int = _agca.FLAG_RATIO, levels=None, smoother: str = "jacobi") -> Hierarchy:
     """Assemble the AGCA hierarchy for coefficients ``nu_levels`` (canonical ids per level)."""
     if levels is None:
         levels = mesh.hierarchy(L)
@@ -62,6 +95,12 @@ def build(L: int, nu_levels: List[np.ndarray], ncomp: int, tau: float = 10.0,
     H.D = [a.diagonal().copy() for a in A]
     A0 = A[0].toarray()
     H.coarse_chol = sla.cho_factor(A0)
+    H.smoother = smoother
+    if smoother == "chebyshev":
+        H.lam = [0.0] + [lambda_max_estimate(A[l], H.D[l], alternating_start(levels[l], ncomp, free[l]))
+                         for l in range(1, L + 1)]
+    elif smoother != "jacobi":
+        raise ValueError(smoother)
     return H
 
 
@@ -83,6 +122,31 @@ def jacobi(H: Hierarchy, l: int, b: np.ndarray, x: np.ndarray, sweeps: int) -> n
     return x
 
 
+def chebyshev(H: Hierarchy, l: int, b: np.ndarray, x: np.ndarray, degree: int) -> np.ndarray:
+    """degree steps of the Chebyshev iteration for D^-1 A on [lmax / CHEB_RATIO, lmax]
+    (three-term recurrence of the shifted and scaled Chebyshev polynomials)."""
+    A, D = H.A[l], H.D[l]
+    lmax = CHEB_BOOST * H.lam[l]
+    lmin = lmax / CHEB_RATIO
+    theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    d = (b - A @ x) / D / theta
+    x = x + d
+    for _ in range(1, degree):
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = rho_new * rho * d + (2.0 * rho_new / delta) * (b - A @ x) / D
+        x = x + d
+        rho = rho_new
+    return x
+
+
+def smooth(H: Hierarchy, l: int, b: np.ndarray, x: np.ndarray, sweeps: int) -> np.ndarray:
+    if H.smoother == "chebyshev":
+        return chebyshev(H, l, b, x, sweeps) if sweeps > 0 else x
+    return jacobi(H, l, b, x, sweeps)
+
+
 def vcycle(H: Hierarchy, b: np.ndarray, l: Optional[int] = None, x: Optional[np.ndarray] = None):
     """One V-cycle on level l for A_l x = b (free-DoF vectors)."""
     if l is None:
@@ -91,12 +155,12 @@ def vcycle(H: Hierarchy, b: np.ndarray, l: Optional[int] = None, x: Optional[np.
         x = np.zeros_like(b)
     if l == 0:
         return sla.cho_solve(H.coarse_chol, b)
-    x = jacobi(H, l, b, x, H.nu1)
+    x = smooth(H, l, b, x, H.nu1)
     r = b - H.A[l] @ x
     rc = H.P[l - 1].T @ r
     ec = vcycle(H, rc, l - 1, None)
     x = x + H.P[l - 1] @ ec
-    x = jacobi(H, l, b, x, H.nu2)
+    x = smooth(H, l, b, x, H.nu2)
     return x
 
 

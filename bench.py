@@ -422,6 +422,7 @@ def main():
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mg-nu", default="bf16", choices=["bf16", "f32"])
+    ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev"])
     ap.add_argument("--profile-apply", action="store_true",
                     help="only run 5 FP64 fine applies and a 256 MiB copy (counter passes)")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -457,8 +458,9 @@ def main():
     L, nc = w.L, w.ncomp
     nus = [torch.from_numpy(v).to(dev) for v in nu]
     f_dev = torch.from_numpy(f.ravel()).to(dev)
-    H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64")
-    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype=args.mg_nu)
+    H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64", smoother=args.smoother)
+    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype=args.mg_nu,
+                    smoother=args.smoother)
     b = H64.load_vector(f_dev)
     gen = torch.Generator(device="cpu").manual_seed(0)
     n = 2 ** (L + 1)
@@ -530,7 +532,7 @@ def main():
                    "free_dofs": free_dofs, "elements": 6 * n ** 3, "applies_per_step": args.applies},
         "time_to_1e-8_s": {"fp64_mg_pcg": round(float(np.median(rec["t64"])), 5),
                            "fp32_mg_fcg": round(float(np.median(rec["t32"])), 5),
-                           "mg_nu_dtype": args.mg_nu,
+                           "mg_nu_dtype": args.mg_nu, "smoother": args.smoother,
                            "speedup_fp32_over_fp64": round(float(np.median(rec["t64"]) /
                                                                  np.median(rec["t32"])), 3)},
         "iterations": {"fp64_mg_pcg": int(np.median(rec["it64"])), "fp32_mg_fcg": int(np.median(rec["it32"]))},

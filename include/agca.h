@@ -65,6 +65,16 @@ typedef enum { AGCA_F64 = 0, AGCA_F32 = 1, AGCA_BF16 = 2 } agca_dtype;
  *  ALL   : Galerkin blocks on every coarse element (eqs. (2.6)-(2.7)). */
 enum { AGCA_FLAG_RATIO = 0, AGCA_FLAG_NONE = 2, AGCA_FLAG_ALL = 3 };
 
+/* Smoother of the V-cycle.
+ *  JACOBI    : damped Jacobi, pre_sweeps / post_sweeps sweeps with damping omega.
+ *  CHEBYSHEV : the Chebyshev polynomial smoother of Section 4, degree pre_sweeps /
+ *              post_sweeps: the Chebyshev iteration for D^-1 A on
+ *              [lambda_max / 10, lambda_max], lambda_max = 1.1 x an estimate per level
+ *              formed at setup (the largest Ritz value of 20 Lanczos steps for the
+ *              pencil (A, D) from (-1)^(X+Y+Z) on the free nodes, in FP64; a lower
+ *              bound of the eigenvalue).  omega is not used. */
+enum { AGCA_SMOOTH_JACOBI = 0, AGCA_SMOOTH_CHEBYSHEV = 1 };
+
 typedef struct {
     int32_t L;               /* finest level, 1 <= L <= 9                                  */
     int32_t ncomp;           /* 1 or 3                                                      */
@@ -73,9 +83,9 @@ typedef struct {
                                 blocks, diagonals and work vectors                          */
     int32_t mg_nu_dtype;     /* AGCA_F64, AGCA_F32 or AGCA_BF16: finest-level coefficient
                                 copy used by the V-cycle (must not be wider than mg_dtype)  */
-    int32_t pre_sweeps;      /* damped-Jacobi sweeps before / after the coarse correction   */
+    int32_t pre_sweeps;      /* smoothing passes before / after the coarse correction      */
     int32_t post_sweeps;
-    int32_t reserved;
+    int32_t smoother;        /* AGCA_SMOOTH_*                                               */
     double flag_ratio;       /* tau (10 in the paper's experiments)                         */
     double omega;            /* Jacobi damping (2/3)                                        */
     uint64_t mem_limit_bytes;/* 0 = unlimited; larger totals fail with AGCA_E_OOM           */
@@ -89,6 +99,7 @@ typedef struct {
     int64_t flagged;         /* elements with a stored Galerkin block (0 on level L)        */
     int64_t block_bytes;     /* bytes of stored Galerkin blocks on this level               */
     int64_t level_bytes;     /* all device bytes the library holds for this level           */
+    double lambda_max;       /* Chebyshev: the eigenvalue estimate of D^-1 A (0 otherwise)  */
 } agca_level_info;
 
 typedef struct agca_hier agca_hier;

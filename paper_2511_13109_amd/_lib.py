@@ -11,6 +11,7 @@ LIB_PATH = os.environ.get("AGCA_LIBRARY") or os.path.join(_PKG, "libagca.so")
 AGCA_OK, AGCA_E_INVALID, AGCA_E_OOM, AGCA_E_HIP, AGCA_E_NOCONV, AGCA_E_NUMERIC, AGCA_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
+SMOOTH_JACOBI, SMOOTH_CHEBYSHEV = 0, 1
 FLAG_RATIO, FLAG_NONE, FLAG_ALL = 0, 2, 3
 SOLVER_PCG, SOLVER_FCG, SOLVER_IR, SOLVER_STATIONARY = 0, 1, 2, 3
 MAX_HISTORY = 1024
@@ -22,14 +23,14 @@ STATUS_NAMES = {0: "AGCA_OK", -1: "AGCA_E_INVALID", -2: "AGCA_E_OOM", -3: "AGCA_
 class Config(C.Structure):
     _fields_ = [("L", C.c_int32), ("ncomp", C.c_int32), ("flag_mode", C.c_int32),
                 ("mg_dtype", C.c_int32), ("mg_nu_dtype", C.c_int32), ("pre_sweeps", C.c_int32),
-                ("post_sweeps", C.c_int32), ("reserved", C.c_int32), ("flag_ratio", C.c_double),
+                ("post_sweeps", C.c_int32), ("smoother", C.c_int32), ("flag_ratio", C.c_double),
                 ("omega", C.c_double), ("mem_limit_bytes", C.c_uint64)]
 
 
 class LevelInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nodes", C.c_int64), ("free_nodes", C.c_int64),
                 ("elements", C.c_int64), ("flagged", C.c_int64), ("block_bytes", C.c_int64),
-                ("level_bytes", C.c_int64)]
+                ("level_bytes", C.c_int64), ("lambda_max", C.c_double)]
 
 
 class SolveOpts(C.Structure):

@@ -61,7 +61,8 @@ class Hierarchy:
     def __init__(self, L: int, ncomp: int, nu_fine: torch.Tensor, nu_coarse: Sequence[torch.Tensor],
                  flag_mode: str = "ratio", tau: float = 10.0, mg_dtype: str = "f64",
                  mg_nu_dtype: Optional[str] = None, pre: int = 2, post: int = 2,
-                 omega: float = 2.0 / 3.0, mem_limit_bytes: int = 0, stream=None):
+                 omega: float = 2.0 / 3.0, mem_limit_bytes: int = 0, stream=None,
+                 smoother: str = "jacobi"):
         self._lib = _lib.load()
         cfg = default_config()
         cfg.L, cfg.ncomp = L, ncomp
@@ -70,6 +71,7 @@ class Hierarchy:
         cfg.mg_dtype = _DT[mg_dtype]
         cfg.mg_nu_dtype = _DT[mg_nu_dtype or mg_dtype]
         cfg.pre_sweeps, cfg.post_sweeps, cfg.omega = pre, post, omega
+        cfg.smoother = {"jacobi": _lib.SMOOTH_JACOBI, "chebyshev": _lib.SMOOTH_CHEBYSHEV}[smoother]
         cfg.mem_limit_bytes = mem_limit_bytes
         self.cfg = cfg
         self.L, self.ncomp = L, ncomp

@@ -76,6 +76,7 @@ struct agca_hier {
     float* s_z32 = nullptr;
     double* trans[2] = {nullptr, nullptr};
     // Stokes (velocity: finest level, pressure: level L-1)
+    std::vector<double> lam;     // Chebyshev: eigenvalue estimate of D^-1 A per level
     int64_t nu_version = 0;      // bumped by every coefficient rebuild
     int64_t mass_version = -1;   // nu_version the pressure mass was formed for
     double* st_mass = nullptr;   // lumped 1/nu pressure mass (level L-1, all nodes)
@@ -214,13 +215,59 @@ int32_t check_dtype(const agca_hier* h, int dtype, bool need_mg) {
 // one pass of the level operator: the assembled stencil where the level has one,
 // the element loop otherwise
 template <typename T>
-int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, T omega) {
+int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, const Sweep<T>& sw) {
     const LevelOp<T> op = level_op<T>(h, l);
     if (op.sten)
-        HIPCHK(h, launch_stencil<T>(h->cfg.ncomp, mode, op.n, op.sten, u, b, op.dinv, out, omega, h->st));
+        HIPCHK(h, launch_stencil<T>(h->cfg.ncomp, mode, op.n, op.sten, u, b, op.dinv, out, sw, h->st));
     else
-        HIPCHK(h, launch_cube<T>(h->cfg.ncomp, mode, op, u, b, out, omega, h->st));
+        HIPCHK(h, launch_cube<T>(h->cfg.ncomp, mode, op, u, b, out, sw, h->st));
     return AGCA_OK;
+}
+template <typename T>
+int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, T omega) {
+    return do_cube<T>(h, l, mode, u, b, out, jacobi_sweep<T>(omega));
+}
+
+// Chebyshev smoother of degree m on level l (Section 4): the Chebyshev iteration for
+// D^-1 A on [lmax / 10, lmax], lmax = 1.1 x the level's eigenvalue estimate.  Pass 0
+// from x: x + D^-1 (b - A x) / theta.  Pass k >= 1: x_k + c1 (x_k - x_{k-1}) +
+// c2 D^-1 (b - A x_k) with rho_k = 1 / (2 sigma - rho_{k-1}), c1 = rho_k rho_{k-1},
+// c2 = 2 rho_k / delta, rho_0 = 1 / sigma.
+struct Cheb {
+    double theta = 1.0, delta = 1.0, sigma = 1.0;
+    explicit Cheb(double lam) {
+        const double lmax = 1.1 * lam, lmin = lmax / 10.0;
+        theta = 0.5 * (lmax + lmin);
+        delta = 0.5 * (lmax - lmin);
+        sigma = theta / delta;
+    }
+    // (c1, c2) of pass k >= 1
+    void coef(int k, double* c1, double* c2) const {
+        double rho = 1.0 / sigma, rho_new = rho;
+        for (int i = 1; i <= k; ++i) {
+            rho_new = 1.0 / (2.0 * sigma - rho);
+            if (i < k) rho = rho_new;
+        }
+        *c1 = rho_new * rho;
+        *c2 = 2.0 * rho_new / delta;
+    }
+};
+template <typename T>
+Sweep<T> cheb_sweep(const Cheb& ch, int k, const T* xprev) {
+    Sweep<T> s;
+    if (k == 0) {
+        s.omega = T(1.0 / ch.theta);
+        s.omega0 = s.omega;
+        return s;
+    }
+    double c1, c2;
+    ch.coef(k, &c1, &c2);
+    s.alpha = T(1.0 + c1);
+    s.gamma = T(-c1);
+    s.omega = T(c2);
+    s.omega0 = T(1.0 / ch.theta);  // the pass-0 scaling, for the fused first two passes
+    s.xprev = xprev;
+    return s;
 }
 
 // whether the first two pre-sweeps can be one pass on level l: the element loop
@@ -249,24 +296,35 @@ int32_t do_smooth(agca_hier* h, int l, int sweeps, double omega, const T* b, T* 
     return AGCA_OK;
 }
 
-// One V(pre,post)-cycle from a zero initial guess.  On element-loop levels without
-// stored blocks the first two pre-smoothing sweeps from zero are one pass (the
-// first, x = omega D^-1 b, is formed while loading); elsewhere the first sweep is
-// the elementwise x = omega D^-1 b.  The remaining sweeps ping-pong between the
-// level's two buffers, and on the finest level the starting buffer is chosen so
-// that the last sweep lands in the caller's x (no copies).
+// One V(pre,post)-cycle from a zero initial guess, with damped Jacobi or the Chebyshev
+// smoother (pre / post = number of passes = Chebyshev degree).  On element-loop levels
+// without stored blocks the first two pre-smoothing passes from zero are one kernel
+// (the first, x = omega0 D^-1 b, is formed while loading; Chebyshev only for degree
+// 2, whose second pass needs no stored first iterate); elsewhere the first pass is
+// the elementwise x = omega0 D^-1 b.  Every further pass writes the level's other
+// buffer (a Chebyshev pass reads the previous iterate from it at the same node), so
+// the passes ping-pong, and on the finest level the starting buffer is chosen so
+// that the last pass lands in the caller's x (no copies).
 template <typename T>
 int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
     const int L = h->cfg.L, nc = h->cfg.ncomp;
     const T om = T(h->cfg.omega);
     const int pre = h->cfg.pre_sweeps, post = h->cfg.post_sweeps;
+    const bool cheb = h->cfg.smoother == AGCA_SMOOTH_CHEBYSHEV;
+    // pass k of a smoothing phase; xprev = the iterate before the current one
+    auto pass = [&](int l, int k, const T* x, const T* bl, T* out, const T* xprev) -> int32_t {
+        if (!cheb) return do_cube<T>(h, l, MODE_JACOBI, x, bl, out, om);
+        const Cheb ch(h->lam[l]);
+        if (k == 0) return do_cube<T>(h, l, MODE_JACOBI, x, bl, out, cheb_sweep<T>(ch, 0, nullptr));
+        return do_cube<T>(h, l, MODE_CHEB, x, bl, out, cheb_sweep<T>(ch, k, xprev));
+    };
     std::vector<T*> xcur(L + 1, nullptr), xalt(L + 1, nullptr);
     for (int l = L; l >= 1; --l) {
         const int64_t cnt = (int64_t)nc * h->lv[l].nodes;
         const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
         T* home = (l == L) ? xL : static_cast<T*>(h->lv[l].x);
         T* other = static_cast<T*>(h->lv[l].t);
-        const bool fuse = fusable<T>(h, l);
+        const bool fuse = fusable<T>(h, l) && (!cheb || pre == 2);
         // out-of-place launches that write this level's iterate after its first producer
         // (pre-sweeps after the first pass, then every post-sweep; the prolongation
         // adds in place)
@@ -275,14 +333,25 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
         T* cur = (launches % 2 == 0) ? home : other;
         T* alt = (cur == home) ? other : home;
         const LevelOp<T> op = level_op<T>(h, l);
-        if (first == 2)
-            TRY(do_cube<T>(h, l, MODE_JACOBI0, nullptr, bl, cur, om));
-        else if (first == 1)
-            HIPCHK(h, launch_first_sweep<T>(cnt, om, op.dinv, bl, cur, h->st));
-        else
+        const T om0 = cheb ? T(1.0 / Cheb(h->lam[l]).theta) : om;
+        if (first == 2) {
+            // passes 0 and 1 from zero: x1 = om0 D^-1 b, then (x_prev = 0)
+            const Sweep<T> sw = cheb ? cheb_sweep<T>(Cheb(h->lam[l]), 1, nullptr) : jacobi_sweep<T>(om);
+            TRY(do_cube<T>(h, l, MODE_JACOBI0, nullptr, bl, cur, sw));
+        } else if (first == 1) {
+            HIPCHK(h, launch_first_sweep<T>(cnt, om0, op.dinv, bl, cur, h->st));
+        } else {
             HIPCHK(h, launch_fill<T>(cnt, T(0), cur, h->st));
+        }
         for (int i = first; i < pre; ++i) {
-            TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, om));
+            if (cheb && i == 1) {
+                // pass 1 from x1 with x_prev = 0: alpha x1 + omega D^-1 (b - A x1)
+                Sweep<T> sw = cheb_sweep<T>(Cheb(h->lam[l]), 1, nullptr);
+                sw.gamma = T(0);
+                TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, sw));
+            } else {
+                TRY(pass(l, i, cur, bl, alt, alt));
+            }
             std::swap(cur, alt);
         }
         xcur[l] = cur;
@@ -300,7 +369,7 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
         T* alt = xalt[l];
         HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, xcur[l - 1], cur, h->st));
         for (int i = 0; i < post; ++i) {
-            TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, om));
+            TRY(pass(l, i, cur, bl, alt, alt));
             std::swap(cur, alt);
         }
         xcur[l] = cur;
@@ -352,6 +421,8 @@ int32_t validate(const agca_config* c) {
         return fail(AGCA_E_INVALID, "an FP64 V-cycle needs an FP64 coefficient");
     if (c->mg_dtype == AGCA_F32 && c->mg_nu_dtype == AGCA_F64)
         return fail(AGCA_E_INVALID, "an FP32 V-cycle uses an FP32 or BF16 coefficient");
+    if (c->smoother != AGCA_SMOOTH_JACOBI && c->smoother != AGCA_SMOOTH_CHEBYSHEV)
+        return fail(AGCA_E_INVALID, "unknown smoother");
     if (c->pre_sweeps < 0 || c->post_sweeps < 0 || c->pre_sweeps > 64 || c->post_sweeps > 64)
         return fail(AGCA_E_INVALID, "sweeps must be in [0, 64]");
     if (!(c->omega > 0.0 && c->omega < 2.0)) return fail(AGCA_E_INVALID, "omega must be in (0, 2)");
@@ -370,6 +441,102 @@ int32_t count_invalid(agca_hier* h, const double* v, int64_t n, int* out) {
 }
 
 // level-0 operator on its single free node (1,1,1): ncomp x ncomp, inverted on the host
+int32_t ensure_solver_vectors(agca_hier* h) {
+    if (h->s_r) return AGCA_OK;
+    const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[h->cfg.L].nodes;
+    TRY(alloc_t(h, &h->s_r, cnt));
+    TRY(alloc_t(h, &h->s_z, cnt));
+    TRY(alloc_t(h, &h->s_p, cnt));
+    TRY(alloc_t(h, &h->s_q, cnt));
+    TRY(alloc_t(h, &h->s_ro, cnt));
+    if (mg32(h)) {
+        TRY(alloc_t(h, &h->s_r32, cnt));
+        TRY(alloc_t(h, &h->s_z32, cnt));
+    }
+    return AGCA_OK;
+}
+
+
+// Largest eigenvalue of the symmetric tridiagonal matrix (diagonal a[0..m), off-diagonal
+// b[0..m-1)): bisection on the Sturm count (number of eigenvalues below x = number of
+// negative pivots of the LDL^T factorisation of T - x I), inside the Gershgorin bounds.
+double tridiag_max_eigenvalue(const std::vector<double>& a, const std::vector<double>& b) {
+    const int m = (int)a.size();
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto below = [&](double x) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < m; ++i) {
+            const double off = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+            d = (a[i] - x) - (i > 0 ? off / d : 0.0);
+            if (d == 0.0) d = -1e-300;  // x is (to rounding) a pivot zero: count it below
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::fabs(hi); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) == m) hi = mid;  // every eigenvalue lies below mid
+        else lo = mid;
+    }
+    return hi;
+}
+
+// Largest eigenvalue of D^-1 A_l for the Chebyshev smoother, levels 1..L, in FP64: the
+// largest Ritz value of 20 Lanczos steps in the D inner product from (-1)^(x+y+z) on the
+// free nodes (a lower bound of the eigenvalue):
+//   alpha_k = v_k.A v_k, w = D^-1 A v_k - alpha_k v_k - beta_{k-1} v_{k-1},
+//   beta_k = sqrt(w.Dw), v_{k+1} = w / beta_k; the process ends early when beta_k
+// vanishes against alpha_k (an invariant Krylov space).
+constexpr int kLanczosSteps = 20;
+constexpr double kLanczosBreakdown = 1e-12;
+
+int32_t estimate_eigenvalues(agca_hier* h) {
+    TRY(ensure_solver_vectors(h));
+    const int L = h->cfg.L, nc = h->cfg.ncomp;
+    h->lam.assign(L + 1, 0.0);
+    for (int l = 1; l <= L; ++l) {
+        const Level& lv = h->lv[l];
+        const int64_t cnt = (int64_t)nc * lv.nodes;
+        double *v = h->s_r, *vprev = h->s_z, *w = h->s_p, *y = h->s_q;
+        double s = 0.0;
+        HIPCHK(h, launch_alternating(nc, lv.n, w, h->st));
+        HIPCHK(h, launch_mul(cnt, lv.diag, w, y, h->st));
+        TRY(do_dot<double>(h, w, y, cnt, &s));
+        if (!(s > 0.0) || !std::isfinite(s)) return fail(AGCA_E_NUMERIC, "eigenvalue estimate failed");
+        HIPCHK(h, launch_axpby<double>(cnt, 1.0 / std::sqrt(s), w, 0.0, v, h->st));
+        std::vector<double> alpha, beta;
+        double b = 0.0;
+        for (int k = 0; k < kLanczosSteps; ++k) {
+            double a = 0.0;
+            TRY(do_cube<double>(h, l, MODE_APPLY, v, nullptr, y, 0.0));
+            TRY(do_dot<double>(h, v, y, cnt, &a));
+            HIPCHK(h, launch_div_or_zero(cnt, y, lv.diag, w, h->st));
+            HIPCHK(h, launch_axpby<double>(cnt, -a, v, 1.0, w, h->st));
+            if (k > 0) HIPCHK(h, launch_axpby<double>(cnt, -b, vprev, 1.0, w, h->st));
+            alpha.push_back(a);
+            HIPCHK(h, launch_mul(cnt, lv.diag, w, y, h->st));
+            TRY(do_dot<double>(h, w, y, cnt, &s));
+            if (!std::isfinite(a) || !std::isfinite(s)) return fail(AGCA_E_NUMERIC, "eigenvalue estimate failed");
+            b = std::sqrt(std::max(s, 0.0));
+            if (!(b > kLanczosBreakdown * std::fabs(a))) break;
+            beta.push_back(b);
+            HIPCHK(h, launch_axpby<double>(cnt, 1.0 / b, w, 0.0, vprev, h->st));
+            std::swap(v, vprev);
+        }
+        beta.resize(alpha.size() - 1);
+        h->lam[l] = tridiag_max_eigenvalue(alpha, beta);
+        if (!(h->lam[l] > 0.0) || !std::isfinite(h->lam[l]))
+            return fail(AGCA_E_NUMERIC, "eigenvalue estimate failed");
+    }
+    return AGCA_OK;
+}
+
 int32_t build_coarsest(agca_hier* h) {
     const int nc = h->cfg.ncomp, M = 4 * nc;
     Level& L0 = h->lv[0];
@@ -611,6 +778,7 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
         }
     }
     TRY(build_coarsest(h));
+    if (h->cfg.smoother == AGCA_SMOOTH_CHEBYSHEV) TRY(estimate_eigenvalues(h));
     HIPCHK(h, hipStreamSynchronize(h->st));
     return AGCA_OK;
 }
@@ -777,6 +945,7 @@ int32_t agca_query(const agca_hier* h, int32_t level, agca_level_info* out) {
     out->flagged = level < h->cfg.L ? lv.nflag : 0;
     out->block_bytes = (lv.blocks64 ? lv.nflag * M * M * 8 : 0) + (lv.blocks32 ? lv.nflag * M * M * 4 : 0);
     out->level_bytes = lv.bytes;
+    out->lambda_max = (size_t)level < h->lam.size() ? h->lam[level] : 0.0;
     return AGCA_OK;
 }
 
@@ -924,20 +1093,6 @@ int32_t agca_load_vector(agca_hier* h, const double* f, double* b) {
 // ---------------------------------------------------------------------------
 // solvers
 // ---------------------------------------------------------------------------
-static int32_t ensure_solver_vectors(agca_hier* h) {
-    if (h->s_r) return AGCA_OK;
-    const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[h->cfg.L].nodes;
-    TRY(alloc_t(h, &h->s_r, cnt));
-    TRY(alloc_t(h, &h->s_z, cnt));
-    TRY(alloc_t(h, &h->s_p, cnt));
-    TRY(alloc_t(h, &h->s_q, cnt));
-    TRY(alloc_t(h, &h->s_ro, cnt));
-    if (mg32(h)) {
-        TRY(alloc_t(h, &h->s_r32, cnt));
-        TRY(alloc_t(h, &h->s_z32, cnt));
-    }
-    return AGCA_OK;
-}
 
 // z = B r with the hierarchy's V-cycle (FP32 V-cycle: cast in and out)
 static int32_t precondition(agca_hier* h, const double* r, double* z) {

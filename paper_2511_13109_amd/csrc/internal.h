@@ -26,15 +26,31 @@ struct LevelOp {
     const T* sten = nullptr;       // assembled stencil (k_stencil.hip layout) or null
 };
 
-// MODE_JACOBI0: two sweeps from a zero guess, x_out = x1 + omega D^-1 (b - A x1) with
-//               x1 = omega D^-1 b formed on the fly (u unused; element loop only)
+// MODE_JACOBI0: two passes from a zero guess: the input x = omega0 D^-1 b is formed on
+//               the fly (u unused; element loop only)
+// MODE_CHEB:    a Chebyshev step, reads x_prev at each output node
 enum CubeMode { MODE_APPLY = 0, MODE_RESIDUAL = 1, MODE_JACOBI = 2, MODE_APPLY_DOT = 3,
-                MODE_JACOBI0 = 4 };
+                MODE_JACOBI0 = 4, MODE_CHEB = 5 };
 
-// v = A u / r = b - A u / x_out = x + omega D^-1 (b - A x)   (one element-loop pass)
+// Coefficients of a smoothing pass: x_out = alpha x + gamma x_prev + omega D^-1 (b - A x)
+// (damped Jacobi: alpha = 1, gamma = 0); omega0 scales the first pass of MODE_JACOBI0.
+template <typename T>
+struct Sweep {
+    T omega = T(0), alpha = T(1), gamma = T(0), omega0 = T(0);
+    const T* xprev = nullptr;
+};
+template <typename T>
+inline Sweep<T> jacobi_sweep(T omega) {
+    Sweep<T> s;
+    s.omega = omega;
+    s.omega0 = omega;
+    return s;
+}
+
+// v = A u / r = b - A u / x_out as above   (one element-loop pass)
 template <typename T>
 hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,
-                       T omega, hipStream_t st);
+                       const Sweep<T>& sw, hipStream_t st);
 // v = A u and per-workgroup partial sums of u . v (FP64 only); *nblocks receives the count
 hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u, double* out,
                            double* partial, int* nblocks, hipStream_t st);
@@ -46,10 +62,11 @@ int cube_grid_blocks(int n);
 hipError_t launch_stencil_assemble(int ncomp, int n, const double* nu, double scale,
                                    const int32_t* blk, const double* blocks, double* S,
                                    hipStream_t st);
-// apply / residual / Jacobi (MODE_APPLY, MODE_RESIDUAL, MODE_JACOBI) with an assembled stencil
+// apply / residual / Jacobi-type passes (MODE_APPLY, MODE_RESIDUAL, MODE_JACOBI, MODE_CHEB)
+// with an assembled stencil
 template <typename T>
 hipError_t launch_stencil(int ncomp, int mode, int n, const T* S, const T* u, const T* b,
-                          const T* dinv, T* out, T omega, hipStream_t st);
+                          const T* dinv, T* out, const Sweep<T>& sw, hipStream_t st);
 
 // transfers (Section 2.1)
 template <typename T>
@@ -83,6 +100,11 @@ hipError_t launch_first_sweep(int64_t n, T omega, const T* dinv, const T* b, T* 
 template <typename T>
 hipError_t launch_fill(int64_t n, T value, T* x, hipStream_t st);
 hipError_t launch_count_invalid(const double* v, int64_t n, int* counter, hipStream_t st);
+// (-1)^(x+y+z) on interior nodes, 0 on the boundary; out = a * b; out = d > 0 ? y / d : 0
+hipError_t launch_alternating(int ncomp, int n, double* x, hipStream_t st);
+hipError_t launch_mul(int64_t n, const double* a, const double* b, double* out, hipStream_t st);
+hipError_t launch_div_or_zero(int64_t n, const double* y, const double* d, double* out,
+                              hipStream_t st);
 // element-id order (e = s + 6 cell) -> internal per-element layout (kuhn.h elem_slot)
 // (exponentiate: the input holds log nu)
 hipError_t launch_to_internal(int64_t cells, const double* by_id, double* internal, bool exponentiate,

@@ -1,7 +1,10 @@
 // Matrix-free element loop on the refined Kuhn lattice (paper eq. (2.3) on the
 // finest level, eq. (2.9) on coarser levels): apply, residual and damped-Jacobi sweep.
-// MODE_JACOBI0 folds the first sweep from a zero guess (u = omega D^-1 b, formed
-// while loading) into the second, so the first iterate is never stored.
+// Jacobi-type passes write alpha x + gamma x_prev + omega D^-1 (b - A x): damped Jacobi
+// (alpha = 1, gamma = 0) and the steps of the Chebyshev smoother (MODE_CHEB reads x_prev
+// at the output node).  MODE_JACOBI0 folds the first pass from a zero guess
+// (x = omega0 D^-1 b, formed while loading) into the second, so the first iterate is
+// never stored.
 //
 // Layout of the work: a workgroup of 256 threads owns a TX x TY column of lattice
 // cells (32 x 8 by default) and marches up through a chunk of z layers.  At every
@@ -137,20 +140,7 @@ __device__ __forceinline__ void tile_of(int gx, int gy, int gz, int& bx, int& by
 #ifndef AGCA_CUBE_PREFETCH_NODE
 #define AGCA_CUBE_PREFETCH_NODE 1
 #endif
-// issue the u-tile loads of a layer right after the previous step's barrier (before
-// its output phase) instead of at the top of the step that stores them
-#ifndef AGCA_CUBE_EARLY_TILE
-#define AGCA_CUBE_EARLY_TILE 1
-#endif
-// right-hand side and diagonal of the step's output nodes loaded at the top of the step
-// (their use follows the step's arithmetic) instead of just before the output
-#ifndef AGCA_CUBE_NODE_EARLY
-#define AGCA_CUBE_NODE_EARLY 0
-#endif
-// coefficient loads issued this many steps ahead of their use (1 or 2)
-#ifndef AGCA_CUBE_NU_AHEAD
-#define AGCA_CUBE_NU_AHEAD 1
-#endif
+
 #ifndef AGCA_CUBE_WAVES_F64V
 #define AGCA_CUBE_WAVES_F64V 3
 #endif
@@ -177,7 +167,8 @@ __attribute__((amdgpu_waves_per_eu(CubeWaves<NC, T>::value > 0 ? CubeWaves<NC, T
 k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
        const T* __restrict__ u, const NT* __restrict__ nu, const int32_t* __restrict__ blk,
        const T* __restrict__ yblk, const T* __restrict__ b, const T* __restrict__ dinv,
-       T* __restrict__ out, const T scale, const T omega, double* __restrict__ partial) {
+       T* __restrict__ out, const T scale, const T omega, const T alpha, const T gamma,
+       const T omega0, const T* __restrict__ xprev, double* __restrict__ partial) {
     // node layers of u: layer j lives in buffer (j + 3) % 3, so a step reads two
     // buffers while the third receives the layer two steps ahead
     // (TX+1) x (TY+1) nodes per layer and component, x fastest, plus 64 slots that
@@ -251,9 +242,9 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             T va = t.a[c], vb = t.b[c];
-            if constexpr (MODE == MODE_JACOBI0) {  // the first sweep from zero, x1 = omega D^-1 b
-                va = omega * t.da[c] * va;
-                vb = omega * t.db[c] * vb;
+            if constexpr (MODE == MODE_JACOBI0) {  // the first sweep from zero, x1 = omega0 D^-1 b
+                va = omega0 * t.da[c] * va;
+                vb = omega0 * t.db[c] * vb;
             }
             ubuf[buf][c][qa] = (ina && zin) ? va : T(0);
             ubuf[buf][c][qb_store] = (inb && zin) ? vb : T(0);
@@ -263,7 +254,7 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     const bool col_ok = cx >= 0 && cx < n && cy >= 0 && cy < n;
     const bool writer = tx >= 1 && ty >= 1 && cx <= n && cy <= n;
     const bool xin = cx > 0 && cx < n && cy > 0 && cy < n;
-    constexpr bool IS_JACOBI = MODE == MODE_JACOBI || MODE == MODE_JACOBI0;
+    constexpr bool IS_JACOBI = MODE == MODE_JACOBI || MODE == MODE_JACOBI0 || MODE == MODE_CHEB;
     constexpr bool NEEDS_B = MODE == MODE_RESIDUAL || IS_JACOBI;
     // cell and node columns of this thread, clamped
     const int64_t cellcol = min(max(cx, 0), n - 1) + (int64_t)n * min(max(cy, 0), n - 1);
@@ -324,10 +315,9 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     }
     RawCell rc;  // the cell layer of the coming step, loaded a step ahead
     load_cell(Z0 - 1, rc);
-    RawCell rn;  // with two steps ahead: the layer after it
-    if constexpr (AGCA_CUBE_NU_AHEAD == 2) load_cell(Z0 <= zend ? Z0 : -1, rn);
-    TileRaw nxt;  // the node layer two ahead of the coming step
-    if constexpr (AGCA_CUBE_EARLY_TILE) load_tile(Z0 + 1, nxt);
+    TileRaw nxt;  // the node layer two ahead of the coming step, loaded after the
+                  // previous step's barrier and staged at the end of this step
+    load_tile(Z0 + 1, nxt);
     T bq[NC], dq[NC];
     load_node(Z0 - 1, bq, dq);
     __syncthreads();
@@ -352,20 +342,14 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
         T self[NC];  // u at this thread's output node (cell corner 0)
 #pragma unroll
         for (int c = 0; c < NC; ++c) self[c] = U[0][c];
-        // issue the next step's loads first so that they overlap this step's work
-        // (tile addresses are clamped into the lattice, so the loads are unconditional)
-        if constexpr (!AGCA_CUBE_EARLY_TILE) load_tile(z + 2, nxt);
-        RawCell rn2;
-        if constexpr (AGCA_CUBE_NU_AHEAD == 2)
-            load_cell(z + 2 <= zend ? z + 2 : -1, rn2);
-        else
-            load_cell(z + 1 <= zend ? z + 1 : -1, rn);
+        // issue the next step's coefficient loads first so that they overlap this step's work
+        RawCell rn;
+        load_cell(z + 1 <= zend ? z + 1 : -1, rn);
         // keep the scheduler from sinking these loads towards their uses at the end of
         // the step, which would expose their latency
         __builtin_amdgcn_sched_barrier(0);
         T bq_n[NC], dq_n[NC];
         if constexpr (CubePrefetchNode<NC, T>::value) load_node(z + 1, bq_n, dq_n);
-        else if constexpr (AGCA_CUBE_NODE_EARLY) load_node(z, bq, dq);
 
         T F[8][NC];
 #pragma unroll
@@ -398,10 +382,10 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
         // again, so the store needs no condition (a branch would pull the loads into it)
         store_tile(bidx(z + 2), z + 2, nxt);
         __syncthreads();
-        if constexpr (AGCA_CUBE_EARLY_TILE) {
-            load_tile(z + 3, nxt);
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        // the layer after next: its loads overlap this step's output phase and the next
+        // step's arithmetic (addresses are clamped into the lattice: no condition)
+        load_tile(z + 3, nxt);
+        __builtin_amdgcn_sched_barrier(0);
 
         if (writer) {
             T s0[NC], s1[NC];
@@ -413,7 +397,7 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
             if (z >= Z0) {
                 const int64_t p = col + (int64_t)z * layer;
                 const bool interior = xin && z > 0 && z < n;
-                if constexpr (!CubePrefetchNode<NC, T>::value && !AGCA_CUBE_NODE_EARLY) load_node(z, bq, dq);
+                if constexpr (!CubePrefetchNode<NC, T>::value) load_node(z, bq, dq);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const T av = carry[c] + s0[c];
@@ -425,8 +409,12 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
                         if (interior) dot_acc += (double)self[c] * (double)av;
                     } else if constexpr (MODE == MODE_RESIDUAL) {
                         o = bq[c] - av;
+                    } else if constexpr (MODE == MODE_CHEB) {
+                        // Chebyshev step: alpha x + gamma x_prev + omega D^-1 (b - A x)
+                        const T xp = interior ? xprev[c * N + p] : T(0);
+                        o = alpha * self[c] + gamma * xp + omega * dq[c] * (bq[c] - av);
                     } else {
-                        o = self[c] + omega * dq[c] * (bq[c] - av);
+                        o = alpha * self[c] + omega * dq[c] * (bq[c] - av);
                     }
                     out[c * N + p] = interior ? o : T(0);
                 }
@@ -435,7 +423,6 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
             for (int c = 0; c < NC; ++c) carry[c] = s1[c];
         }
         rc = rn;
-        if constexpr (AGCA_CUBE_NU_AHEAD == 2) rn = rn2;
         if constexpr (CubePrefetchNode<NC, T>::value) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -533,7 +520,7 @@ int resident_slots(K kernel) {
 }
 
 template <int NC, typename T, typename NT, int MODE, bool BLK>
-hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omega,
+hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, const Sweep<T>& sw,
                     hipStream_t st, double* partial = nullptr, int* nblocks = nullptr) {
     const int n = op.n;
     static const int slots = resident_slots(k_cube<NC, T, NT, MODE, BLK>);
@@ -560,17 +547,19 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, T omeg
     hipLaunchKernelGGL((k_cube<NC, T, NT, MODE, BLK>), grid, block, 0, st, n, zc, gx, gy,
                        xcd_map ? gz : -gz, u,
                        reinterpret_cast<const NT*>(op.nu), op.blk, op.yblk, b, op.dinv, out,
-                       scale, omega, partial);
+                       scale, sw.omega, sw.alpha, sw.gamma, sw.omega0, sw.xprev, partial);
     return hipGetLastError();
 }
 
 template <int NC, typename T, int MODE>
-hipError_t dispatch_nu(const LevelOp<T>& op, const T* u, const T* b, T* out, T omega,
+hipError_t dispatch_nu(const LevelOp<T>& op, const T* u, const T* b, T* out, const Sweep<T>& sw,
                        hipStream_t st) {
     if (!op.nu || !out || op.n < 2) return hipErrorInvalidValue;
     if (MODE != MODE_JACOBI0 && !u) return hipErrorInvalidValue;
     if (MODE != MODE_APPLY && !b) return hipErrorInvalidValue;
-    if ((MODE == MODE_JACOBI || MODE == MODE_JACOBI0) && !op.dinv) return hipErrorInvalidValue;
+    if ((MODE == MODE_JACOBI || MODE == MODE_JACOBI0 || MODE == MODE_CHEB) && !op.dinv)
+        return hipErrorInvalidValue;
+    if (MODE == MODE_CHEB && !sw.xprev) return hipErrorInvalidValue;
     if (op.blk && (!op.blocks || !op.ids || !op.yblk || op.nflag <= 0)) return hipErrorInvalidValue;
     // the stored-block products are formed from u before the element loop, which
     // MODE_JACOBI0 never stores
@@ -579,16 +568,16 @@ hipError_t dispatch_nu(const LevelOp<T>& op, const T* u, const T* b, T* out, T o
     if constexpr (sizeof(T) == 8) {
         if (op.nu_kind != AGCA_F64) return hipErrorInvalidValue;
         if constexpr (MODE != MODE_JACOBI0)
-            if (blk) return launch_t<NC, T, double, MODE, true>(op, u, b, out, omega, st);
-        return launch_t<NC, T, double, MODE, false>(op, u, b, out, omega, st);
+            if (blk) return launch_t<NC, T, double, MODE, true>(op, u, b, out, sw, st);
+        return launch_t<NC, T, double, MODE, false>(op, u, b, out, sw, st);
     } else {
         if (op.nu_kind == AGCA_F32) {
             if constexpr (MODE != MODE_JACOBI0)
-                if (blk) return launch_t<NC, T, float, MODE, true>(op, u, b, out, omega, st);
-            return launch_t<NC, T, float, MODE, false>(op, u, b, out, omega, st);
+                if (blk) return launch_t<NC, T, float, MODE, true>(op, u, b, out, sw, st);
+            return launch_t<NC, T, float, MODE, false>(op, u, b, out, sw, st);
         }
         if (op.nu_kind == AGCA_BF16 && !blk)
-            return launch_t<NC, T, uint16_t, MODE, false>(op, u, b, out, omega, st);
+            return launch_t<NC, T, uint16_t, MODE, false>(op, u, b, out, sw, st);
         return hipErrorInvalidValue;
     }
 }
@@ -605,38 +594,39 @@ hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u
         return hipErrorInvalidValue;
     if (op.blk && (!op.blocks || !op.ids || !op.yblk || op.nflag <= 0)) return hipErrorInvalidValue;
     if (ncomp == 1)
-        return op.blk ? launch_t<1, double, double, MODE_APPLY_DOT, true>(op, u, nullptr, out, 0.0, st,
+        return op.blk ? launch_t<1, double, double, MODE_APPLY_DOT, true>(op, u, nullptr, out, Sweep<double>{}, st,
                                                                            partial, nblocks)
-                      : launch_t<1, double, double, MODE_APPLY_DOT, false>(op, u, nullptr, out, 0.0, st,
+                      : launch_t<1, double, double, MODE_APPLY_DOT, false>(op, u, nullptr, out, Sweep<double>{}, st,
                                                                             partial, nblocks);
-    return op.blk ? launch_t<3, double, double, MODE_APPLY_DOT, true>(op, u, nullptr, out, 0.0, st,
+    return op.blk ? launch_t<3, double, double, MODE_APPLY_DOT, true>(op, u, nullptr, out, Sweep<double>{}, st,
                                                                        partial, nblocks)
-                  : launch_t<3, double, double, MODE_APPLY_DOT, false>(op, u, nullptr, out, 0.0, st,
+                  : launch_t<3, double, double, MODE_APPLY_DOT, false>(op, u, nullptr, out, Sweep<double>{}, st,
                                                                         partial, nblocks);
 }
 
 template <int NC, typename T>
-hipError_t launch_cube_nc(int mode, const LevelOp<T>& op, const T* u, const T* b, T* out, T omega,
-                          hipStream_t st) {
+hipError_t launch_cube_nc(int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,
+                          const Sweep<T>& sw, hipStream_t st) {
     switch (mode) {
-        case MODE_APPLY: return dispatch_nu<NC, T, MODE_APPLY>(op, u, b, out, omega, st);
-        case MODE_RESIDUAL: return dispatch_nu<NC, T, MODE_RESIDUAL>(op, u, b, out, omega, st);
-        case MODE_JACOBI: return dispatch_nu<NC, T, MODE_JACOBI>(op, u, b, out, omega, st);
-        case MODE_JACOBI0: return dispatch_nu<NC, T, MODE_JACOBI0>(op, u, b, out, omega, st);
+        case MODE_APPLY: return dispatch_nu<NC, T, MODE_APPLY>(op, u, b, out, sw, st);
+        case MODE_RESIDUAL: return dispatch_nu<NC, T, MODE_RESIDUAL>(op, u, b, out, sw, st);
+        case MODE_JACOBI: return dispatch_nu<NC, T, MODE_JACOBI>(op, u, b, out, sw, st);
+        case MODE_JACOBI0: return dispatch_nu<NC, T, MODE_JACOBI0>(op, u, b, out, sw, st);
+        case MODE_CHEB: return dispatch_nu<NC, T, MODE_CHEB>(op, u, b, out, sw, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
 hipError_t launch_cube(int ncomp, int mode, const LevelOp<T>& op, const T* u, const T* b, T* out,
-                       T omega, hipStream_t st) {
-    return ncomp == 1 ? launch_cube_nc<1, T>(mode, op, u, b, out, omega, st)
-                      : launch_cube_nc<3, T>(mode, op, u, b, out, omega, st);
+                       const Sweep<T>& sw, hipStream_t st) {
+    return ncomp == 1 ? launch_cube_nc<1, T>(mode, op, u, b, out, sw, st)
+                      : launch_cube_nc<3, T>(mode, op, u, b, out, sw, st);
 }
 
 template hipError_t launch_cube<double>(int, int, const LevelOp<double>&, const double*,
-                                        const double*, double*, double, hipStream_t);
+                                        const double*, double*, const Sweep<double>&, hipStream_t);
 template hipError_t launch_cube<float>(int, int, const LevelOp<float>&, const float*,
-                                       const float*, float*, float, hipStream_t);
+                                       const float*, float*, const Sweep<float>&, hipStream_t);
 
 }  // namespace agca

@@ -80,7 +80,8 @@ k_stencil_assemble(int n, const double* __restrict__ nu, double scale, const int
 template <int NC, typename T, int MODE>
 __global__ void __launch_bounds__(NT)
 k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T* __restrict__ b,
-                const T* __restrict__ dinv, T* __restrict__ out, T omega) {
+                const T* __restrict__ dinv, T* __restrict__ out, T omega, T alpha, T gamma,
+                const T* __restrict__ xprev) {
     const int64_t n1 = n + 1, N = n1 * n1 * n1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     const int c = blockIdx.y;
@@ -110,27 +111,30 @@ k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T
         out[o] = acc;
     } else if constexpr (MODE == MODE_RESIDUAL) {
         out[o] = b[o] - acc;
+    } else if constexpr (MODE == MODE_CHEB) {
+        out[o] = alpha * u[o] + gamma * xprev[o] + omega * dinv[o] * (b[o] - acc);
     } else {
-        out[o] = u[o] + omega * dinv[o] * (b[o] - acc);
+        out[o] = alpha * u[o] + omega * dinv[o] * (b[o] - acc);
     }
 }
 
 template <int NC, typename T, int MODE>
-hipError_t launch_mode(int n, const T* S, const T* u, const T* b, const T* dinv, T* out, T omega,
-                       hipStream_t st) {
+hipError_t launch_mode(int n, const T* S, const T* u, const T* b, const T* dinv, T* out,
+                       const Sweep<T>& sw, hipStream_t st) {
     const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
     hipLaunchKernelGGL((k_stencil_apply<NC, T, MODE>), dim3((unsigned)((N + NT - 1) / NT), NC),
-                       dim3(NT), 0, st, n, S, u, b, dinv, out, omega);
+                       dim3(NT), 0, st, n, S, u, b, dinv, out, sw.omega, sw.alpha, sw.gamma, sw.xprev);
     return hipGetLastError();
 }
 
 template <int NC, typename T>
 hipError_t launch_nc(int mode, int n, const T* S, const T* u, const T* b, const T* dinv, T* out,
-                     T omega, hipStream_t st) {
+                     const Sweep<T>& sw, hipStream_t st) {
     switch (mode) {
-        case MODE_APPLY: return launch_mode<NC, T, MODE_APPLY>(n, S, u, b, dinv, out, omega, st);
-        case MODE_RESIDUAL: return launch_mode<NC, T, MODE_RESIDUAL>(n, S, u, b, dinv, out, omega, st);
-        case MODE_JACOBI: return launch_mode<NC, T, MODE_JACOBI>(n, S, u, b, dinv, out, omega, st);
+        case MODE_APPLY: return launch_mode<NC, T, MODE_APPLY>(n, S, u, b, dinv, out, sw, st);
+        case MODE_RESIDUAL: return launch_mode<NC, T, MODE_RESIDUAL>(n, S, u, b, dinv, out, sw, st);
+        case MODE_JACOBI: return launch_mode<NC, T, MODE_JACOBI>(n, S, u, b, dinv, out, sw, st);
+        case MODE_CHEB: return launch_mode<NC, T, MODE_CHEB>(n, S, u, b, dinv, out, sw, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -152,17 +156,18 @@ hipError_t launch_stencil_assemble(int ncomp, int n, const double* nu, double sc
 
 template <typename T>
 hipError_t launch_stencil(int ncomp, int mode, int n, const T* S, const T* u, const T* b,
-                          const T* dinv, T* out, T omega, hipStream_t st) {
+                          const T* dinv, T* out, const Sweep<T>& sw, hipStream_t st) {
     if (!S || !u || !out || n < 2) return hipErrorInvalidValue;
     if (mode != MODE_APPLY && !b) return hipErrorInvalidValue;
-    if (mode == MODE_JACOBI && !dinv) return hipErrorInvalidValue;
-    return ncomp == 1 ? launch_nc<1, T>(mode, n, S, u, b, dinv, out, omega, st)
-                      : launch_nc<3, T>(mode, n, S, u, b, dinv, out, omega, st);
+    if ((mode == MODE_JACOBI || mode == MODE_CHEB) && !dinv) return hipErrorInvalidValue;
+    if (mode == MODE_CHEB && !sw.xprev) return hipErrorInvalidValue;
+    return ncomp == 1 ? launch_nc<1, T>(mode, n, S, u, b, dinv, out, sw, st)
+                      : launch_nc<3, T>(mode, n, S, u, b, dinv, out, sw, st);
 }
 
 template hipError_t launch_stencil<double>(int, int, int, const double*, const double*, const double*,
-                                           const double*, double*, double, hipStream_t);
+                                           const double*, double*, const Sweep<double>&, hipStream_t);
 template hipError_t launch_stencil<float>(int, int, int, const float*, const float*, const float*,
-                                          const float*, float*, float, hipStream_t);
+                                          const float*, float*, const Sweep<float>&, hipStream_t);
 
 }  // namespace agca

@@ -227,6 +227,34 @@ __global__ void __launch_bounds__(NT) k_fill(int64_t n, T value, T* __restrict__
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) x[i] = value;
 }
 
+// (-1)^(x+y+z) at interior nodes (every component), 0 on the boundary
+__global__ void __launch_bounds__(NT) k_alternating(int ncomp, int n, double* __restrict__ x) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (p >= N) return;
+    const int xx = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    const bool in = xx > 0 && y > 0 && z > 0 && xx < n && y < n && z < n;
+    const double v = in ? (((xx + y + z) & 1) ? -1.0 : 1.0) : 0.0;
+    for (int c = 0; c < ncomp; ++c) x[c * N + p] = v;
+}
+
+__global__ void __launch_bounds__(NT)
+k_mul(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) out[i] = a[i] * b[i];
+}
+
+// out = y / d where d > 0, else 0 (the diagonal is 0 on boundary slots)
+__global__ void __launch_bounds__(NT)
+k_div_or_zero(int64_t n, const double* __restrict__ y, const double* __restrict__ d,
+              double* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
+        const double dv = d[i];
+        out[i] = dv > 0.0 ? y[i] / dv : 0.0;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT) k_zero_boundary(int ncomp, int n, T* __restrict__ x) {
     const int64_t n1 = n + 1, N = n1 * n1 * n1;
@@ -396,6 +424,23 @@ hipError_t launch_fill(int64_t n, T value, T* x, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (!x) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_stride(n)), dim3(NT), 0, st, n, value, x);
+    return hipGetLastError();
+}
+hipError_t launch_alternating(int ncomp, int n, double* x, hipStream_t st) {
+    if (!x || n < 2) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_alternating, dim3(grid_for(N)), dim3(NT), 0, st, ncomp, n, x);
+    return hipGetLastError();
+}
+hipError_t launch_mul(int64_t n, const double* a, const double* b, double* out, hipStream_t st) {
+    if (!a || !b || !out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mul, dim3(grid_stride(n)), dim3(NT), 0, st, n, a, b, out);
+    return hipGetLastError();
+}
+hipError_t launch_div_or_zero(int64_t n, const double* y, const double* d, double* out,
+                              hipStream_t st) {
+    if (!y || !d || !out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_div_or_zero, dim3(grid_stride(n)), dim3(NT), 0, st, n, y, d, out);
     return hipGetLastError();
 }
 template <typename T>

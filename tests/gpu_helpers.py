@@ -20,15 +20,15 @@ def field_for(kind: str, L: int, seed: int = 2):
     raise ValueError(kind)
 
 
-def oracle_case(kind: str, L: int, ncomp: int, mode: int = 0):
+def oracle_case(kind: str, L: int, ncomp: int, mode: int = 0, smoother: str = "jacobi"):
     """Oracle hierarchy plus the per-level coefficients (canonical ids) for a field."""
-    key = (kind, L, ncomp, mode)
+    key = (kind, L, ncomp, mode, smoother)
     if key in _CACHE:
         return _CACHE[key]
     levels = mesh.hierarchy(L)
     field = field_for(kind, L)
     nu_levels = [field.nu(mesh.centroids_canonical(lv)) for lv in levels]
-    H = mg.build(L, nu_levels, ncomp, mode=mode, levels=levels)
+    H = mg.build(L, nu_levels, ncomp, mode=mode, levels=levels, smoother=smoother)
     _CACHE[key] = (H, nu_levels, field)
     return _CACHE[key]
 

@@ -265,3 +265,64 @@ def test_cast_round_to_nearest_even():
         assert back[-1] == 1.0 + 2 ** -7
     finally:
         G.close()
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev smoother (Section 4): eigenvalue estimates, V-cycle and PCG against
+# the oracle, for degree 2 (first two passes fused on element-loop levels) and
+# degree 3 (every pass separate)
+# ---------------------------------------------------------------------------
+CHEB_CASES = [("sinkers", 3, 3, 2), ("sinkers", 4, 3, 2), ("unaligned", 4, 1, 3), ("sinkers", 3, 3, 3)]
+
+
+@pytest.mark.parametrize("case", CHEB_CASES, ids=lambda c: f"{c[0]}-L{c[1]}-nc{c[2]}-deg{c[3]}")
+def test_chebyshev_smoother(case):
+    from paper_2511_13109_amd import Hierarchy
+    import copy
+    kind, L, ncomp, deg = case
+    print(f"\n[chebyshev {case}]", flush=True)
+    H0, nu_levels, field = oracle_case(kind, L, ncomp, 0, "chebyshev")
+    H = copy.copy(H0)
+    H.nu1 = H.nu2 = deg
+    nus = [_dev(v) for v in nu_levels]
+    G = Hierarchy(L, ncomp, nus[L], nus[:L], smoother="chebyshev", pre=deg, post=deg)
+    try:
+        for l in range(1, L + 1):
+            lam = G.query(l)["lambda_max"]
+            assert abs(lam - H.lam[l]) <= 1e-10 * H.lam[l], (l, lam, H.lam[l])
+        rng = np.random.default_rng(11)
+        b = rand_full(H, L, rng)
+        m = interior_full(H, L)
+        x = G.vcycle(_dev(b)).cpu().numpy()
+        ref = np.zeros_like(b)
+        ref[m] = mg.vcycle(H, b[m])
+        assert rel_err(x, ref) < 1e-11
+        lv = H.levels[L]
+        f = field.force(mesh.centroids_canonical(lv), ncomp) if kind == "sinkers" else \
+            np.ones(lv.tets.shape[0])
+        bb = fem.load_vector(lv, f, ncomp)
+        tol = 1e-8
+        r_ref = mg.pcg(H.A[L], bb[m], lambda r: mg.vcycle(H, r), tol)
+        r_jac = mg.pcg(H.A[L], bb[m], lambda r: mg.vcycle(_jacobi_twin(H), r), tol)
+        xg, st = G.solve(_dev(bb), solver="pcg", tol=tol)
+        print(f"[chebyshev {case}] PCG gpu {st['iterations']} oracle {r_ref.iterations} "
+              f"(Jacobi V-cycle {r_jac.iterations})", flush=True)
+        assert st["converged"] and abs(st["iterations"] - r_ref.iterations) <= 1
+    finally:
+        G.close()
+    # the FP32 V-cycle with the Chebyshev smoother inside FCG reaches the FP64 residual
+    G32 = Hierarchy(L, ncomp, nus[L], nus[:L], smoother="chebyshev", pre=deg, post=deg,
+                    mg_dtype="f32", mg_nu_dtype="f32")
+    try:
+        _, st = G32.solve(_dev(bb), solver="fcg", tol=tol, max_iter=1500)
+        assert st["converged"] and st["rel_residual"] <= tol
+    finally:
+        G32.close()
+
+
+def _jacobi_twin(H):
+    import copy
+    J = copy.copy(H)
+    J.smoother = "jacobi"
+    J.nu1 = J.nu2 = 2
+    return J

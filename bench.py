@@ -9,10 +9,13 @@ f = (0, 0, -xi); synthetic inputs from the seeded generators in workloads/.
 
 One step = one pass over the whole hot path for the resident coefficient:
   1. rebuild both hierarchies from the resident coefficients (flags, Galerkin
-     blocks of flagged elements, diagonals, coarsest inverse),
+     blocks of flagged elements, diagonals, coarsest inverse, and the spectral
+     bounds of the Chebyshev smoother),
   2. a batch of fine-grid operator applications v = A_L u (FP64), each timed
      with HIP events after a 512 MiB read that evicts the Infinity Cache,
-  3. an FP64 solve to 1e-8 with the FP64 AGCA V-cycle (PCG),
+  3. an FP64 solve to 1e-8 with the FP64 AGCA V-cycle (PCG); the V-cycle is
+     V(2,2) with the degree-2 Chebyshev smoother of Section 4 (--smoother
+     jacobi: damped Jacobi, omega = 2/3),
   4. a solve to 1e-8 with the FP32 V-cycle and BF16 finest coefficient inside
      FP64 flexible CG.
 Printed metric: fine-grid apply throughput in GDoF/s (free DoFs / average
@@ -422,7 +425,7 @@ def main():
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mg-nu", default="bf16", choices=["bf16", "f32"])
-    ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "chebyshev"])
+    ap.add_argument("--smoother", default="chebyshev", choices=["jacobi", "chebyshev"])
     ap.add_argument("--profile-apply", action="store_true",
                     help="only run 5 FP64 fine applies and a 256 MiB copy (counter passes)")
     ap.add_argument("--summarize-profile", metavar="DIR",

@@ -71,7 +71,6 @@ struct agca_hier {
     double* s_z = nullptr;
     double* s_p = nullptr;
     double* s_q = nullptr;
-    double* s_ro = nullptr;
     float* s_r32 = nullptr;
     float* s_z32 = nullptr;
     double* trans[2] = {nullptr, nullptr};
@@ -448,7 +447,6 @@ int32_t ensure_solver_vectors(agca_hier* h) {
     TRY(alloc_t(h, &h->s_z, cnt));
     TRY(alloc_t(h, &h->s_p, cnt));
     TRY(alloc_t(h, &h->s_q, cnt));
-    TRY(alloc_t(h, &h->s_ro, cnt));
     if (mg32(h)) {
         TRY(alloc_t(h, &h->s_r32, cnt));
         TRY(alloc_t(h, &h->s_z32, cnt));
@@ -1115,7 +1113,7 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     std::memset(stats, 0, sizeof(*stats));
     const int L = h->cfg.L;
     const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[L].nodes;
-    double *r = h->s_r, *z = h->s_z, *p = h->s_p, *q = h->s_q, *ro = h->s_ro;
+    double *r = h->s_r, *z = h->s_z, *p = h->s_p, *q = h->s_q;
     auto t0 = std::chrono::steady_clock::now();
     if (!o->use_x0) HIPCHK(h, launch_fill<double>(cnt, 0.0, x, h->st));
     HIPCHK(h, launch_zero_boundary<double>(h->cfg.ncomp, h->lv[L].n, x, h->st));
@@ -1159,18 +1157,37 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
         rel = rec_rel = 0.0;
     } else if (rel > o->tol) {
         if (o->solver == AGCA_SOLVER_PCG || o->solver == AGCA_SOLVER_FCG) {
+            // FCG(1): beta = z_k . (r_k - r_{k-1}) / (z_{k-1} . r_{k-1}), formed as
+            // -alpha z_k . q_{k-1} / (z_{k-1} . r_{k-1}) since r_k - r_{k-1} = -alpha q_{k-1}
+            // (no copy of the old residual).  With the FP32 V-cycle the residual update
+            // also writes the V-cycle's FP32 input, and z stays in FP32: the dot products
+            // and the direction update widen it on the fly.
             const bool flex = o->solver == AGCA_SOLVER_FCG;
-            double rz = 0.0;
+            const bool mixed = mg32(h);
+            float *r32 = h->s_r32, *z32 = h->s_z32;
+            auto vcycle = [&]() -> int32_t {
+                return mixed ? do_vcycle<float>(h, r32, z32) : do_vcycle<double>(h, r, z);
+            };
+            auto dots = [&](const double* qq) -> hipError_t {
+                return mixed ? launch_dot2<float>(cnt, z32, r, qq, h->partial, h->nb_partial, h->st)
+                             : launch_dot2<double>(cnt, z, r, qq, h->partial, h->nb_partial, h->st);
+            };
+            auto direction = [&](double beta) -> hipError_t {
+                return mixed ? launch_zpbp<float>(cnt, z32, beta, p, h->st)
+                             : launch_zpbp<double>(cnt, z, beta, p, h->st);
+            };
+            double rz = 0.0, alpha = 0.0;
             bool restart = true;
             double tmp[2];
             while (it < o->max_iter) {
                 if (restart) {
-                    TRY(precondition(h, r, z));
-                    HIPCHK(h, launch_dot2(cnt, z, r, nullptr, h->partial, h->nb_partial, h->st));
+                    if (mixed) HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, r, r32, cnt, h->st));
+                    TRY(vcycle());
+                    HIPCHK(h, dots(nullptr));
                     TRY(reduce_to(h, h->partial, h->nb_partial, 0));
                     TRY(fetch(h, 1, tmp));
                     rz = tmp[0];
-                    HIPCHK(h, hipMemcpyAsync(p, z, sizeof(double) * cnt, hipMemcpyDeviceToDevice, h->st));
+                    HIPCHK(h, direction(0.0));
                     restart = false;
                 }
                 if (!(rz > 0.0) || !std::isfinite(rz)) {
@@ -1188,9 +1205,9 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     status = fail(AGCA_E_NUMERIC, "search direction has non-positive energy");
                     break;
                 }
-                const double alpha = rz / pq;
-                // x += alpha p, r -= alpha q (keeping the old r for FCG), fused with r . r
-                HIPCHK(h, launch_cg_update(cnt, alpha, p, q, x, r, flex ? ro : nullptr, h->partial,
+                alpha = rz / pq;
+                // x += alpha p, r -= alpha q (and its FP32 copy), fused with r . r
+                HIPCHK(h, launch_cg_update(cnt, alpha, p, q, x, r, mixed ? r32 : nullptr, h->partial,
                                            h->nb_partial, h->st));
                 TRY(reduce_to(h, h->partial, h->nb_partial, 0));
                 TRY(fetch(h, 1, tmp));
@@ -1209,16 +1226,16 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     restart = true;
                     continue;
                 }
-                TRY(precondition(h, r, z));
-                // z . r and, for FCG, z . r_old in one pass
-                HIPCHK(h, launch_dot2(cnt, z, r, flex ? ro : nullptr, h->partial, h->nb_partial, h->st));
+                TRY(vcycle());
+                // z . r and, for FCG, z . q in one pass
+                HIPCHK(h, dots(flex ? q : nullptr));
                 TRY(reduce_to(h, h->partial, h->nb_partial, 0));
                 if (flex) TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, 1));
                 TRY(fetch(h, flex ? 2 : 1, tmp));
                 const double rz_new = tmp[0];
-                const double beta = flex ? (rz_new - tmp[1]) / rz : rz_new / rz;
+                const double beta = flex ? -alpha * tmp[1] / rz : rz_new / rz;
                 rz = rz_new;
-                HIPCHK(h, launch_axpby<double>(cnt, 1.0, z, beta, p, h->st));
+                HIPCHK(h, direction(beta));
             }
         } else {
             // iterative refinement / stationary: x += B r, r = b - A x (the residual is exact)

@@ -85,13 +85,17 @@ hipError_t launch_dot_partial(const T* x, const T* y, int64_t n, double* partial
 hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t st);
 template <typename T>
 hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStream_t st);  // y = a x + b y
-// CG update: x += alpha p, r -= alpha q (ro = r before the update if ro != null), and
-// partial sums of r . r over nblocks workgroups
+// CG update: x += alpha p, r -= alpha q (and r32 = FP32 copy of the new r if r32 != null),
+// and partial sums of r . r over nblocks workgroups
 hipError_t launch_cg_update(int64_t n, double alpha, const double* p, const double* q, double* x,
-                            double* r, double* ro, double* partial, int nblocks, hipStream_t st);
-// partial sums of z . r and z . ro (two arrays of nblocks)
-hipError_t launch_dot2(int64_t n, const double* z, const double* r, const double* ro,
-                       double* partial, int nblocks, hipStream_t st);
+                            double* r, float* r32, double* partial, int nblocks, hipStream_t st);
+// partial sums of z . r and z . q (two arrays of nblocks; the second only if q != null)
+template <typename Z>
+hipError_t launch_dot2(int64_t n, const Z* z, const double* r, const double* q, double* partial,
+                       int nblocks, hipStream_t st);
+// p = z + beta p (beta = 0 overwrites p without reading it)
+template <typename Z>
+hipError_t launch_zpbp(int64_t n, const Z* z, double beta, double* p, hipStream_t st);
 hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_zero_boundary(int ncomp, int n, T* x, hipStream_t st);

@@ -151,35 +151,51 @@ __device__ __forceinline__ void block_sum_store(double v, double* __restrict__ o
     __syncthreads();
 }
 
+// x += alpha p, r -= alpha q, and r . r; with r32 the new residual is also stored in
+// FP32 (the input of the FP32 V-cycle)
 __global__ void __launch_bounds__(NT)
 k_cg_update(int64_t n, double alpha, const double* __restrict__ p, const double* __restrict__ q,
-            double* __restrict__ x, double* __restrict__ r, double* __restrict__ ro,
+            double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
             double* __restrict__ partial) {
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * NT;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
         x[i] += alpha * p[i];
-        const double r0 = r[i];
-        if (ro) ro[i] = r0;
-        const double r1 = r0 - alpha * q[i];
+        const double r1 = r[i] - alpha * q[i];
         r[i] = r1;
+        if (r32) r32[i] = (float)r1;
         acc += r1 * r1;
     }
     block_sum_store(acc, partial + blockIdx.x);
 }
 
+// z . r and (with q) z . q, z in FP64 or FP32 (the FP32 V-cycle's output, widened)
+template <typename Z>
 __global__ void __launch_bounds__(NT)
-k_dot2(int64_t n, const double* __restrict__ z, const double* __restrict__ r,
-       const double* __restrict__ ro, double* __restrict__ partial) {
+k_dot2(int64_t n, const Z* __restrict__ z, const double* __restrict__ r,
+       const double* __restrict__ q, double* __restrict__ partial) {
     double a = 0.0, b = 0.0;
     const int64_t stride = (int64_t)gridDim.x * NT;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
-        const double zi = z[i];
+        const double zi = (double)z[i];
         a += zi * r[i];
-        if (ro) b += zi * ro[i];
+        if (q) b += zi * q[i];
     }
     block_sum_store(a, partial + blockIdx.x);
     block_sum_store(b, partial + gridDim.x + blockIdx.x);
+}
+
+// p = z + beta p (beta = 0: p = z without reading p), z in FP64 or FP32
+template <typename Z>
+__global__ void __launch_bounds__(NT)
+k_zpbp(int64_t n, const Z* __restrict__ z, double beta, double* __restrict__ p) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    if (beta == 0.0) {
+        for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) p[i] = (double)z[i];
+    } else {
+        for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride)
+            p[i] = (double)z[i] + beta * p[i];
+    }
 }
 
 // FP64 -> BF16 with a single round-to-nearest-even: round to FP32 with
@@ -395,17 +411,31 @@ hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStre
     return hipGetLastError();
 }
 hipError_t launch_cg_update(int64_t n, double alpha, const double* p, const double* q, double* x,
-                            double* r, double* ro, double* partial, int nblocks, hipStream_t st) {
+                            double* r, float* r32, double* partial, int nblocks, hipStream_t st) {
     if (!p || !q || !x || !r || !partial || nblocks <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cg_update, dim3(nblocks), dim3(NT), 0, st, n, alpha, p, q, x, r, ro, partial);
+    hipLaunchKernelGGL(k_cg_update, dim3(nblocks), dim3(NT), 0, st, n, alpha, p, q, x, r, r32, partial);
     return hipGetLastError();
 }
-hipError_t launch_dot2(int64_t n, const double* z, const double* r, const double* ro,
-                       double* partial, int nblocks, hipStream_t st) {
+template <typename Z>
+hipError_t launch_dot2(int64_t n, const Z* z, const double* r, const double* q, double* partial,
+                       int nblocks, hipStream_t st) {
     if (!z || !r || !partial || nblocks <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dot2, dim3(nblocks), dim3(NT), 0, st, n, z, r, ro, partial);
+    hipLaunchKernelGGL(k_dot2<Z>, dim3(nblocks), dim3(NT), 0, st, n, z, r, q, partial);
     return hipGetLastError();
 }
+template hipError_t launch_dot2<double>(int64_t, const double*, const double*, const double*, double*,
+                                        int, hipStream_t);
+template hipError_t launch_dot2<float>(int64_t, const float*, const double*, const double*, double*,
+                                       int, hipStream_t);
+template <typename Z>
+hipError_t launch_zpbp(int64_t n, const Z* z, double beta, double* p, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!z || !p) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zpbp<Z>, dim3(grid_stride(n)), dim3(NT), 0, st, n, z, beta, p);
+    return hipGetLastError();
+}
+template hipError_t launch_zpbp<double>(int64_t, const double*, double, double*, hipStream_t);
+template hipError_t launch_zpbp<float>(int64_t, const float*, double, double*, hipStream_t);
 hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (!src || !dst) return hipErrorInvalidValue;

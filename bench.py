@@ -113,8 +113,8 @@ def summarize_profile(d: str, command_prefix: str) -> str:
               "-o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline",
               "",
               f"Total kernel time {total / 1e6:.1f} ms.  k_cube template arguments: <components, "
-              "vector type, coefficient type, mode (0 apply, 1 residual, 2 Jacobi, 3 apply with dot), "
-              "stored blocks>.",
+              "vector type, coefficient type, mode (0 apply, 1 residual, 2 Jacobi-type pass, 3 apply "
+              "with dot, 4 first two passes from zero, 5 Chebyshev pass), stored blocks>.",
               "",
               "| kernel | calls | avg us | total ms | % |",
               "|---|---|---|---|---|"]
@@ -266,6 +266,10 @@ def device_inputs(w, dev, chunk: int = 1 << 25):
     return nus, f.reshape(-1)
 
 
+def progress(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def cold_apply_us(H, level, u, v, reps=10):
     """Median duration of one apply with the Infinity Cache flushed before each (HIP events)."""
     import torch
@@ -298,12 +302,15 @@ def report_large(args, dev) -> dict:
     out = {"report": w.name, "description": w.description, "levels": L + 1,
            "free_dofs": nc * (2 ** (L + 1) - 1) ** 3, "input_generation_s": round(t_gen, 2)}
     t0 = time.perf_counter()
-    H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64")
+    H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64", smoother=args.smoother)
     out["setup_fp64_s"] = round(time.perf_counter() - t0, 3)
+    out["smoother"] = args.smoother
+    progress(f"[large] inputs {t_gen:.1f} s, FP64 hierarchy {out['setup_fp64_s']:.1f} s")
     b = H64.load_vector(f)
     del f
     x, s64 = H64.solve(b, solver="pcg", tol=w.tol, max_iter=4000, raise_on_noconv=False,
                        record_history=False)
+    progress(f"[large] FP64-MG PCG {s64['iterations']} it {s64['seconds']:.2f} s")
     out["fp64_mg_pcg"] = {k: s64[k] for k in ("iterations", "seconds", "rel_residual", "converged",
                                                 "floor_limited")}
     n = 2 ** (L + 1)
@@ -319,10 +326,11 @@ def report_large(args, dev) -> dict:
     out["stored_block_bytes_fp64"] = int(sum(i["block_bytes"] for i in info))
     dev64 = H64.device_bytes()
     t0 = time.perf_counter()
-    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype="bf16")
+    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype="bf16", smoother=args.smoother)
     out["setup_mixed_s"] = round(time.perf_counter() - t0, 3)
     x32, s32 = H32.solve(b, solver="fcg", tol=w.tol, max_iter=4000, raise_on_noconv=False,
                          record_history=False)
+    progress(f"[large] FP32-MG FCG {s32['iterations']} it {s32['seconds']:.2f} s")
     out["fp32_mg_fcg"] = {k: s32[k] for k in ("iterations", "seconds", "rel_residual", "converged",
                                                 "floor_limited")}
     u32, v32 = u.float(), torch.empty_like(u, dtype=torch.float32)
@@ -358,9 +366,10 @@ def report_stokes(args, dev) -> dict:
     nus, f = device_inputs(w, dev)
     out = {"report": w.name, "description": w.description,
            "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3,
-           "fgmres_restart": args.stokes_restart}
+           "fgmres_restart": args.stokes_restart, "smoother": args.smoother}
     for mg, solver in (("f32", "fgmres"), ("f64", "fgmres"), ("f64", "minres")):
-        H = Hierarchy(L, 3, nus[L], nus[:L], mg_dtype=mg, mg_nu_dtype=("bf16" if mg == "f32" else "f64"))
+        H = Hierarchy(L, 3, nus[L], nus[:L], mg_dtype=mg, mg_nu_dtype=("bf16" if mg == "f32" else "f64"),
+                      smoother=args.smoother)
         S = Stokes(H)
         fu = H.load_vector(f)
         _, _, st = S.solve(fu, solver=solver, restart=args.stokes_restart, tol=w.tol,
@@ -391,7 +400,7 @@ def report_adjoint(args, dev) -> dict:
     nu_c = [torch.from_numpy(np.exp(g.log_nu(element_centroids(l)))).to(dev) for l in range(L)]
     f = torch.from_numpy(np.ascontiguousarray(np.asarray(g.force(cf, 3)).T)).to(dev).reshape(-1)
     log_obs = log_nu + torch.from_numpy(g.noise(log_nu.numel())).to(dev)
-    H = Hierarchy(L, 3, torch.exp(log_nu), nu_c)
+    H = Hierarchy(L, 3, torch.exp(log_nu), nu_c, smoother=args.smoother)
     b = H.load_vector(f)
     with torch.no_grad():
         obs = dsolve(log_obs, b, H, nu_c, tol=w.tol).clone()
@@ -411,7 +420,7 @@ def report_adjoint(args, dev) -> dict:
     hom = -float(torch.dot(u.detach() - obs, u.detach()))
     out = {"report": w.name, "description": w.description, "forward_s": round(t_fwd, 4),
            "adjoint_and_gradient_s": round(t_bwd, 4), "J": J_value,
-           "homogeneity_rel_err": abs(float(gg.sum()) - hom) / abs(hom)}
+           "homogeneity_rel_err": abs(float(gg.sum()) - hom) / abs(hom), "smoother": args.smoother}
     H.close()
     return out
 

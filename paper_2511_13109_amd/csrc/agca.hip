@@ -510,10 +510,21 @@ int32_t estimate_eigenvalues(agca_hier* h) {
         HIPCHK(h, launch_axpby<double>(cnt, 1.0 / std::sqrt(s), w, 0.0, v, h->st));
         std::vector<double> alpha, beta;
         double b = 0.0;
+        const LevelOp<double> op = level_op<double>(h, l);
         for (int k = 0; k < kLanczosSteps; ++k) {
             double a = 0.0;
-            TRY(do_cube<double>(h, l, MODE_APPLY, v, nullptr, y, 0.0));
-            TRY(do_dot<double>(h, v, y, cnt, &a));
+            if (op.sten) {
+                TRY(do_cube<double>(h, l, MODE_APPLY, v, nullptr, y, 0.0));
+                TRY(do_dot<double>(h, v, y, cnt, &a));
+            } else {
+                // element-loop level: y = A v with v . A v in the same pass
+                int nbq = 0;
+                double tmp[1];
+                HIPCHK(h, launch_cube_dot(nc, op, v, y, h->partial, &nbq, h->st));
+                TRY(reduce_to(h, h->partial, nbq, 0));
+                TRY(fetch(h, 1, tmp));
+                a = tmp[0];
+            }
             HIPCHK(h, launch_div_or_zero(cnt, y, lv.diag, w, h->st));
             HIPCHK(h, launch_axpby<double>(cnt, -a, v, 1.0, w, h->st));
             if (k > 0) HIPCHK(h, launch_axpby<double>(cnt, -b, vprev, 1.0, w, h->st));

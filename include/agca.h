@@ -254,8 +254,10 @@ typedef struct {
 /* Solve [[A, B^T], [B, 0]] (u, p) = (f, g) in FP64 with the block-diagonal
  * preconditioner diag(one AGCA V-cycle of A, diag(m)^-1): FGMRES(restart), right
  * preconditioned with modified Gram-Schmidt (any mg_dtype: the FP32 V-cycle makes the
- * preconditioner non-linear), or MINRES (mg_dtype F64 only: it needs a fixed SPD
- * preconditioner; its true residual is checked every step).  The returned p has
+ * preconditioner non-linear), or MINRES (its theory needs a fixed SPD preconditioner,
+ * which the FP32 V-cycle is only up to FP32 rounding; the true residual is checked every
+ * step, so a run that stagnates reports AGCA_E_NOCONV, never a false convergence).  The
+ * returned p has
  * zero mean over the pressure nodes.  Work space: 2 restart + 5 (FGMRES) or 10
  * (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy.
  * Returns AGCA_OK when converged, AGCA_E_NOCONV (u, p, stats filled) otherwise;

@@ -1565,8 +1565,6 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
         return fail(AGCA_E_INVALID, "unknown Stokes solver");
     if (o->solver == AGCA_STOKES_FGMRES && (o->restart < 1 || o->restart > AGCA_RED_SLOTS - 2))
         return fail(AGCA_E_INVALID, "restart must be in [1, 126]");
-    if (o->solver == AGCA_STOKES_MINRES && mg32(h))
-        return fail(AGCA_E_INVALID, "MINRES needs the FP64 V-cycle (a fixed SPD preconditioner)");
     TRY(ensure_solver_vectors(h));
     std::memset(stats, 0, sizeof(*stats));
     const StokesDims d = stokes_dims(h);

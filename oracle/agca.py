@@ -15,8 +15,12 @@
 Flag (element-wise viscosity-variation test): a coarse element m on level l < L
 is flagged when the maximum of the finest-level coefficient over its finest
 descendants exceeds tau times the minimum (strict, in FP64).  The paper's own
-test (eq. (2.8)) is a gradient test at macro-element granularity; the ratio
-test is the reading used for the benchmark problems.
+test (eq. (2.8)) is a gradient test at macro-element granularity: the
+coefficient is interpolated into the P1 space of the finest level, the norm of
+its (element-wise constant) gradient is taken on every finest element, and a
+macro element (level 0) is Galerkin-coarsened on all coarse levels when the
+largest norm inside it exceeds the tolerance; ``macro_gradient_max`` computes
+those maxima and mode FLAG_MACRO takes the 48 macro flags from the caller.
 
 Local block layout: a block belongs to one coarse element; its rows and columns
 are ordered (component c, vertex a) -> 4 c + a, with the element's vertices in
@@ -31,11 +35,37 @@ from typing import Dict, List, Optional
 import numpy as np
 import scipy.sparse as sp
 
-from .fem import assemble, element_dofs, element_matrices
+from .fem import assemble, element_dofs, element_geometry, element_matrices
 from .mesh import Level, ancestor
 from .transfer import composite
 
-FLAG_RATIO, FLAG_GRADIENT, FLAG_NONE, FLAG_ALL = 0, 1, 2, 3
+FLAG_RATIO, FLAG_MACRO, FLAG_NONE, FLAG_ALL = 0, 1, 2, 3
+
+
+def macro_gradient_max(levels: List[Level], eta_nodes: np.ndarray) -> np.ndarray:
+    """max over the finest elements d inside each macro element M of ||grad eta_h|_d||
+    (eq. (2.8)); eta_h is the P1 function with nodal values ``eta_nodes`` (by canonical
+    node id of the finest level).  Returned by canonical id of level 0 (48 values)."""
+    L = len(levels) - 1
+    fine = levels[L]
+    g, _ = element_geometry(fine.coords[fine.tets])            # (T, 4, 3), Bey order
+    vals = eta_nodes[fine.node_id[fine.tets]]                  # (T, 4)
+    grad = np.einsum("tb,tbd->td", vals, g)
+    norm = np.sqrt((grad ** 2).sum(axis=1))
+    anc = ancestor(levels, 0, L)                               # Bey index on level 0
+    out = np.zeros(levels[0].tets.shape[0])
+    np.maximum.at(out, anc, norm)
+    canon = np.empty_like(out)
+    canon[levels[0].elem_id] = out
+    return canon
+
+
+def macro_descendant_flags(levels: List[Level], macro_flags: np.ndarray, l: int) -> np.ndarray:
+    """Flag per canonical id of level l: the flag of the element's macro ancestor."""
+    anc = ancestor(levels, 0, l)                               # Bey index on level 0
+    out = np.zeros(levels[l].tets.shape[0], dtype=bool)
+    out[levels[l].elem_id] = np.asarray(macro_flags, dtype=bool)[levels[0].elem_id[anc]]
+    return out
 
 
 def descendant_minmax(levels: List[Level], nu_fine: np.ndarray, l: int):
@@ -59,15 +89,17 @@ def descendant_minmax(levels: List[Level], nu_fine: np.ndarray, l: int):
 
 
 def flags(levels: List[Level], nu_fine: np.ndarray, l: int, tau: float = 10.0,
-          mode: int = FLAG_RATIO) -> np.ndarray:
+          mode: int = FLAG_RATIO, macro_flags: Optional[np.ndarray] = None) -> np.ndarray:
     """Boolean flag per canonical element id of level l (l < L)."""
     T = levels[l].tets.shape[0]
     if mode == FLAG_NONE:
         return np.zeros(T, dtype=bool)
     if mode == FLAG_ALL:
         return np.ones(T, dtype=bool)
+    if mode == FLAG_MACRO:
+        return macro_descendant_flags(levels, macro_flags, l)
     if mode != FLAG_RATIO:
-        raise NotImplementedError("only the ratio test is implemented in the oracle")
+        raise ValueError(mode)
     mn, mx = descendant_minmax(levels, nu_fine, l)
     return mx > tau * mn
 
@@ -83,7 +115,8 @@ def fine_mask_under(levels: List[Level], flag_l: np.ndarray, l: int) -> np.ndarr
 
 
 def agca_operators(levels: List[Level], Ps: List[sp.csr_matrix], nu_levels: List[np.ndarray],
-                   ncomp: int, tau: float = 10.0, mode: int = FLAG_RATIO) -> Dict:
+                   ncomp: int, tau: float = 10.0, mode: int = FLAG_RATIO,
+                   macro_flags: Optional[np.ndarray] = None) -> Dict:
     """Full (Neumann) AGCA operators on every level, plus the flags.
 
     ``nu_levels[l]`` is the coefficient by canonical element id on level l;
@@ -96,7 +129,7 @@ def agca_operators(levels: List[Level], Ps: List[sp.csr_matrix], nu_levels: List
     ops[L] = assemble(levels[L], nu_fine, ncomp)
     fl[L] = np.zeros(levels[L].tets.shape[0], dtype=bool)
     for l in range(L - 1, -1, -1):
-        f = flags(levels, nu_fine, l, tau, mode)
+        f = flags(levels, nu_fine, l, tau, mode, macro_flags)
         fl[l] = f
         A = assemble(levels[l], nu_levels[l], ncomp, elem_mask=~f)
         if f.any():

@@ -103,12 +103,13 @@ def lambda_max_estimate(A, D: np.ndarray, x0: np.ndarray, steps: int = LANCZOS_S
 
 
 def build(L: int, nu_levels: List[np.ndarray], ncomp: int, tau: float = 10.0,
-          mode: int = _agca.FLAG_RATIO, levels=None, smoother: str = "jacobi") -> Hierarchy:
+          mode: int = _agca.FLAG_RATIO, levels=None, smoother: str = "jacobi",
+          macro_flags: Optional[np.ndarray] = None) -> Hierarchy:
     """Assemble the AGCA hierarchy for coefficients ``nu_levels`` (canonical ids per level)."""
     if levels is None:
         levels = mesh.hierarchy(L)
     Pf = transfer.prolongations(levels, ncomp)
-    res = _agca.agca_operators(levels, Pf, nu_levels, ncomp, tau, mode)
+    res = _agca.agca_operators(levels, Pf, nu_levels, ncomp, tau, mode, macro_flags)
     free = [fem.free_dofs(lv, ncomp) for lv in levels]
     A = [fem.restrict_free(op, fr) for op, fr in zip(res["ops"], free)]
     P = [Pf[l][free[l + 1]][:, free[l]].tocsr() for l in range(L)]

@@ -61,9 +61,13 @@ typedef enum { AGCA_F64 = 0, AGCA_F32 = 1, AGCA_BF16 = 2 } agca_dtype;
  *  RATIO : a level-l element (l < L) uses its stored Galerkin block when the
  *          maximum of the finest coefficient over its finest descendants exceeds
  *          flag_ratio times the minimum (strict, FP64); DCA otherwise.
+ *  MACRO : the paper's macro granularity (eqs. (2.8)-(2.9)): every coarse element
+ *          inside a macro element k (level-0 element id k, 0..47) with
+ *          macro_flags[k] != 0 uses its stored Galerkin block, every other one
+ *          DCA.  agca_macro_gradient() gives the gradient test of (2.8).
  *  NONE  : DCA on every coarse element (eq. (2.5)).
  *  ALL   : Galerkin blocks on every coarse element (eqs. (2.6)-(2.7)). */
-enum { AGCA_FLAG_RATIO = 0, AGCA_FLAG_NONE = 2, AGCA_FLAG_ALL = 3 };
+enum { AGCA_FLAG_RATIO = 0, AGCA_FLAG_MACRO = 1, AGCA_FLAG_NONE = 2, AGCA_FLAG_ALL = 3 };
 
 /* Smoother of the V-cycle.
  *  JACOBI    : damped Jacobi, pre_sweeps / post_sweeps sweeps with damping omega.
@@ -89,6 +93,7 @@ typedef struct {
     double flag_ratio;       /* tau (10 in the paper's experiments)                         */
     double omega;            /* Jacobi damping (2/3)                                        */
     uint64_t mem_limit_bytes;/* 0 = unlimited; larger totals fail with AGCA_E_OOM           */
+    uint8_t macro_flags[48]; /* AGCA_FLAG_MACRO: nonzero = Galerkin-coarsen that macro element */
 } agca_config;
 
 typedef struct {
@@ -265,6 +270,14 @@ typedef struct {
  * or the MINRES true residuals. */
 int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* opts, const double* f,
                           const double* g, double* u, double* p, agca_solve_stats* stats);
+
+/* Gradient test of eq. (2.8): for every macro element k (level-0 element id, 0..47)
+ * the largest norm of grad eta_h over the finest elements inside it, eta_h the P1
+ * function on level L with nodal values eta_nodes (device, (2^(L+1)+1)^3 doubles by
+ * node id x + (n+1)(y + (n+1) z)).  gmax: host, 48 doubles.  Runs on `stream`
+ * (a hipStream_t, may be null) and waits for it; allocates 384 bytes of device memory
+ * for the call.  AGCA_E_INVALID for a bad L or a non-finite result. */
+int32_t agca_macro_gradient(int32_t L, const double* eta_nodes, double* gmax, void* stream);
 
 /* b = load vector of a per-element constant source: b_i = sum_e f_e |e| / 4 on
  * level L.  f: device, ncomp blocks of 6 n_L^3 doubles; b: device FP64 level vector. */

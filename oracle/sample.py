@@ -188,10 +188,11 @@ def block_at_point(coarse: int, fine: int, p, nu_fine_by_id: np.ndarray, ncomp: 
 
 def coarse_apply_at_node(level: int, fine: int, node_xyz, nu_level_by_id: np.ndarray,
                          nu_fine_by_id: np.ndarray, ncomp: int, u_full: np.ndarray,
-                         tau: float = 10.0, seed: int = 0) -> np.ndarray:
+                         tau: float = 10.0, seed: int = 0, macro_flags=None) -> np.ndarray:
     """(A_l u) at one interior node of a coarse level (eq. (2.9)): the Galerkin block of
     every flagged element around the node, the DCA element matrix with the level's own
-    coefficient for the others."""
+    coefficient for the others.  Flags: the ratio test, or with ``macro_flags`` (48
+    values by level-0 element id) the flag of the macro element holding the element."""
     n = 2 ** (level + 1)
     nn = (n + 1) ** 3
     free = _free_mask(level)
@@ -199,7 +200,10 @@ def coarse_apply_at_node(level: int, fine: int, node_xyz, nu_level_by_id: np.nda
     out = np.zeros(ncomp)
     for c4, nid, eid, a in elements_around(level, x, seed):
         cen = c4.mean(axis=0)
-        _, flagged = flag_at_point(level, fine, cen, nu_fine_by_id, tau)
+        if macro_flags is None:
+            _, flagged = flag_at_point(level, fine, cen, nu_fine_by_id, tau)
+        else:
+            flagged = bool(macro_flags[locate(0, cen)[2]])
         if flagged:
             _, K = block_at_point(level, fine, cen, nu_fine_by_id, ncomp)
             order = np.argsort(c4.sum(axis=1), kind="stable")

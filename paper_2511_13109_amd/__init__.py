@@ -12,7 +12,7 @@ from . import grid  # noqa: F401
 def __getattr__(name):
     # the binding loads libagca.so on first use and fails loudly if it is missing
     if name in ("Hierarchy", "Stokes", "coefficients_from_field", "AGCAError", "default_config",
-                "validate_config"):
+                "validate_config", "macro_gradient"):
         from . import agca
         return getattr(agca, name)
     if name == "autograd":

@@ -12,7 +12,7 @@ AGCA_OK, AGCA_E_INVALID, AGCA_E_OOM, AGCA_E_HIP, AGCA_E_NOCONV, AGCA_E_NUMERIC, 
     0, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
 SMOOTH_JACOBI, SMOOTH_CHEBYSHEV = 0, 1
-FLAG_RATIO, FLAG_NONE, FLAG_ALL = 0, 2, 3
+FLAG_RATIO, FLAG_MACRO, FLAG_NONE, FLAG_ALL = 0, 1, 2, 3
 SOLVER_PCG, SOLVER_FCG, SOLVER_IR, SOLVER_STATIONARY = 0, 1, 2, 3
 MAX_HISTORY = 1024
 
@@ -24,7 +24,8 @@ class Config(C.Structure):
     _fields_ = [("L", C.c_int32), ("ncomp", C.c_int32), ("flag_mode", C.c_int32),
                 ("mg_dtype", C.c_int32), ("mg_nu_dtype", C.c_int32), ("pre_sweeps", C.c_int32),
                 ("post_sweeps", C.c_int32), ("smoother", C.c_int32), ("flag_ratio", C.c_double),
-                ("omega", C.c_double), ("mem_limit_bytes", C.c_uint64)]
+                ("omega", C.c_double), ("mem_limit_bytes", C.c_uint64),
+                ("macro_flags", C.c_uint8 * 48)]
 
 
 class LevelInfo(C.Structure):
@@ -60,6 +61,7 @@ SIGNATURES = {
     "agca_create": (C.c_int32, [C.POINTER(Config), C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p,
                                 C.POINTER(C.c_void_p)]),
     "agca_destroy": (C.c_int32, [C.c_void_p]),
+    "agca_macro_gradient": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "agca_set_nu": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "agca_set_log_nu": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "agca_query": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(LevelInfo)]),

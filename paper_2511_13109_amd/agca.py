@@ -19,8 +19,8 @@ from ._lib import AGCAError, check  # noqa: F401
 
 _DT = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16}
 _TORCH = {_lib.F64: torch.float64, _lib.F32: torch.float32}
-_FLAG = {"ratio": _lib.FLAG_RATIO, "none": _lib.FLAG_NONE, "dca": _lib.FLAG_NONE,
-         "all": _lib.FLAG_ALL, "gca": _lib.FLAG_ALL}
+_FLAG = {"ratio": _lib.FLAG_RATIO, "macro": _lib.FLAG_MACRO, "none": _lib.FLAG_NONE,
+         "dca": _lib.FLAG_NONE, "all": _lib.FLAG_ALL, "gca": _lib.FLAG_ALL}
 _SOLVER = {"pcg": _lib.SOLVER_PCG, "fcg": _lib.SOLVER_FCG, "ir": _lib.SOLVER_IR,
            "stationary": _lib.SOLVER_STATIONARY}
 
@@ -51,6 +51,18 @@ def validate_config(cfg: _lib.Config) -> int:
     return _lib.load().agca_validate_config(C.byref(cfg))
 
 
+def macro_gradient(L: int, eta_nodes: torch.Tensor, stream=None) -> np.ndarray:
+    """Largest |grad eta_h| over the finest elements of each of the 48 macro elements
+    (eq. (2.8)); eta_nodes: (2^(L+1)+1)^3 float64 device tensor of nodal values."""
+    if eta_nodes.dtype != torch.float64 or eta_nodes.numel() != (2 ** (L + 1) + 1) ** 3:
+        raise ValueError("eta_nodes must hold (2^(L+1)+1)^3 float64 nodal values")
+    st = stream if stream is not None else torch.cuda.current_stream(eta_nodes.device)
+    out = np.zeros(48)
+    check(_lib.load().agca_macro_gradient(L, _ptr(eta_nodes), out.ctypes.data_as(C.c_void_p),
+                                          C.c_void_p(st.cuda_stream)), "agca_macro_gradient")
+    return out
+
+
 class Hierarchy:
     """AGCA multigrid hierarchy on levels 0..L (paper Section 2).
 
@@ -62,7 +74,7 @@ class Hierarchy:
                  flag_mode: str = "ratio", tau: float = 10.0, mg_dtype: str = "f64",
                  mg_nu_dtype: Optional[str] = None, pre: int = 2, post: int = 2,
                  omega: float = 2.0 / 3.0, mem_limit_bytes: int = 0, stream=None,
-                 smoother: str = "jacobi"):
+                 smoother: str = "jacobi", macro_flags: Optional[Sequence[bool]] = None):
         self._lib = _lib.load()
         cfg = default_config()
         cfg.L, cfg.ncomp = L, ncomp
@@ -73,6 +85,11 @@ class Hierarchy:
         cfg.pre_sweeps, cfg.post_sweeps, cfg.omega = pre, post, omega
         cfg.smoother = {"jacobi": _lib.SMOOTH_JACOBI, "chebyshev": _lib.SMOOTH_CHEBYSHEV}[smoother]
         cfg.mem_limit_bytes = mem_limit_bytes
+        if flag_mode == "macro":
+            if macro_flags is None or len(macro_flags) != 48:
+                raise ValueError("flag_mode 'macro' needs 48 macro flags")
+            for k, f in enumerate(macro_flags):
+                cfg.macro_flags[k] = 1 if f else 0
         self.cfg = cfg
         self.L, self.ncomp = L, ncomp
         self.mg_dtype = cfg.mg_dtype

@@ -409,8 +409,8 @@ int32_t validate(const agca_config* c) {
     if (!c) return fail(AGCA_E_INVALID, "null config");
     if (c->L < 1 || c->L > 9) return fail(AGCA_E_INVALID, "L must be in [1, 9]");
     if (c->ncomp != 1 && c->ncomp != 3) return fail(AGCA_E_INVALID, "ncomp must be 1 or 3");
-    if (c->flag_mode != AGCA_FLAG_RATIO && c->flag_mode != AGCA_FLAG_NONE &&
-        c->flag_mode != AGCA_FLAG_ALL)
+    if (c->flag_mode != AGCA_FLAG_RATIO && c->flag_mode != AGCA_FLAG_MACRO &&
+        c->flag_mode != AGCA_FLAG_NONE && c->flag_mode != AGCA_FLAG_ALL)
         return fail(AGCA_E_INVALID, "unknown flag_mode");
     if (c->mg_dtype != AGCA_F64 && c->mg_dtype != AGCA_F32)
         return fail(AGCA_E_INVALID, "mg_dtype must be F64 or F32");
@@ -648,6 +648,9 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
             for (void* p : tmp) hipFree(p);
             tmp.clear();
         };
+        uint64_t macro_bits = 0;
+        for (int k = 0; k < 48; ++k)
+            if (h->cfg.macro_flags[k]) macro_bits |= (uint64_t)1 << k;
         int32_t rc = AGCA_OK;
         for (int i = 0; i < 2 && rc == AGCA_OK; ++i) {
             rc = talloc((void**)&mn[i], emax * sizeof(double));
@@ -666,8 +669,10 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
                                ? launch_minmax_from_fine(h->lv[l].n, h->lv[L].nu64, mn[cur], mx[cur], h->st)
                                : launch_minmax_up(h->lv[l].n, mn[fin], mx[fin], mn[cur], mx[cur], h->st);
             if (e == hipSuccess)
-                e = launch_flag(h->lv[l].elems, mn[cur], mx[cur], h->cfg.flag_ratio, h->cfg.flag_mode,
-                                h->lv[l].flag, h->st);
+                e = (h->cfg.flag_mode == AGCA_FLAG_MACRO)
+                        ? launch_flag_macro(h->lv[l].elems, h->lv[l].n, l, macro_bits, h->lv[l].flag, h->st)
+                        : launch_flag(h->lv[l].elems, mn[cur], mx[cur], h->cfg.flag_ratio, h->cfg.flag_mode,
+                                      h->lv[l].flag, h->st);
             if (e == hipSuccess)
                 e = launch_compact(h->lv[l].elems, h->lv[l].flag, h->lv[l].blk, h->lv[l].blk_soa,
                                    h->lv[l].ids, cnt_dev + l, scratch, sbytes, h->st);
@@ -836,6 +841,31 @@ int32_t free_blocks(agca_hier* h) {
 extern "C" {
 
 const char* agca_last_error(void) { return g_err.c_str(); }
+
+int32_t agca_macro_gradient(int32_t L, const double* eta_nodes, double* gmax, void* stream) {
+    if (L < 1 || L > 9) return fail(AGCA_E_INVALID, "L must be in [1, 9]");
+    if (!eta_nodes || !gmax) return fail(AGCA_E_INVALID, "null pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned long long* d = nullptr;
+    if (hipMalloc((void**)&d, 48 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AGCA_E_OOM, "hipMalloc failed");
+    }
+    unsigned long long bits[48];
+    hipError_t e = hipMemsetAsync(d, 0, sizeof(bits), st);
+    if (e == hipSuccess) e = launch_macro_grad_max(L, eta_nodes, d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(bits, d, sizeof(bits), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(d);
+    if (e != hipSuccess) return fail(AGCA_E_HIP, std::string("macro gradient: ") + hipGetErrorString(e));
+    for (int k = 0; k < 48; ++k) {
+        double v;
+        std::memcpy(&v, &bits[k], sizeof(v));
+        if (!std::isfinite(v)) return fail(AGCA_E_INVALID, "non-finite nodal values");
+        gmax[k] = v;
+    }
+    return AGCA_OK;
+}
 
 void agca_default_config(agca_config* c) {
     if (!c) return;

@@ -121,6 +121,12 @@ hipError_t launch_minmax_up(int n_coarse, const double* mn_f, const double* mx_f
                             double* mx, hipStream_t st);
 hipError_t launch_flag(int64_t ne, const double* mn, const double* mx, double tau, int mode,
                        int32_t* flag, hipStream_t st);
+// flag = 1 for the level-l elements (n = 2^(l+1) cells per axis) inside the macro
+// elements whose bit is set in `bits` (bit k = level-0 element id k)
+hipError_t launch_flag_macro(int64_t ne, int n, int l, uint64_t bits, int32_t* flag, hipStream_t st);
+// per macro element the largest |grad eta_h| over the finest elements of level L, as the
+// bit patterns of non-negative doubles, max-combined into gbits[48] (zeroed by the caller)
+hipError_t launch_macro_grad_max(int L, const double* eta, unsigned long long* gbits, hipStream_t st);
 // exclusive scan of flags -> blk index (or -1) and total count (device int64)
 hipError_t launch_compact(int64_t ne, const int32_t* flag, int32_t* blk, int32_t* blk_soa,
                           int32_t* ids, int64_t* count_dev, void* scratch, size_t scratch_bytes,

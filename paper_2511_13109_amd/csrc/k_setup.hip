@@ -66,6 +66,65 @@ k_flag(int64_t ne, const double* __restrict__ mn, const double* __restrict__ mx,
     flag[e] = f;
 }
 
+// Macro-element granularity (eqs. (2.8)-(2.9)).  A level-l element (cell c, order s)
+// lies in the macro cube c >> l; inside that cube the Kuhn simplex with axis order
+// (a1, a2, a3) is the set x_a1 >= x_a2 >= x_a3 of relative coordinates, so the macro
+// simplex holding the element is the descending order of its centroid's relative
+// coordinates.  In units of a quarter level-l cell that centroid is 4 (c - corner)
+// plus 3, 2, 1 along the element's own a1, a2, a3: integers with distinct residues
+// mod 4, hence never tied.
+__device__ __forceinline__ int macro_of(int64_t e, int n, int l) {
+    const int s = (int)(e % 6);
+    int64_t c = e / 6;
+    const int cx = (int)(c % n), cy = (int)((c / n) % n), cz = (int)(c / ((int64_t)n * n));
+    const int mx = cx >> l, my = cy >> l, mz = cz >> l;
+    auto w = [&](int ax) { return ax == axis1(s) ? 3 : (ax == axis2(s) ? 2 : 1); };
+    const int r0 = 4 * (cx - (mx << l)) + w(0);
+    const int r1 = 4 * (cy - (my << l)) + w(1);
+    const int r2 = 4 * (cz - (mz << l)) + w(2);
+    const int a1 = (r0 > r1) ? (r0 > r2 ? 0 : 2) : (r1 > r2 ? 1 : 2);
+    const int a3 = (r0 < r1) ? (r0 < r2 ? 0 : 2) : (r1 < r2 ? 1 : 2);
+    return order_index(a1, 3 - a1 - a3, a3) + 6 * (mx + 2 * (my + 2 * mz));
+}
+
+__global__ void __launch_bounds__(NT)
+k_flag_macro(int64_t ne, int n, int l, uint64_t bits, int32_t* __restrict__ flag) {
+    const int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (e >= ne) return;
+    flag[e] = (int32_t)((bits >> macro_of(e, n, l)) & 1u);
+}
+
+// max over the finest elements of each macro element of |grad eta_h| (P1 interpolant):
+// along the path of simplex s the gradient components are n (eta(k_j) - eta(k_{j-1}))
+// on axis a_j.  Norms are >= 0, so the maximum of their bit patterns as unsigned
+// integers is the maximum of the values (exact and order-independent).
+__global__ void __launch_bounds__(NT)
+k_macro_grad_max(int n, int l, const double* __restrict__ eta, unsigned long long* __restrict__ gbits) {
+    __shared__ unsigned long long loc[48];
+    if (threadIdx.x < 48) loc[threadIdx.x] = 0ull;
+    __syncthreads();
+    const int64_t ne = 6LL * n * n * n;
+    const int64_t n1 = n + 1;
+    const double scale = (double)n;
+    for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < ne; e += (int64_t)gridDim.x * NT) {
+        const int s = (int)(e % 6);
+        const int64_t c = e / 6;
+        const int64_t cx = c % n, cy = (c / n) % n, cz = c / ((int64_t)n * n);
+        const int64_t base = cx + n1 * (cy + n1 * cz);
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = path_corner(s, j);
+            v[j] = eta[base + (k & 1) + n1 * (((k >> 1) & 1) + n1 * (k >> 2))];
+        }
+        const double g1 = scale * (v[1] - v[0]), g2 = scale * (v[2] - v[1]), g3 = scale * (v[3] - v[2]);
+        const double nrm = sqrt(g1 * g1 + g2 * g2 + g3 * g3);
+        atomicMax(&loc[macro_of(e, n, l)], (unsigned long long)__double_as_longlong(nrm));
+    }
+    __syncthreads();
+    if (threadIdx.x < 48 && loc[threadIdx.x] != 0ull) atomicMax(&gbits[threadIdx.x], loc[threadIdx.x]);
+}
+
 __global__ void __launch_bounds__(NT)
 k_scatter_ids(int64_t ne, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
               int32_t* __restrict__ blk, int32_t* __restrict__ blk_soa, int32_t* __restrict__ ids,
@@ -259,6 +318,19 @@ hipError_t launch_flag(int64_t ne, const double* mn, const double* mx, double ta
                        int32_t* flag, hipStream_t st) {
     if (!mn || !mx || !flag) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_flag, dim3(grid_for(ne)), dim3(NT), 0, st, ne, mn, mx, tau, mode, flag);
+    return hipGetLastError();
+}
+hipError_t launch_flag_macro(int64_t ne, int n, int l, uint64_t bits, int32_t* flag, hipStream_t st) {
+    if (!flag || ne != 6LL * n * n * n || n != (2 << l)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_flag_macro, dim3(grid_for(ne)), dim3(NT), 0, st, ne, n, l, bits, flag);
+    return hipGetLastError();
+}
+hipError_t launch_macro_grad_max(int L, const double* eta, unsigned long long* gbits, hipStream_t st) {
+    if (!eta || !gbits || L < 0 || L > 12) return hipErrorInvalidValue;
+    const int n = 2 << L;
+    const int64_t ne = 6LL * n * n * n;
+    const unsigned blocks = (unsigned)std::min<int64_t>((ne + NT - 1) / NT, 4096);
+    hipLaunchKernelGGL(k_macro_grad_max, dim3(blocks), dim3(NT), 0, st, n, L, eta, gbits);
     return hipGetLastError();
 }
 hipError_t compact_scratch_bytes(int64_t ne, size_t* bytes) {

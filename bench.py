@@ -1,7 +1,8 @@
 """Benchmark of the AGCA multigrid hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-    python bench.py --workload sinker513|stokes257|adjoint129 [--level L]   (report lines)
+    python bench.py --workload sinker513|stokes257|adjoint129|coarsening [--level L]
+                                                            (report lines)
 
 Workload (default): the vector viscous block -div(2 nu eps(u)) = f on 129^3
 nodes (7 levels), 8 tanh-smoothed sinkers of radius 0.1, contrast 1e6,
@@ -425,6 +426,87 @@ def report_adjoint(args, dev) -> dict:
     return out
 
 
+def report_coarsening(args, dev) -> dict:
+    """Direct against adaptive against Galerkin coarsening (Sections 2.3, 4.2-4.3): PCG
+    iterations to 1e-8 of the vector viscous block with the FP64 V-cycle for the
+    coefficients eta_1..eta_4 and sharp multi-sinkers eta_6 at three dynamic ratios,
+    with DCA on every coarse level, the per-element ratio flag (tau = 10), the
+    macro-element gradient flag (eq. (2.8), nu = 10) and Galerkin coarsening on every
+    level; then the tolerance sweep of Fig. 9 on the tanh-smoothed cube."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy, macro_gradient
+    from workloads import Sinkers
+    from workloads.fields import ShapeField
+    from workloads.lattice import element_centroids
+    L = args.level or 5
+    n = 2 ** (L + 1)
+    p = np.arange((n + 1) ** 3)
+    xyz = np.stack([p % (n + 1), (p // (n + 1)) % (n + 1), p // (n + 1) ** 2], axis=1) / n
+    cents = [element_centroids(l) for l in range(L + 1)]
+    max_iter = 1000
+
+    def run(field, mode, tol_grad=10.0, nu=None, g=None):
+        if nu is None:
+            nu = [torch.from_numpy(field.nu(c)).to(dev) for c in cents]
+        if g is None:
+            g = macro_gradient(L, torch.from_numpy(field.nu(xyz)).to(dev))
+        mf = g > tol_grad
+        kw = {"flag_mode": mode}
+        if mode == "macro":
+            kw["macro_flags"] = mf
+        H = Hierarchy(L, 3, nu[L], nu[:L], smoother=args.smoother, **kw)
+        f = torch.from_numpy(np.ascontiguousarray(field.force(cents[L], 3).T)).to(dev).reshape(-1)
+        b = H.load_vector(f)
+        _, st = H.solve(b, solver="pcg", tol=1e-8, max_iter=max_iter, raise_on_noconv=False,
+                        record_history=False)
+        info = [H.query(l) for l in range(L)]
+        rec = {"iterations": st["iterations"] if (st["converged"] or st["floor_limited"]) else None,
+               "rel_residual": float("%.3g" % st["rel_residual"]),
+               "flagged_fraction": round(sum(i["flagged"] for i in info) / sum(i["elements"] for i in info), 4),
+               "block_bytes": int(sum(i["block_bytes"] for i in info))}
+        if mode == "macro":
+            rec["macros"] = int(mf.sum())
+        H.close()
+        return rec
+
+    fields = [("eta1 aligned cube", lambda dr: ShapeField("cube", dr)),
+              ("eta2 unaligned cube", lambda dr: ShapeField("ucube", dr)),
+              ("eta3 tanh cube omega=10", lambda dr: ShapeField("tcube", dr, 10.0)),
+              ("eta3 tanh cube omega=100", lambda dr: ShapeField("tcube", dr, 100.0)),
+              ("eta3 tanh cube omega=1000", lambda dr: ShapeField("tcube", dr, 1000.0)),
+              ("eta4 sphere", lambda dr: ShapeField("sphere", dr)),
+              ("eta6 1 sharp sinker", lambda dr: Sinkers(1, 2, radius=0.1, width=1e-9, contrast=dr)),
+              ("eta6 4 sharp sinkers", lambda dr: Sinkers(4, 2, radius=0.1, width=1e-9, contrast=dr)),
+              ("eta6 16 sharp sinkers", lambda dr: Sinkers(16, 2, radius=0.1, width=1e-9, contrast=dr))]
+    out = {"report": "coarsening", "levels": L + 1, "nodes_per_axis": n + 1, "smoother": args.smoother,
+           "solver": f"FP64-MG PCG to 1e-8, at most {max_iter} iterations (null: not reached)",
+           "cases": []}
+    for dr in (1e2, 1e4, 1e6):
+        for name, make in fields:
+            field = make(dr)
+            nu = [torch.from_numpy(field.nu(c)).to(dev) for c in cents]
+            g = macro_gradient(L, torch.from_numpy(field.nu(xyz)).to(dev))
+            rec = {"field": name, "DR": dr}
+            for mode in ("dca", "ratio", "macro", "gca"):
+                rec[mode] = run(field, mode, nu=nu, g=g)
+            progress(f"[coarsening] {name} DR={dr:g}: " + ", ".join(
+                f"{m} {rec[m]['iterations']}" for m in ("dca", "ratio", "macro", "gca")))
+            out["cases"].append(rec)
+    # Fig. 9: tolerance sweep of the macro gradient test on the tanh-smoothed cube
+    out["tolerance_sweep"] = []
+    for omega in (10.0, 100.0, 1000.0):
+        field = ShapeField("tcube", 1e6, omega)
+        nu = [torch.from_numpy(field.nu(c)).to(dev) for c in cents]
+        g = macro_gradient(L, torch.from_numpy(field.nu(xyz)).to(dev))
+        for tol in (1e-2, 1e0, 1e2, 1e4, 1e6):
+            rec = run(field, "macro", tol_grad=tol, nu=nu, g=g)
+            rec.update({"omega": omega, "tolerance": tol})
+            out["tolerance_sweep"].append(rec)
+            progress(f"[coarsening] tanh cube omega={omega:g} tol={tol:g}: {rec['macros']} macros, "
+                     f"{rec['iterations']} it, {rec['block_bytes'] / 1e6:.1f} MB")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,7 +544,8 @@ def main():
         return
     # the other workloads print a report line of their own (the benchmark line is the
     # 129^3 sinker workload)
-    reports = {"sinker513": report_large, "stokes257": report_stokes, "adjoint129": report_adjoint}
+    reports = {"sinker513": report_large, "stokes257": report_stokes, "adjoint129": report_adjoint,
+               "coarsening": report_coarsening}
     if args.workload in reports:
         print(json.dumps(reports[args.workload](args, dev)), flush=True)
         return

@@ -122,6 +122,54 @@ class Sinkers:
         return self.nu_lo + (self.nu_hi - self.nu_lo) * self.xi_torch(pts)
 
 
+class ShapeField:
+    """eta_1 to eta_4 of eqs. (3.6)-(3.9): nu = eta_low + (eta_high - eta_low) xi with
+    eta_high = DR^1/2, eta_low = DR^-1/2, and f = (0, 0, -xi) (3.11).
+
+    kind 'cube'   : xi_1, the box of half-width 1/8 around (1/2, 1/2, 1/2) (grid-aligned)
+         'ucube'  : xi_2, the same box around (11/24, 11/24, 11/24) (unaligned)
+         'tcube'  : xi_3, the unaligned box smoothed by tanh with steepness omega:
+                    prod_i (tanh(omega (x_i - c + 1/8)) - tanh(omega (x_i - c - 1/8))) / 2,
+                    reading the auxiliary function of (3.7) as the one (3.6) names
+         'sphere' : xi_4, the ball of radius 0.1 around (1/2, 1/2, 1/2)
+    """
+
+    C_UA = 11.0 / 24.0
+
+    def __init__(self, kind: str, contrast: float, omega: float = 10.0):
+        if kind not in ("cube", "ucube", "tcube", "sphere"):
+            raise ValueError(kind)
+        self.kind, self.omega = kind, float(omega)
+        self.nu_hi = math.sqrt(contrast)
+        self.nu_lo = 1.0 / math.sqrt(contrast)
+
+    def _xi(self, pts: np.ndarray) -> np.ndarray:
+        if self.kind == "cube":
+            return np.all(np.abs(pts - 0.5) <= 0.125, axis=1).astype(np.float64)
+        if self.kind == "ucube":
+            return np.all(np.abs(pts - self.C_UA) <= 0.125, axis=1).astype(np.float64)
+        if self.kind == "sphere":
+            return (((pts - 0.5) ** 2).sum(axis=1) <= 0.01).astype(np.float64)
+        w = self.omega
+        c = self.C_UA
+        t = 0.5 * (np.tanh(w * (pts - (c - 0.125))) - np.tanh(w * (pts - (c + 0.125))))
+        return t.prod(axis=1)
+
+    def xi(self, pts: np.ndarray) -> np.ndarray:
+        return _chunked(self._xi, pts)
+
+    def nu(self, pts: np.ndarray) -> np.ndarray:
+        return self.nu_lo + (self.nu_hi - self.nu_lo) * self.xi(pts)
+
+    def force(self, pts: np.ndarray, ncomp: int = 3) -> np.ndarray:
+        xi = self.xi(pts)
+        if ncomp == 1:
+            return xi
+        f = np.zeros((pts.shape[0], ncomp))
+        f[:, -1] = -xi
+        return f
+
+
 class GaussianLogField:
     """log nu = affine rescale of a sum of Gaussians, with contrast exp(2*half_range).
 

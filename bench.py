@@ -303,9 +303,11 @@ def report_large(args, dev) -> dict:
     out = {"report": w.name, "description": w.description, "levels": L + 1,
            "free_dofs": nc * (2 ** (L + 1) - 1) ** 3, "input_generation_s": round(t_gen, 2)}
     t0 = time.perf_counter()
-    H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64", smoother=args.smoother)
+    H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64", smoother=args.smoother,
+                    coarse_storage=args.coarse_storage)
     out["setup_fp64_s"] = round(time.perf_counter() - t0, 3)
     out["smoother"] = args.smoother
+    out["coarse_storage"] = args.coarse_storage
     progress(f"[large] inputs {t_gen:.1f} s, FP64 hierarchy {out['setup_fp64_s']:.1f} s")
     b = H64.load_vector(f)
     del f
@@ -327,7 +329,8 @@ def report_large(args, dev) -> dict:
     out["stored_block_bytes_fp64"] = int(sum(i["block_bytes"] for i in info))
     dev64 = H64.device_bytes()
     t0 = time.perf_counter()
-    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype="bf16", smoother=args.smoother)
+    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype="bf16", smoother=args.smoother,
+                    coarse_storage=args.coarse_storage)
     out["setup_mixed_s"] = round(time.perf_counter() - t0, 3)
     x32, s32 = H32.solve(b, solver="fcg", tol=w.tol, max_iter=4000, raise_on_noconv=False,
                          record_history=False)
@@ -517,6 +520,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mg-nu", default="bf16", choices=["bf16", "f32"])
     ap.add_argument("--smoother", default="chebyshev", choices=["jacobi", "chebyshev"])
+    ap.add_argument("--coarse-storage", default="blocks", choices=["blocks", "mean"],
+                    help="flagged elements keep their Galerkin block, or the descendant mean "
+                         "of the coefficient (the same operator for P1)")
     ap.add_argument("--profile-apply", action="store_true",
                     help="only run 5 FP64 fine applies and a 256 MiB copy (counter passes)")
     ap.add_argument("--summarize-profile", metavar="DIR",

@@ -69,6 +69,15 @@ typedef enum { AGCA_F64 = 0, AGCA_F32 = 1, AGCA_BF16 = 2 } agca_dtype;
  *  ALL   : Galerkin blocks on every coarse element (eqs. (2.6)-(2.7)). */
 enum { AGCA_FLAG_RATIO = 0, AGCA_FLAG_MACRO = 1, AGCA_FLAG_NONE = 2, AGCA_FLAG_ALL = 3 };
 
+/* How a flagged element's Galerkin operator is kept.
+ *  BLOCKS : its 4 ncomp x 4 ncomp Galerkin block (eq. (2.7)), computed in FP64 from
+ *           the finest coefficient (plus an FP32 copy for the FP32 V-cycle).
+ *  MEAN   : one scalar: with P1 functions the block equals the element's DCA matrix
+ *           with the arithmetic mean of the finest coefficient over its descendants,
+ *           so that mean replaces the element's coarse coefficient and nothing else is
+ *           stored (the same operator up to rounding; agca_get_blocks then fails). */
+enum { AGCA_STORE_BLOCKS = 0, AGCA_STORE_MEAN = 1 };
+
 /* Smoother of the V-cycle.
  *  JACOBI    : damped Jacobi, pre_sweeps / post_sweeps sweeps with damping omega.
  *  CHEBYSHEV : the Chebyshev polynomial smoother of Section 4, degree pre_sweeps /
@@ -94,6 +103,7 @@ typedef struct {
     double omega;            /* Jacobi damping (2/3)                                        */
     uint64_t mem_limit_bytes;/* 0 = unlimited; larger totals fail with AGCA_E_OOM           */
     uint8_t macro_flags[48]; /* AGCA_FLAG_MACRO: nonzero = Galerkin-coarsen that macro element */
+    int32_t coarse_storage;  /* AGCA_STORE_*                                                */
 } agca_config;
 
 typedef struct {

@@ -12,6 +12,7 @@ AGCA_OK, AGCA_E_INVALID, AGCA_E_OOM, AGCA_E_HIP, AGCA_E_NOCONV, AGCA_E_NUMERIC, 
     0, -1, -2, -3, -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
 SMOOTH_JACOBI, SMOOTH_CHEBYSHEV = 0, 1
+STORE_BLOCKS, STORE_MEAN = 0, 1
 FLAG_RATIO, FLAG_MACRO, FLAG_NONE, FLAG_ALL = 0, 1, 2, 3
 SOLVER_PCG, SOLVER_FCG, SOLVER_IR, SOLVER_STATIONARY = 0, 1, 2, 3
 MAX_HISTORY = 1024
@@ -25,7 +26,7 @@ class Config(C.Structure):
                 ("mg_dtype", C.c_int32), ("mg_nu_dtype", C.c_int32), ("pre_sweeps", C.c_int32),
                 ("post_sweeps", C.c_int32), ("smoother", C.c_int32), ("flag_ratio", C.c_double),
                 ("omega", C.c_double), ("mem_limit_bytes", C.c_uint64),
-                ("macro_flags", C.c_uint8 * 48)]
+                ("macro_flags", C.c_uint8 * 48), ("coarse_storage", C.c_int32)]
 
 
 class LevelInfo(C.Structure):

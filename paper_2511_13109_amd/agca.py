@@ -74,7 +74,8 @@ class Hierarchy:
                  flag_mode: str = "ratio", tau: float = 10.0, mg_dtype: str = "f64",
                  mg_nu_dtype: Optional[str] = None, pre: int = 2, post: int = 2,
                  omega: float = 2.0 / 3.0, mem_limit_bytes: int = 0, stream=None,
-                 smoother: str = "jacobi", macro_flags: Optional[Sequence[bool]] = None):
+                 smoother: str = "jacobi", macro_flags: Optional[Sequence[bool]] = None,
+                 coarse_storage: str = "blocks"):
         self._lib = _lib.load()
         cfg = default_config()
         cfg.L, cfg.ncomp = L, ncomp
@@ -85,6 +86,7 @@ class Hierarchy:
         cfg.pre_sweeps, cfg.post_sweeps, cfg.omega = pre, post, omega
         cfg.smoother = {"jacobi": _lib.SMOOTH_JACOBI, "chebyshev": _lib.SMOOTH_CHEBYSHEV}[smoother]
         cfg.mem_limit_bytes = mem_limit_bytes
+        cfg.coarse_storage = {"blocks": _lib.STORE_BLOCKS, "mean": _lib.STORE_MEAN}[coarse_storage]
         if flag_mode == "macro":
             if macro_flags is None or len(macro_flags) != 48:
                 raise ValueError("flag_mode 'macro' needs 48 macro flags")

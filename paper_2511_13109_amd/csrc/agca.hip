@@ -36,7 +36,9 @@ struct Level {
     int32_t* blk = nullptr;      // by element id: stored block index or -1
     int32_t* blk_soa = nullptr;  // the same in the internal layout (element loop)
     int32_t* ids = nullptr;
-    int64_t nflag = 0;
+    int64_t nflag = 0;           // flagged elements
+    int64_t nblk = 0;            // stored Galerkin blocks: nflag, or 0 when the flagged
+                                 // elements' DCA coefficient carries the descendant mean
     double* blocks64 = nullptr;
     float* blocks32 = nullptr;
     double* yblk64 = nullptr;    // per-flagged-element block products (scratch)
@@ -163,9 +165,9 @@ LevelOp<double> level_op<double>(const agca_hier* h, int l) {
     op.n = L.n;
     op.nu = L.nu64;
     op.nu_kind = AGCA_F64;
-    op.blk = (l < h->cfg.L && L.nflag > 0) ? L.blk_soa : nullptr;
+    op.blk = (l < h->cfg.L && L.nblk > 0) ? L.blk_soa : nullptr;
     op.ids = L.ids;
-    op.nflag = L.nflag;
+    op.nflag = L.nblk;
     op.blocks = L.blocks64;
     op.yblk = L.yblk64;
     op.dinv = L.dinv64;
@@ -184,9 +186,9 @@ LevelOp<float> level_op<float>(const agca_hier* h, int l) {
         op.nu = L.nu32;
         op.nu_kind = AGCA_F32;
     }
-    op.blk = (l < h->cfg.L && L.nflag > 0) ? L.blk_soa : nullptr;
+    op.blk = (l < h->cfg.L && L.nblk > 0) ? L.blk_soa : nullptr;
     op.ids = L.ids;
-    op.nflag = L.nflag;
+    op.nflag = L.nblk;
     op.blocks = L.blocks32;
     op.yblk = L.yblk32;
     op.dinv = L.dinv32;
@@ -420,6 +422,8 @@ int32_t validate(const agca_config* c) {
         return fail(AGCA_E_INVALID, "an FP64 V-cycle needs an FP64 coefficient");
     if (c->mg_dtype == AGCA_F32 && c->mg_nu_dtype == AGCA_F64)
         return fail(AGCA_E_INVALID, "an FP32 V-cycle uses an FP32 or BF16 coefficient");
+    if (c->coarse_storage != AGCA_STORE_BLOCKS && c->coarse_storage != AGCA_STORE_MEAN)
+        return fail(AGCA_E_INVALID, "unknown coarse_storage");
     if (c->smoother != AGCA_SMOOTH_JACOBI && c->smoother != AGCA_SMOOTH_CHEBYSHEV)
         return fail(AGCA_E_INVALID, "unknown smoother");
     if (c->pre_sweeps < 0 || c->post_sweeps < 0 || c->pre_sweeps > 64 || c->post_sweeps > 64)
@@ -553,10 +557,10 @@ int32_t build_coarsest(agca_hier* h) {
     HIPCHK(h, hipMemcpyAsync(nu.data(), L0.nu64, 48 * sizeof(double), hipMemcpyDeviceToHost, h->st));
     std::vector<int32_t> blk(48, -1);
     std::vector<double> blocks;
-    const bool has_blocks = h->cfg.L > 0 && L0.nflag > 0;
+    const bool has_blocks = h->cfg.L > 0 && L0.nblk > 0;
     if (has_blocks) {
         HIPCHK(h, hipMemcpyAsync(blk.data(), L0.blk, 48 * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
-        blocks.resize((size_t)L0.nflag * M * M);
+        blocks.resize((size_t)L0.nblk * M * M);
         HIPCHK(h, hipMemcpyAsync(blocks.data(), L0.blocks64, blocks.size() * sizeof(double),
                                  hipMemcpyDeviceToHost, h->st));
     }
@@ -627,7 +631,8 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
     }
     // flags: min/max pyramid from level L-1 down to 0
     {
-        double *mn[2] = {nullptr, nullptr}, *mx[2] = {nullptr, nullptr};
+        double *mn[2] = {nullptr, nullptr}, *mx[2] = {nullptr, nullptr}, *mean[2] = {nullptr, nullptr};
+        const bool store_mean = h->cfg.coarse_storage == AGCA_STORE_MEAN;
         const int64_t emax = h->lv[L - 1].elems;
         void* scratch = nullptr;
         size_t sbytes = 0;
@@ -655,6 +660,7 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
         for (int i = 0; i < 2 && rc == AGCA_OK; ++i) {
             rc = talloc((void**)&mn[i], emax * sizeof(double));
             if (rc == AGCA_OK) rc = talloc((void**)&mx[i], emax * sizeof(double));
+            if (rc == AGCA_OK && store_mean) rc = talloc((void**)&mean[i], emax * sizeof(double));
         }
         if (rc == AGCA_OK) rc = talloc(&scratch, sbytes);
         int64_t* cnt_dev = nullptr;
@@ -673,6 +679,14 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
                         ? launch_flag_macro(h->lv[l].elems, h->lv[l].n, l, macro_bits, h->lv[l].flag, h->st)
                         : launch_flag(h->lv[l].elems, mn[cur], mx[cur], h->cfg.flag_ratio, h->cfg.flag_mode,
                                       h->lv[l].flag, h->st);
+            if (e == hipSuccess && store_mean) {
+                // the flagged elements' Galerkin blocks equal their DCA element matrices with
+                // the mean finest coefficient: keep that mean as their coefficient instead
+                e = (l == L - 1) ? launch_mean_from_fine(h->lv[l].n, h->lv[L].nu64, mean[cur], h->st)
+                                 : launch_mean_up(h->lv[l].n, mean[fin], mean[cur], h->st);
+                if (e == hipSuccess)
+                    e = launch_override_mean(h->lv[l].elems, h->lv[l].flag, mean[cur], h->lv[l].nu64, h->st);
+            }
             if (e == hipSuccess)
                 e = launch_compact(h->lv[l].elems, h->lv[l].flag, h->lv[l].blk, h->lv[l].blk_soa,
                                    h->lv[l].ids, cnt_dev + l, scratch, sbytes, h->st);
@@ -691,19 +705,22 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
             h->error = true;
             return fail(AGCA_E_HIP, std::string("flag count readback: ") + hipGetErrorString(e));
         }
-        for (int l = 0; l < L; ++l) h->lv[l].nflag = counts[l];
+        for (int l = 0; l < L; ++l) {
+            h->lv[l].nflag = counts[l];
+            h->lv[l].nblk = (h->cfg.coarse_storage == AGCA_STORE_MEAN) ? 0 : counts[l];
+        }
     }
     // block storage
     for (int l = 0; l < L; ++l) {
         Level& lv = h->lv[l];
         lv.blocks64 = nullptr;
         lv.blocks32 = nullptr;
-        if (lv.nflag > 0) {
-            TRY(alloc_t(h, &lv.blocks64, (size_t)lv.nflag * M * M, &lv.bytes));
-            TRY(alloc_t(h, &lv.yblk64, (size_t)lv.nflag * M, &lv.bytes));
+        if (lv.nblk > 0) {
+            TRY(alloc_t(h, &lv.blocks64, (size_t)lv.nblk * M * M, &lv.bytes));
+            TRY(alloc_t(h, &lv.yblk64, (size_t)lv.nblk * M, &lv.bytes));
             if (mg32(h)) {
-                TRY(alloc_t(h, &lv.blocks32, (size_t)lv.nflag * M * M, &lv.bytes));
-                TRY(alloc_t(h, &lv.yblk32, (size_t)lv.nflag * M, &lv.bytes));
+                TRY(alloc_t(h, &lv.blocks32, (size_t)lv.nblk * M * M, &lv.bytes));
+                TRY(alloc_t(h, &lv.yblk32, (size_t)lv.nblk * M, &lv.bytes));
             }
         }
     }
@@ -711,14 +728,14 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
     {
         int lowest = -1;  // coarsest... any flagged level <= L-2 ?
         for (int l = 0; l <= L - 2; ++l)
-            if (h->lv[l].nflag > 0) {
+            if (h->lv[l].nblk > 0) {
                 lowest = l;
                 break;
             }
         const double h_fine = 1.0 / h->lv[L].n;
         if (lowest < 0) {
-            if (L >= 1 && h->lv[L - 1].nflag > 0)
-                HIPCHK(h, launch_gca_from_fine(nc, h->lv[L - 1].n, h->lv[L - 1].nflag, h->lv[L - 1].ids,
+            if (L >= 1 && h->lv[L - 1].nblk > 0)
+                HIPCHK(h, launch_gca_from_fine(nc, h->lv[L - 1].n, h->lv[L - 1].nblk, h->lv[L - 1].ids,
                                                h->lv[L].nu64, h_fine, h->lv[L - 1].blocks64, h->st));
         } else {
             // levels L-2 .. lowest need the Galerkin matrices of every element of the level
@@ -767,7 +784,7 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
     for (int l = 0; l <= L; ++l) {
         Level& lv = h->lv[l];
         const double scale = 1.0 / (6.0 * lv.n);
-        HIPCHK(h, launch_diagonal(nc, lv.n, lv.nu64, scale, (l < L && lv.nflag > 0) ? lv.blk : nullptr,
+        HIPCHK(h, launch_diagonal(nc, lv.n, lv.nu64, scale, (l < L && lv.nblk > 0) ? lv.blk : nullptr,
                                   lv.blocks64, lv.diag, h->st));
         const int64_t cnt = (int64_t)nc * lv.nodes;
         if (mg32(h)) {
@@ -779,12 +796,12 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
                 HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, lv.nu64, lv.nu32, lv.elems, h->st));
             if (lv.blocks32)
                 HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, lv.blocks64, lv.blocks32,
-                                      (int64_t)lv.nflag * M * M, h->st));
+                                      (int64_t)lv.nblk * M * M, h->st));
         } else {
             HIPCHK(h, launch_invert_diag<double>(cnt, lv.diag, lv.dinv64, h->st));
         }
         if (lv.sten64) {
-            HIPCHK(h, launch_stencil_assemble(nc, lv.n, lv.nu64, scale, lv.nflag > 0 ? lv.blk_soa : nullptr,
+            HIPCHK(h, launch_stencil_assemble(nc, lv.n, lv.nu64, scale, lv.nblk > 0 ? lv.blk_soa : nullptr,
                                               lv.blocks64, lv.sten64, h->st));
             if (lv.sten32)
                 HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, lv.sten64, lv.sten32,
@@ -818,10 +835,10 @@ int32_t free_blocks(agca_hier* h) {
                 }
         }
         const int M = 4 * h->cfg.ncomp;
-        const int64_t freed = (lv.blocks64 ? lv.nflag * M * M * (int64_t)sizeof(double) : 0) +
-                              (lv.blocks32 ? lv.nflag * M * M * (int64_t)sizeof(float) : 0) +
-                              (lv.yblk64 ? lv.nflag * M * (int64_t)sizeof(double) : 0) +
-                              (lv.yblk32 ? lv.nflag * M * (int64_t)sizeof(float) : 0);
+        const int64_t freed = (lv.blocks64 ? lv.nblk * M * M * (int64_t)sizeof(double) : 0) +
+                              (lv.blocks32 ? lv.nblk * M * M * (int64_t)sizeof(float) : 0) +
+                              (lv.yblk64 ? lv.nblk * M * (int64_t)sizeof(double) : 0) +
+                              (lv.yblk32 ? lv.nblk * M * (int64_t)sizeof(float) : 0);
         h->bytes -= freed;
         lv.bytes -= freed;
         lv.blocks64 = nullptr;
@@ -829,6 +846,7 @@ int32_t free_blocks(agca_hier* h) {
         lv.yblk64 = nullptr;
         lv.yblk32 = nullptr;
         lv.nflag = 0;
+        lv.nblk = 0;
     }
     return AGCA_OK;
 }
@@ -982,7 +1000,7 @@ int32_t agca_query(const agca_hier* h, int32_t level, agca_level_info* out) {
     out->free_nodes = (int64_t)(lv.n - 1) * (lv.n - 1) * (lv.n - 1);
     out->elements = lv.elems;
     out->flagged = level < h->cfg.L ? lv.nflag : 0;
-    out->block_bytes = (lv.blocks64 ? lv.nflag * M * M * 8 : 0) + (lv.blocks32 ? lv.nflag * M * M * 4 : 0);
+    out->block_bytes = (lv.blocks64 ? lv.nblk * M * M * 8 : 0) + (lv.blocks32 ? lv.nblk * M * M * 4 : 0);
     out->level_bytes = lv.bytes;
     out->lambda_max = (size_t)level < h->lam.size() ? h->lam[level] : 0.0;
     return AGCA_OK;
@@ -1007,10 +1025,12 @@ int32_t agca_get_blocks(const agca_hier* h, int32_t level, double* blocks_host, 
     if (level >= h->cfg.L) return fail(AGCA_E_INVALID, "the finest level has no blocks");
     const Level& lv = h->lv[level];
     const int M = 4 * h->cfg.ncomp;
-    if (cap < lv.nflag * M * M) return fail(AGCA_E_INVALID, "blocks buffer too small");
+    if (h->cfg.coarse_storage == AGCA_STORE_MEAN && lv.nflag > 0)
+        return fail(AGCA_E_INVALID, "no stored blocks: the hierarchy keeps the descendant mean instead");
+    if (cap < lv.nblk * M * M) return fail(AGCA_E_INVALID, "blocks buffer too small");
     agca_hier* hh = const_cast<agca_hier*>(h);
-    if (lv.nflag > 0) {
-        HIPCHK(hh, hipMemcpyAsync(blocks_host, lv.blocks64, lv.nflag * M * M * sizeof(double),
+    if (lv.nblk > 0) {
+        HIPCHK(hh, hipMemcpyAsync(blocks_host, lv.blocks64, lv.nblk * M * M * sizeof(double),
                                   hipMemcpyDeviceToHost, h->st));
         HIPCHK(hh, hipStreamSynchronize(h->st));
     }

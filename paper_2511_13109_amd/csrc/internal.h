@@ -121,6 +121,12 @@ hipError_t launch_minmax_up(int n_coarse, const double* mn_f, const double* mx_f
                             double* mx, hipStream_t st);
 hipError_t launch_flag(int64_t ne, const double* mn, const double* mx, double tau, int mode,
                        int32_t* flag, hipStream_t st);
+// descendant means of the finest coefficient (canonical ids), and their use as the DCA
+// coefficient of the flagged elements (nu in the internal layout)
+hipError_t launch_mean_from_fine(int n_coarse, const double* nu_fine, double* mean, hipStream_t st);
+hipError_t launch_mean_up(int n_coarse, const double* mean_f, double* mean, hipStream_t st);
+hipError_t launch_override_mean(int64_t ne, const int32_t* flag, const double* mean, double* nu,
+                                hipStream_t st);
 // flag = 1 for the level-l elements (n = 2^(l+1) cells per axis) inside the macro
 // elements whose bit is set in `bits` (bit k = level-0 element id k)
 hipError_t launch_flag_macro(int64_t ne, int n, int l, uint64_t bits, int32_t* flag, hipStream_t st);

@@ -66,6 +66,44 @@ k_flag(int64_t ne, const double* __restrict__ mn, const double* __restrict__ mx,
     flag[e] = f;
 }
 
+// Descendant means of the finest coefficient.  For P1 functions the Galerkin
+// product of a coarse element (eq. (2.7)) sums the finest element matrices
+// nu_d K_d of its descendants against the constant gradients of the coarse hat
+// functions; all descendants have the same volume, so the block is the coarse
+// element matrix with the arithmetic mean of nu_d.  The mean of equal-size
+// groups is the mean of the group means, so the pyramid is exact up to rounding.
+__global__ void __launch_bounds__(NT)
+k_mean_from_fine(int n, const double* __restrict__ nu_fine, double* __restrict__ mean) {
+    const int64_t ne = 6LL * n * n * n;
+    const int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (e >= ne) return;
+    const int64_t cells_f = 8LL * n * n * n;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += nu_fine[elem_index(child_id(n, e, k), cells_f)];
+    mean[e] = 0.125 * s;
+}
+
+__global__ void __launch_bounds__(NT)
+k_mean_up(int n, const double* __restrict__ mean_f, double* __restrict__ mean) {
+    const int64_t ne = 6LL * n * n * n;
+    const int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (e >= ne) return;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += mean_f[child_id(n, e, k)];
+    mean[e] = 0.125 * s;
+}
+
+// nu_l(e) <- mean(e) on flagged elements (nu in the internal layout)
+__global__ void __launch_bounds__(NT)
+k_override_mean(int64_t ne, const int32_t* __restrict__ flag, const double* __restrict__ mean,
+                double* __restrict__ nu) {
+    const int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x;
+    if (e >= ne || !flag[e]) return;
+    nu[elem_index(e, ne / 6)] = mean[e];
+}
+
 // Macro-element granularity (eqs. (2.8)-(2.9)).  A level-l element (cell c, order s)
 // lies in the macro cube c >> l; inside that cube the Kuhn simplex with axis order
 // (a1, a2, a3) is the set x_a1 >= x_a2 >= x_a3 of relative coordinates, so the macro
@@ -318,6 +356,24 @@ hipError_t launch_flag(int64_t ne, const double* mn, const double* mx, double ta
                        int32_t* flag, hipStream_t st) {
     if (!mn || !mx || !flag) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_flag, dim3(grid_for(ne)), dim3(NT), 0, st, ne, mn, mx, tau, mode, flag);
+    return hipGetLastError();
+}
+hipError_t launch_mean_from_fine(int n_coarse, const double* nu_fine, double* mean, hipStream_t st) {
+    if (!nu_fine || !mean || n_coarse < 2) return hipErrorInvalidValue;
+    const int64_t ne = 6LL * n_coarse * n_coarse * n_coarse;
+    hipLaunchKernelGGL(k_mean_from_fine, dim3(grid_for(ne)), dim3(NT), 0, st, n_coarse, nu_fine, mean);
+    return hipGetLastError();
+}
+hipError_t launch_mean_up(int n_coarse, const double* mean_f, double* mean, hipStream_t st) {
+    if (!mean_f || !mean || n_coarse < 2) return hipErrorInvalidValue;
+    const int64_t ne = 6LL * n_coarse * n_coarse * n_coarse;
+    hipLaunchKernelGGL(k_mean_up, dim3(grid_for(ne)), dim3(NT), 0, st, n_coarse, mean_f, mean);
+    return hipGetLastError();
+}
+hipError_t launch_override_mean(int64_t ne, const int32_t* flag, const double* mean, double* nu,
+                                hipStream_t st) {
+    if (!flag || !mean || !nu || ne <= 0 || ne % 6) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_override_mean, dim3(grid_for(ne)), dim3(NT), 0, st, ne, flag, mean, nu);
     return hipGetLastError();
 }
 hipError_t launch_flag_macro(int64_t ne, int n, int l, uint64_t bits, int32_t* flag, hipStream_t st) {

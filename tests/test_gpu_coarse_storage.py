@@ -1,0 +1,92 @@
+"""Mean-coefficient storage of the flagged elements (coarse_storage = "mean") through the
+C ABI.  With P1 functions an element's Galerkin block (eq. (2.7)) equals its DCA
+element matrix with the arithmetic mean of the finest coefficient over its
+descendants; the library then keeps that mean instead of the block.  The operators
+must still match the oracle's Galerkin products (which know nothing of the identity)
+to 1e-12 on every level, the V-cycle to 1e-11, and the 129^3 solves must match the
+block-storing hierarchy.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import agca, mg
+
+from gpu_helpers import oracle_apply_full, oracle_case, rand_full, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("ncomp", [1, 3])
+@pytest.mark.parametrize("mode", ["ratio", "all"])
+def test_mean_storage_matches_oracle(mode, ncomp):
+    from paper_2511_13109_amd import Hierarchy
+    L = 3
+    om = {"ratio": agca.FLAG_RATIO, "all": agca.FLAG_ALL}[mode]
+    print(f"\n[mean storage {mode} ncomp={ncomp} L={L}]", flush=True)
+    H, nu, _ = oracle_case("sinkers", L, ncomp, om)
+    G = Hierarchy(L, ncomp, _dev(nu[L]), [_dev(v) for v in nu[:L]], flag_mode=mode,
+                  coarse_storage="mean")
+    try:
+        rng = np.random.default_rng(11)
+        for l in range(1, L + 1):
+            info = G.query(l)
+            if l < L:
+                assert info["flagged"] == int(H.flags[l].sum())
+                assert np.array_equal(G.flags(l), np.nonzero(H.flags[l])[0])
+            assert info["block_bytes"] == 0
+            u = rand_full(H, l, rng)
+            v = G.apply(l, _dev(u)).cpu().numpy()
+            assert rel_err(v, oracle_apply_full(H, l, u)) <= 1e-12, l
+        b = rand_full(H, L, rng)
+        z = G.vcycle(_dev(b)).cpu().numpy()
+        zr = np.zeros_like(b)
+        zr[H.free[L]] = mg.vcycle(H, b[H.free[L]])
+        assert rel_err(z, zr) <= 1e-11
+        with pytest.raises(Exception):
+            G.blocks(1)
+    finally:
+        G.close()
+
+
+@pytest.mark.parametrize("mg_dtype", ["f64", "f32"])
+def test_mean_storage_full_size_matches_blocks(mg_dtype):
+    from paper_2511_13109_amd import Hierarchy
+    from workloads import workload
+    from workloads.lattice import element_centroids
+    L, NC = 6, 3
+    print(f"\n[mean storage 129^3 {mg_dtype}]", flush=True)
+    w = workload("sinker129")
+    field = w.make_field()
+    nu = [_dev(field.nu(element_centroids(l))) for l in range(L + 1)]
+    f = _dev(np.asarray(field.force(element_centroids(L), NC)).T).reshape(-1)
+    nud = "bf16" if mg_dtype == "f32" else "f64"
+    Gb = Hierarchy(L, NC, nu[L], nu[:L], mg_dtype=mg_dtype, mg_nu_dtype=nud)
+    Gm = Hierarchy(L, NC, nu[L], nu[:L], mg_dtype=mg_dtype, mg_nu_dtype=nud, coarse_storage="mean")
+    try:
+        rng = np.random.default_rng(3)
+        for l in (2, 4, 5):
+            n = 2 ** (l + 1)
+            u = _dev(rng.standard_normal(NC * (n + 1) ** 3))
+            a, c = Gb.apply(l, u).cpu().numpy(), Gm.apply(l, u).cpu().numpy()
+            assert rel_err(c, a) <= 1e-12, l
+            assert Gm.query(l)["flagged"] == Gb.query(l)["flagged"]
+        assert sum(Gm.query(l)["block_bytes"] for l in range(L)) == 0
+        assert Gm.device_bytes() < Gb.device_bytes()
+        b = Gb.load_vector(f)
+        solver = "fcg" if mg_dtype == "f32" else "pcg"
+        _, sb = Gb.solve(b, solver=solver, tol=1e-8, max_iter=2000, raise_on_noconv=False)
+        _, sm = Gm.solve(b, solver=solver, tol=1e-8, max_iter=2000, raise_on_noconv=False)
+        print(f"[{mg_dtype}] blocks {sb['iterations']} it {sb['seconds']*1e3:.1f} ms, "
+              f"mean {sm['iterations']} it {sm['seconds']*1e3:.1f} ms, "
+              f"bytes {Gb.device_bytes()} -> {Gm.device_bytes()}", flush=True)
+        assert sm["converged"] or sm["floor_limited"]
+        assert abs(sm["iterations"] - sb["iterations"]) <= max(3, sb["iterations"] // 20)
+    finally:
+        Gb.close()
+        Gm.close()

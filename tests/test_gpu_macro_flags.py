@@ -80,12 +80,14 @@ def test_macro_flag_hierarchy_matches_oracle(ncomp):
         G.close()
 
 
-def test_macro_flags_element_loop_level_sampled():
-    # 129^3: level 5 (65^3 nodes) runs the element loop with stored blocks on the
-    # flagged macros' elements (k_block_products + k_cube with blocks)
+@pytest.mark.parametrize("storage", ["blocks", "mean"])
+def test_macro_flags_element_loop_level_sampled(storage):
+    # 129^3: level 5 (65^3 nodes) runs the element loop on the flagged macros' elements,
+    # with stored blocks (k_block_products + k_cube with blocks) or with the descendant
+    # mean as their coefficient
     from paper_2511_13109_amd import Hierarchy, macro_gradient
     L, NC = 6, 3
-    print(f"\n[macro flags 129^3, element-loop coarse level]", flush=True)
+    print(f"\n[macro flags 129^3, element-loop coarse level, {storage}]", flush=True)
     w = workload("sinker129")
     field = w.make_field()
     nu = [field.nu(element_centroids(l)) for l in range(L + 1)]
@@ -93,7 +95,7 @@ def test_macro_flags_element_loop_level_sampled():
     mf = np.zeros(48, dtype=bool)
     mf[np.argsort(-g)[:12]] = True                 # the 12 macros with the steepest gradient
     G = Hierarchy(L, NC, torch.from_numpy(nu[L]).cuda(), [torch.from_numpy(v).cuda() for v in nu[:L]],
-                  flag_mode="macro", macro_flags=mf)
+                  flag_mode="macro", macro_flags=mf, coarse_storage=storage)
     try:
         level = 5
         assert G.query(level)["flagged"] == 12 * 8 ** level

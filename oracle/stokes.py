@@ -16,7 +16,12 @@ condition).  Readings taken here:
   m_L(v) = sum over d containing v of |d| / (4 nu_d).
 * The pressure is fixed up to a constant (B^T 1 = 0 on free velocities); solutions
   are reported with zero mean pressure (plain average over the pressure nodes).
-* Preconditioner: block diagonal, diag(V-cycle of A, diag(m)^-1).
+* Preconditioners: block diagonal, diag(V-cycle of A, diag(m)^-1), and the upper
+  block-triangular one of eq. (4.1).  With S~ an approximation of the positive
+  B A^-1 B^T, the inverse of [[A, B^T], [0, -S~]] is
+  [[A~^-1, A~^-1 B^T S~^-1], [0, -S~^-1]]: (4.1) as printed has +S~^-1 in the
+  pressure block, which with exact blocks would not make K Q^-1 = [[I, 0], [B A^-1, I]]
+  (two GMRES steps); the sign is read so that it does.  Here S~ = diag(m).
 """
 
 from __future__ import annotations
@@ -84,14 +89,23 @@ class StokesSystem:
     def split(self, x):
         return x[:self.nu_], x[self.nu_:]
 
-    def precond(self) -> Callable:
-        """diag(V-cycle on the velocity block, lumped 1/nu mass inverse)."""
+    def precond(self, kind: str = "diagonal", a_inv: Callable = None,
+                s_inv: Callable = None) -> Callable:
+        """diag(V-cycle, lumped 1/nu mass inverse), or the upper block-triangular
+        [[A~^-1, A~^-1 B^T S~^-1], [0, -S~^-1]]; a_inv / s_inv replace the V-cycle and
+        the mass inverse (the exact inverses make K Q^-1 unipotent)."""
         H = self.H
+        a_inv = a_inv or (lambda ru: mg.vcycle(H, ru))
+        s_inv = s_inv or (lambda rp: rp / self.m)
 
         def M(r):
             ru, rp = self.split(r)
-            zu = mg.vcycle(H, ru)
-            return np.concatenate([zu, rp / self.m])
+            if kind == "diagonal":
+                return np.concatenate([a_inv(ru), s_inv(rp)])
+            if kind != "triangular":
+                raise ValueError(kind)
+            q = s_inv(rp)
+            return np.concatenate([a_inv(ru + self.B.T @ q), -q])
         return M
 
     def direct(self, b: np.ndarray) -> np.ndarray:
@@ -112,8 +126,8 @@ class StokesSystem:
         return x
 
     def solve(self, b: np.ndarray, solver: str, tol: float, restart: int = 30,
-              maxit: int = 500) -> mg.SolveResult:
-        M = self.precond()
+              maxit: int = 500, precond: str = "diagonal") -> mg.SolveResult:
+        M = self.precond(precond)
         if solver == "fgmres":
             res = mg.fgmres(self.K, b, M, tol, restart=restart, maxit=maxit)
         elif solver == "minres":

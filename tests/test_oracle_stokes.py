@@ -98,3 +98,41 @@ def test_krylov_solutions_equal_direct(solver):
     res = S.solve(b, solver, tol=1e-10, restart=30, maxit=2000)
     assert res.converged, (solver, res.iterations)
     assert np.linalg.norm(res.x - x_ref) <= 1e-6 * np.linalg.norm(x_ref)
+
+
+def test_triangular_preconditioner_with_exact_blocks_takes_two_steps():
+    # With A~ = A and S~ = B A^-1 B^T (pseudo-inverse: constants are its kernel) the
+    # upper block-triangular preconditioner makes K Q^-1 = [[I, 0], [B A^-1, I]], whose
+    # minimal polynomial is (z - 1)^2: GMRES ends after two steps.  The other sign of
+    # the pressure block does not (three distinct eigenvalues).
+    from workloads import Sinkers
+    L = 2
+    levels = mesh.hierarchy(L)
+    field = Sinkers(2, 3, radius=0.2, width=2.0 / 2 ** (L + 1), contrast=1e2)
+    nu = [field.nu(mesh.centroids_canonical(lv)) for lv in levels]
+    H = mg.build(L, nu, 3, levels=levels)
+    S = stokes.StokesSystem(H)
+    A_inv = np.linalg.inv(S.A.toarray())
+    B = S.B.toarray()
+    S_pinv = np.linalg.pinv(B @ A_inv @ B.T)
+    f = np.asarray(field.force(mesh.centroids_canonical(levels[L]), 3))
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal(S.np_)
+    g -= g.mean()
+    for gp in (np.zeros(S.np_), g):
+        b = np.concatenate([fem.load_vector(levels[L], f, 3)[H.free[L]], gp])
+        M = S.precond("triangular", a_inv=lambda r: A_inv @ r, s_inv=lambda r: S_pinv @ r)
+        res = mg.fgmres(S.K, b, M, 1e-10, restart=30, maxit=50)
+        assert res.converged and res.iterations <= 2, res.iterations
+
+    def wrong_sign(r):
+        ru, rp = S.split(r)
+        q = S_pinv @ rp
+        return np.concatenate([A_inv @ (ru + B.T @ q), q])
+    res = mg.fgmres(S.K, b, wrong_sign, 1e-10, restart=30, maxit=50)
+    assert res.iterations > 2
+    # with the V-cycle and the lumped mass the triangular form still beats the diagonal one
+    b0 = np.concatenate([fem.load_vector(levels[L], f, 3)[H.free[L]], np.zeros(S.np_)])
+    it_d = S.solve(b0, "fgmres", tol=1e-8, restart=30, maxit=2000, precond="diagonal").iterations
+    it_t = S.solve(b0, "fgmres", tol=1e-8, restart=30, maxit=2000, precond="triangular").iterations
+    assert it_t < it_d, (it_t, it_d)

@@ -258,23 +258,29 @@ int32_t agca_stokes_grad(agca_hier* h, const double* p, double* v);
 int32_t agca_stokes_mass(agca_hier* h, double* m);
 
 typedef enum { AGCA_STOKES_FGMRES = 0, AGCA_STOKES_MINRES = 1 } agca_stokes_solver;
+/* DIAGONAL   : diag(V-cycle, diag(m)^-1).
+ * TRIANGULAR : the upper block-triangular preconditioner of eq. (4.1) with the same
+ *              blocks, [[V, V B^T S^-1], [0, -S^-1]], S = diag(m) approximating the
+ *              positive B A^-1 B^T (the sign of the pressure block for which exact
+ *              blocks make the preconditioned matrix unipotent); FGMRES only. */
+typedef enum { AGCA_STOKES_DIAGONAL = 0, AGCA_STOKES_TRIANGULAR = 1 } agca_stokes_precond;
 typedef struct {
     int32_t solver;          /* agca_stokes_solver                                          */
     int32_t restart;         /* FGMRES restart length, 1..126                              */
     int32_t max_iter;
     int32_t record_history;
     double tol;              /* stop when ||r||_2 <= tol ||(f, g)||_2 (eq. (4.3))           */
+    int32_t precond;         /* agca_stokes_precond                                         */
 } agca_stokes_opts;
 
-/* Solve [[A, B^T], [B, 0]] (u, p) = (f, g) in FP64 with the block-diagonal
- * preconditioner diag(one AGCA V-cycle of A, diag(m)^-1): FGMRES(restart), right
+/* Solve [[A, B^T], [B, 0]] (u, p) = (f, g) in FP64 with a block preconditioner built
+ * from one AGCA V-cycle of A and diag(m) (opts->precond): FGMRES(restart), right
  * preconditioned with modified Gram-Schmidt (any mg_dtype: the FP32 V-cycle makes the
- * preconditioner non-linear), or MINRES (its theory needs a fixed SPD preconditioner,
- * which the FP32 V-cycle is only up to FP32 rounding; the true residual is checked every
- * step, so a run that stagnates reports AGCA_E_NOCONV, never a false convergence).  The
- * returned p has
- * zero mean over the pressure nodes.  Work space: 2 restart + 5 (FGMRES) or 10
- * (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy.
+ * preconditioner non-linear), or MINRES with the block-diagonal one (its theory needs a
+ * fixed SPD preconditioner, which the FP32 V-cycle is only up to FP32 rounding; the true
+ * residual is checked every step, so a run that stagnates reports AGCA_E_NOCONV, never a
+ * false convergence).  The returned p has zero mean over the pressure nodes.  Work
+ * space: 2 restart + 5 (FGMRES; one more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy.
  * Returns AGCA_OK when converged, AGCA_E_NOCONV (u, p, stats filled) otherwise;
  * stats->history holds the FGMRES residual estimates (true residual at restarts)
  * or the MINRES true residuals. */

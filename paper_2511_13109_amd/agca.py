@@ -300,9 +300,10 @@ class Stokes:
 
     def solve(self, f: torch.Tensor, g: Optional[torch.Tensor] = None, solver: str = "fgmres",
               restart: int = 30, tol: float = 1e-8, max_iter: int = 1000, record_history: bool = True,
-              raise_on_noconv: bool = True):
+              raise_on_noconv: bool = True, precond: str = "diagonal"):
         opts = _lib.StokesOpts()
         opts.solver = {"fgmres": _lib.STOKES_FGMRES, "minres": _lib.STOKES_MINRES}[solver]
+        opts.precond = {"diagonal": _lib.STOKES_DIAGONAL, "triangular": _lib.STOKES_TRIANGULAR}[precond]
         opts.restart, opts.max_iter, opts.tol = restart, max_iter, tol
         opts.record_history = 1 if record_history else 0
         g = self.pvec() if g is None else g

@@ -84,6 +84,7 @@ struct agca_hier {
     double* st_pf = nullptr;     // fine-level scalar scratch (interpolated pressure)
     double* st_qf = nullptr;     // fine-level scalar scratch (fine divergence)
     double* st_work = nullptr;   // Krylov vectors, st_work_vecs of them
+    double* st_tri = nullptr;    // during a triangular-preconditioned solve: one Stokes vector
     int64_t st_work_vecs = 0;
     std::vector<void*> allocs;
     int64_t bytes = 0;
@@ -1410,11 +1411,23 @@ static int32_t stokes_apply(agca_hier* h, const double* x, double* y) {
     TRY(stokes_div(h, x, y + d.nu));
     return AGCA_OK;
 }
-// z = diag(V-cycle, mass^-1) r
+// z = diag(V-cycle, mass^-1) r, or with the upper block-triangular preconditioner of
+// eq. (4.1), z = [[V, V B^T S^-1], [0, -S^-1]] r with S = diag(mass) approximating the
+// positive B A^-1 B^T: q = r_p / m, z_u = V(r_u + B^T q), z_p = -q.
 static int32_t stokes_precond(agca_hier* h, const double* r, double* z) {
     const StokesDims d = stokes_dims(h);
-    TRY(precondition(h, r, z));
-    HIPCHK(h, launch_div_elementwise(d.np, r + d.nu, h->st_mass, z + d.nu, h->st));
+    if (!h->st_tri) {
+        TRY(precondition(h, r, z));
+        HIPCHK(h, launch_div_elementwise(d.np, r + d.nu, h->st_mass, z + d.nu, h->st));
+        return AGCA_OK;
+    }
+    double* tu = h->st_tri;
+    double* q = tu + d.nu;
+    HIPCHK(h, launch_div_elementwise(d.np, r + d.nu, h->st_mass, q, h->st));
+    HIPCHK(h, launch_axpby<double>(d.nu, 1.0, r, 0.0, tu, h->st));
+    TRY(stokes_grad_add(h, q, tu));
+    TRY(precondition(h, tu, z));
+    HIPCHK(h, launch_axpby<double>(d.np, -1.0, q, 0.0, z + d.nu, h->st));
     return AGCA_OK;
 }
 static int32_t stokes_norm(agca_hier* h, const double* x, double* out) {
@@ -1615,14 +1628,20 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
         return fail(AGCA_E_INVALID, "unknown Stokes solver");
     if (o->solver == AGCA_STOKES_FGMRES && (o->restart < 1 || o->restart > AGCA_RED_SLOTS - 2))
         return fail(AGCA_E_INVALID, "restart must be in [1, 126]");
+    if (o->precond != AGCA_STOKES_DIAGONAL && o->precond != AGCA_STOKES_TRIANGULAR)
+        return fail(AGCA_E_INVALID, "unknown Stokes preconditioner");
+    if (o->precond == AGCA_STOKES_TRIANGULAR && o->solver != AGCA_STOKES_FGMRES)
+        return fail(AGCA_E_INVALID, "the triangular preconditioner is not symmetric: FGMRES only");
     TRY(ensure_solver_vectors(h));
     std::memset(stats, 0, sizeof(*stats));
     const StokesDims d = stokes_dims(h);
     // contiguous right-hand side and solution in the last two work vectors' place
     const int64_t kry = (o->solver == AGCA_STOKES_FGMRES) ? 2 * (int64_t)o->restart + 3 : 8;
-    TRY(stokes_work(h, kry + 2));
+    const bool tri = o->precond == AGCA_STOKES_TRIANGULAR;
+    TRY(stokes_work(h, kry + 2 + (tri ? 1 : 0)));
     double* bvec = h->st_work + kry * d.tot;
     double* xvec = bvec + d.tot;
+    h->st_tri = tri ? xvec + d.tot : nullptr;
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(h, hipMemcpyAsync(bvec, f, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, h->st));
     HIPCHK(h, launch_zero_boundary<double>(3, d.nf, bvec, h->st));
@@ -1636,11 +1655,14 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     if (bn == 0.0) {
         HIPCHK(h, launch_fill<double>(d.tot, 0.0, xvec, h->st));
         hist.push_back(0.0);
-    } else if (o->solver == AGCA_STOKES_FGMRES) {
-        TRY(stokes_fgmres(h, o, bvec, xvec, bn, &rel, &it, hist));
     } else {
-        TRY(stokes_minres(h, o, bvec, xvec, bn, &rel, &it, hist));
+        const int32_t rc = (o->solver == AGCA_STOKES_FGMRES)
+                               ? stokes_fgmres(h, o, bvec, xvec, bn, &rel, &it, hist)
+                               : stokes_minres(h, o, bvec, xvec, bn, &rel, &it, hist);
+        h->st_tri = nullptr;
+        if (rc != AGCA_OK) return rc;
     }
+    h->st_tri = nullptr;
     // pressure with zero mean (the constant is the kernel of B^T on free velocities)
     double psum = 0.0;
     {

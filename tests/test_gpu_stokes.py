@@ -104,3 +104,27 @@ def test_solve_mixed_precision(case, solver):
     xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
     # residual recomputed by the oracle (FP64, assembled K)
     assert np.linalg.norm(b - S.K @ xg) <= 1.0001e-8 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("mg_dtype", ["f64", "f32"])
+def test_triangular_preconditioner(case, mg_dtype):
+    L, levels, H, S, fu, GS, GS32 = case
+    G = GS if mg_dtype == "f64" else GS32
+    b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
+    tol = 1e-9 if mg_dtype == "f64" else 1e-8
+    u, p, st = G.solve(_dev(fu), solver="fgmres", restart=30, tol=tol, max_iter=3000,
+                       precond="triangular")
+    print(f"[fgmres triangular {mg_dtype} L={L}] {st['iterations']} it", flush=True)
+    assert st["converged"] and st["rel_residual"] <= tol
+    xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
+    assert np.linalg.norm(b - S.K @ xg) <= 1.0001 * tol * np.linalg.norm(b)
+    if mg_dtype == "f64":
+        ref = S.solve(b, "fgmres", tol=tol, restart=30, maxit=3000, precond="triangular")
+        assert ref.converged
+        k = min(len(st["history"]), len(ref.history), 20)
+        assert np.allclose(st["history"][:k], ref.history[:k], rtol=1e-6, atol=1e-14)
+        assert abs(st["iterations"] - ref.iterations) <= max(1, int(0.05 * ref.iterations))
+        _, _, sd = G.solve(_dev(fu), solver="fgmres", restart=30, tol=tol, max_iter=3000)
+        assert st["iterations"] < sd["iterations"]
+    with pytest.raises(Exception):
+        G.solve(_dev(fu), solver="minres", tol=tol, precond="triangular")

@@ -1,0 +1,116 @@
+"""Degenerate and boundary cases of the GPU path through the C ABI: the smallest
+hierarchy (L = 1: 5^3 nodes, one free node on level 0), a zero right-hand side, a
+start at the exact solution, a zero iteration budget, a constant coefficient (no
+flags; DCA equals Galerkin coarsening), and a zero Stokes right-hand side.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import agca, fem, mesh, mg
+
+from gpu_helpers import interior_full, oracle_apply_full, rand_full, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _pair(L, ncomp, nu_fn, smoother="jacobi"):
+    from paper_2511_13109_amd import Hierarchy
+    levels = mesh.hierarchy(L)
+    nu = [nu_fn(mesh.centroids_canonical(lv)) for lv in levels]
+    H = mg.build(L, nu, ncomp, levels=levels, smoother=smoother)
+    G = Hierarchy(L, ncomp, _dev(nu[L]), [_dev(v) for v in nu[:L]], smoother=smoother)
+    return levels, H, G
+
+
+def _sinker_nu(pts):
+    from workloads import Sinkers
+    return Sinkers(2, 7, radius=0.2, width=0.05, contrast=1e4).nu(pts)
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "chebyshev"])
+@pytest.mark.parametrize("ncomp", [1, 3])
+def test_smallest_hierarchy(ncomp, smoother):
+    print(f"\n[L=1 ncomp={ncomp} {smoother}]", flush=True)
+    levels, H, G = _pair(1, ncomp, _sinker_nu, smoother)
+    try:
+        rng = np.random.default_rng(1)
+        for l in (0, 1):
+            u = rand_full(H, l, rng)
+            assert rel_err(G.apply(l, _dev(u)).cpu().numpy(), oracle_apply_full(H, l, u)) <= 1e-12
+        b = rand_full(H, 1, rng)
+        z = G.vcycle(_dev(b)).cpu().numpy()
+        zr = np.zeros_like(b)
+        zr[H.free[1]] = mg.vcycle(H, b[H.free[1]])
+        assert rel_err(z, zr) <= 1e-11
+        x, st = G.solve(_dev(b), solver="pcg", tol=1e-10, max_iter=200)
+        ref = mg.pcg(H.A[1], b[H.free[1]], lambda r: mg.vcycle(H, r), 1e-10, maxit=200)
+        assert st["converged"] and abs(st["iterations"] - ref.iterations) <= 1
+    finally:
+        G.close()
+
+
+def test_zero_rhs_exact_start_and_zero_budget():
+    levels, H, G = _pair(3, 3, _sinker_nu)
+    try:
+        nn = (levels[3].n + 1) ** 3
+        zero = torch.zeros(3 * nn, dtype=torch.float64, device="cuda")
+        x, st = G.solve(zero, solver="pcg", tol=1e-8)
+        assert st["converged"] and st["iterations"] == 0 and float(x.abs().max()) == 0.0
+        # start at (an FP64 rounding of) the exact solution: already converged
+        rng = np.random.default_rng(2)
+        b = rand_full(H, 3, rng)
+        xs = np.zeros_like(b)
+        import scipy.sparse.linalg as spla
+        xs[H.free[3]] = spla.spsolve(H.A[3].tocsc(), b[H.free[3]])
+        x0 = _dev(xs)
+        x, st = G.solve(_dev(b), x=x0, solver="pcg", tol=1e-8)
+        assert st["converged"] and st["iterations"] == 0
+        # no iterations allowed: not converged, reported without raising
+        x, st = G.solve(_dev(b), solver="pcg", tol=1e-8, max_iter=0, raise_on_noconv=False)
+        assert not st["converged"] and st["iterations"] == 0
+        assert abs(st["rel_residual"] - 1.0) <= 1e-12
+    finally:
+        G.close()
+
+
+def test_constant_coefficient_has_no_flags_and_dca_equals_gca():
+    from paper_2511_13109_amd import Hierarchy
+    L = 3
+    levels = mesh.hierarchy(L)
+    nu = [np.full(lv.tets.shape[0], 2.5) for lv in levels]
+    G = Hierarchy(L, 3, _dev(nu[L]), [_dev(v) for v in nu[:L]])
+    Gg = Hierarchy(L, 3, _dev(nu[L]), [_dev(v) for v in nu[:L]], flag_mode="all")
+    try:
+        rng = np.random.default_rng(3)
+        for l in range(L):
+            assert G.query(l)["flagged"] == 0
+            n = levels[l].n
+            u = _dev(rng.standard_normal(3 * (n + 1) ** 3))
+            a, g = G.apply(l, u).cpu().numpy(), Gg.apply(l, u).cpu().numpy()
+            assert rel_err(a, g) <= 1e-12, l
+    finally:
+        G.close()
+        Gg.close()
+
+
+def test_stokes_zero_rhs():
+    from paper_2511_13109_amd import Hierarchy, Stokes
+    L = 2
+    levels = mesh.hierarchy(L)
+    nu = [_dev(_sinker_nu(mesh.centroids_canonical(lv))) for lv in levels]
+    G = Hierarchy(L, 3, nu[L], nu[:L])
+    try:
+        S = Stokes(G)
+        f = torch.zeros(3 * (levels[L].n + 1) ** 3, dtype=torch.float64, device="cuda")
+        for solver, pc in (("fgmres", "diagonal"), ("fgmres", "triangular"), ("minres", "diagonal")):
+            u, p, st = S.solve(f, solver=solver, precond=pc, tol=1e-8)
+            assert st["converged"] and st["iterations"] == 0
+            assert float(u.abs().max()) == 0.0 and float(p.abs().max()) == 0.0
+    finally:
+        G.close()

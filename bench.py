@@ -91,6 +91,70 @@ def _short(name: str) -> str:
     return "".join(out)
 
 
+# algorithmic bytes per finest node of the solver's finest-level kernels (vector problem):
+# vectors of ncomp values, the finest coefficient (6 elements per node), scalars per dof
+def _node_bytes(vb: int, nub: int, nvec: int, nc: int = 3) -> int:
+    return nvec * nc * vb + 6 * nub
+
+
+SOLVER_KERNEL_BYTES = {
+    # k_cube<ncomp, vector type, coefficient type, mode, blocks>: mode 0 apply (u in, v out),
+    # 1 residual (+b), 2 Jacobi-type pass (u, b, D^-1 in, out), 3 apply + dot, 4 first two
+    # passes from zero (b, D^-1 in, out), 5 Chebyshev pass (+ previous iterate)
+    "k_cube<3, double, double, 0, false>": ("apply", _node_bytes(8, 8, 2)),
+    "k_cube<3, double, double, 1, false>": ("residual", _node_bytes(8, 8, 3)),
+    "k_cube<3, double, double, 2, false>": ("Jacobi-type pass", _node_bytes(8, 8, 4)),
+    "k_cube<3, double, double, 3, false>": ("apply + p.Ap", _node_bytes(8, 8, 2)),
+    "k_cube<3, double, double, 4, false>": ("first two passes", _node_bytes(8, 8, 3)),
+    "k_cube<3, double, double, 5, false>": ("Chebyshev pass", _node_bytes(8, 8, 5)),
+    "k_cube<3, float, unsigned short, 1, false>": ("FP32/BF16 residual", _node_bytes(4, 2, 3)),
+    "k_cube<3, float, unsigned short, 2, false>": ("FP32/BF16 Jacobi-type pass", _node_bytes(4, 2, 4)),
+    "k_cube<3, float, unsigned short, 4, false>": ("FP32/BF16 first two passes", _node_bytes(4, 2, 3)),
+    "k_cube<3, float, unsigned short, 5, false>": ("FP32/BF16 Chebyshev pass", _node_bytes(4, 2, 5)),
+    "k_cg_update": ("x += a p, r -= a q, r.r (mixed: + FP32 r)", 3 * (6 * 8)),
+    "k_dot2<double>": ("z.r (PCG)", 3 * 16),
+    "k_dot2<float>": ("z.r, z.q (FCG, FP32 z)", 3 * 20),
+    "k_zpbp<double>": ("p = z + beta p", 3 * 24),
+    "k_zpbp<float>": ("p = z + beta p (FP32 z)", 3 * 20),
+    "k_restrict<double>": ("restriction 129^3 -> 65^3", 3 * 8 + 3 * 8 // 8),
+    "k_restrict<float>": ("restriction 129^3 -> 65^3, FP32", 3 * 4 + 3 * 4 // 8),
+    "k_prolong_add<double>": ("prolongation 65^3 -> 129^3", 3 * 16 + 3 * 8 // 8),
+    "k_prolong_add<float>": ("prolongation 65^3 -> 129^3, FP32", 3 * 8 + 3 * 4 // 8),
+}
+
+
+def summarize_trace(path: str, L: int = 6) -> str:
+    """Markdown table of the finest-level solver kernels in a rocprofv3 kernel trace of one
+    bench step: for every kernel its launches on the finest level (the launch grid with
+    the longest average duration: every level has its own grid), their average
+    duration, the algorithmic bytes per launch and the rate."""
+    import csv
+    import collections
+    n = 2 ** (L + 1)
+    nodes = (n + 1) ** 3
+    groups = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        k = _short(r["Kernel_Name"])
+        if k in SOLVER_KERNEL_BYTES:
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            groups[k].append((grid, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    lines = ["| kernel | what | launches | avg us | MB per launch | GB/s | of 8 TB/s |",
+             "|---|---|---|---|---|---|---|"]
+    for k, (what, per_node) in SOLVER_KERNEL_BYTES.items():
+        if k not in groups:
+            continue
+        by_grid = collections.defaultdict(list)
+        for g, d in groups[k]:
+            by_grid[g].append(d)
+        ds = max(by_grid.values(), key=lambda v: float(np.mean(v)))
+        us = float(np.mean(ds)) / 1e3
+        mb = per_node * nodes / 1e6
+        gbs = mb * 1e6 / (us * 1e-6) / 1e9
+        lines.append(f"| `{k}` | {what} | {len(ds)} | {us:.2f} | {mb:.1f} | {gbs:.0f} | "
+                     f"{gbs / HBM_PEAK_GBS:.3f} |")
+    return "\n".join(lines)
+
+
 def summarize_profile(d: str, command_prefix: str) -> str:
     """Markdown summary of a profiling directory written by the three rocprofv3 runs
     named in the text (kernel statistics, FETCH_SIZE pass, WRITE_SIZE pass)."""
@@ -527,6 +591,8 @@ def main():
                          "of the coefficient (the same operator for P1)")
     ap.add_argument("--profile-apply", action="store_true",
                     help="only run 5 FP64 fine applies and a 256 MiB copy (counter passes)")
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="print the finest-level solver-kernel table of a rocprofv3 kernel trace")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print the markdown summary of a profiling directory and exit")
     ap.add_argument("--level", type=int, default=None, help="finest level of a report workload")
@@ -535,6 +601,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile, ""))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

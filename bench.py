@@ -91,35 +91,36 @@ def _short(name: str) -> str:
     return "".join(out)
 
 
-# algorithmic bytes per finest node of the solver's finest-level kernels (vector problem):
-# vectors of ncomp values, the finest coefficient (6 elements per node), scalars per dof
-def _node_bytes(vb: int, nub: int, nvec: int, nc: int = 3) -> int:
-    return nvec * nc * vb + 6 * nub
+# algorithmic bytes of the solver's finest-level kernels (vector problem): bytes per node
+# of the ncomp-vectors read or written, and bytes per cell of the finest coefficient
+def _vec(vb: int, nvec: int, nc: int = 3) -> int:
+    return nvec * nc * vb
 
 
 SOLVER_KERNEL_BYTES = {
     # k_cube<ncomp, vector type, coefficient type, mode, blocks>: mode 0 apply (u in, v out),
     # 1 residual (+b), 2 Jacobi-type pass (u, b, D^-1 in, out), 3 apply + dot, 4 first two
     # passes from zero (b, D^-1 in, out), 5 Chebyshev pass (+ previous iterate)
-    "k_cube<3, double, double, 0, false>": ("apply", _node_bytes(8, 8, 2)),
-    "k_cube<3, double, double, 1, false>": ("residual", _node_bytes(8, 8, 3)),
-    "k_cube<3, double, double, 2, false>": ("Jacobi-type pass", _node_bytes(8, 8, 4)),
-    "k_cube<3, double, double, 3, false>": ("apply + p.Ap", _node_bytes(8, 8, 2)),
-    "k_cube<3, double, double, 4, false>": ("first two passes", _node_bytes(8, 8, 3)),
-    "k_cube<3, double, double, 5, false>": ("Chebyshev pass", _node_bytes(8, 8, 5)),
-    "k_cube<3, float, unsigned short, 1, false>": ("FP32/BF16 residual", _node_bytes(4, 2, 3)),
-    "k_cube<3, float, unsigned short, 2, false>": ("FP32/BF16 Jacobi-type pass", _node_bytes(4, 2, 4)),
-    "k_cube<3, float, unsigned short, 4, false>": ("FP32/BF16 first two passes", _node_bytes(4, 2, 3)),
-    "k_cube<3, float, unsigned short, 5, false>": ("FP32/BF16 Chebyshev pass", _node_bytes(4, 2, 5)),
-    "k_cg_update": ("x += a p, r -= a q, r.r (mixed: + FP32 r)", 3 * (6 * 8)),
-    "k_dot2<double>": ("z.r (PCG)", 3 * 16),
-    "k_dot2<float>": ("z.r, z.q (FCG, FP32 z)", 3 * 20),
-    "k_zpbp<double>": ("p = z + beta p", 3 * 24),
-    "k_zpbp<float>": ("p = z + beta p (FP32 z)", 3 * 20),
-    "k_restrict<double>": ("restriction 129^3 -> 65^3", 3 * 8 + 3 * 8 // 8),
-    "k_restrict<float>": ("restriction 129^3 -> 65^3, FP32", 3 * 4 + 3 * 4 // 8),
-    "k_prolong_add<double>": ("prolongation 65^3 -> 129^3", 3 * 16 + 3 * 8 // 8),
-    "k_prolong_add<float>": ("prolongation 65^3 -> 129^3, FP32", 3 * 8 + 3 * 4 // 8),
+    "k_cube<3, double, double, 0, false>": ("apply", _vec(8, 2), 48),
+    "k_cube<3, double, double, 1, false>": ("residual", _vec(8, 3), 48),
+    "k_cube<3, double, double, 2, false>": ("Jacobi-type pass", _vec(8, 4), 48),
+    "k_cube<3, double, double, 3, false>": ("apply + p.Ap", _vec(8, 2), 48),
+    "k_cube<3, double, double, 4, false>": ("first two passes", _vec(8, 3), 48),
+    "k_cube<3, double, double, 5, false>": ("Chebyshev pass", _vec(8, 5), 48),
+    "k_cube<3, float, unsigned short, 1, false>": ("FP32/BF16 residual", _vec(4, 3), 12),
+    "k_cube<3, float, unsigned short, 2, false>": ("FP32/BF16 Jacobi-type pass", _vec(4, 4), 12),
+    "k_cube<3, float, unsigned short, 4, false>": ("FP32/BF16 first two passes", _vec(4, 3), 12),
+    "k_cube<3, float, unsigned short, 5, false>": ("FP32/BF16 Chebyshev pass", _vec(4, 5), 12),
+    "k_cg_update": ("x += a p, r -= a q, r.r (mixed: + FP32 r)", 3 * 6 * 8, 0),
+    "k_dot2<double>": ("z.r (PCG)", 3 * 16, 0),
+    "k_dot2<float>": ("z.r, z.q (FCG, FP32 z)", 3 * 20, 0),
+    "k_zpbp<double>": ("p = z + beta p", 3 * 24, 0),
+    "k_zpbp<float>": ("p = z + beta p (FP32 z)", 3 * 20, 0),
+    # per fine node; the coarse vector (1/8 of the nodes) is added below
+    "k_restrict<double>": ("restriction 129^3 -> 65^3", 3 * 8, 0),
+    "k_restrict<float>": ("restriction 129^3 -> 65^3, FP32", 3 * 4, 0),
+    "k_prolong_add<double>": ("prolongation 65^3 -> 129^3", 3 * 16, 0),
+    "k_prolong_add<float>": ("prolongation 65^3 -> 129^3, FP32", 3 * 8, 0),
 }
 
 
@@ -140,7 +141,8 @@ def summarize_trace(path: str, L: int = 6) -> str:
             groups[k].append((grid, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
     lines = ["| kernel | what | launches | avg us | MB per launch | GB/s | of 8 TB/s |",
              "|---|---|---|---|---|---|---|"]
-    for k, (what, per_node) in SOLVER_KERNEL_BYTES.items():
+    nc1 = (n // 2 + 1) ** 3
+    for k, (what, per_node, per_cell) in SOLVER_KERNEL_BYTES.items():
         if k not in groups:
             continue
         by_grid = collections.defaultdict(list)
@@ -148,7 +150,8 @@ def summarize_trace(path: str, L: int = 6) -> str:
             by_grid[g].append(d)
         ds = max(by_grid.values(), key=lambda v: float(np.mean(v)))
         us = float(np.mean(ds)) / 1e3
-        mb = per_node * nodes / 1e6
+        coarse = (per_node // 2 if "prolong" in k else per_node) * nc1 if "restrict" in k or "prolong" in k else 0
+        mb = (per_node * nodes + per_cell * n ** 3 + coarse) / 1e6
         gbs = mb * 1e6 / (us * 1e-6) / 1e9
         lines.append(f"| `{k}` | {what} | {len(ds)} | {us:.2f} | {mb:.1f} | {gbs:.0f} | "
                      f"{gbs / HBM_PEAK_GBS:.3f} |")

@@ -1,5 +1,7 @@
 """Adjoint gradient of J = 1/2 ||u - u_obs||^2 with respect to log nu per finest element.
 
+Part of the CPU oracle: test infrastructure only (tests, smoke check, CPU baseline).
+
 Not part of the paper (an extension of the method): with A(nu) u = f and A
 symmetric, the Lagrangian J + lambda^T (A u - f) gives A lambda = -(u - u_obs).
 Each element matrix is linear in its own coefficient, dA_e/dnu_e = A_e / nu_e,

@@ -1,5 +1,7 @@
 """Flags, DCA / GCA / AGCA coarse operators and local Galerkin blocks (paper Section 2.2-2.3).
 
+Part of the CPU oracle: test infrastructure only (tests, smoke check, CPU baseline).
+
 * DCA (eq. (2.5)): re-discretise on level l with the coefficient evaluated there
   (one value per coarse element, ``nu_levels[l]``).
 * GCA (eqs. (2.6)-(2.7)): A_l = Pi_l^T A_L Pi_l with Pi_l the composite linear

@@ -1,5 +1,7 @@
 """P1 finite elements: element matrices and global sparse assembly (paper eqs. (2.3), (2.5), (3.5)).
 
+Part of the CPU oracle: test infrastructure only (tests, smoke check, CPU baseline).
+
 Element matrices come from the inverse of the 4x4 barycentric matrix
 [[1 1 1 1], [x_0 .. x_3]] (rows 1..3 of the inverse's columns are the constant
 gradients of the barycentric coordinates) and the volume |det| / 6.

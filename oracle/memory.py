@@ -1,5 +1,7 @@
 """Memory model of the paper (Section 5, eqs. (5.1)-(5.8), Table 1), in units of N_L.
 
+Part of the CPU oracle: test infrastructure only (tests, smoke check, CPU baseline).
+
 N_L is a fine-grid vector holding all velocity and pressure DoFs of the Stokes
 problem.  The paper's printed constants are approximations of the limits
 computed here; the tests compare these exact values against them.

@@ -1,5 +1,7 @@
 """Macro grid, uniform Bey refinement and canonical numbering (paper Section 2.1, eq. (2.2), Fig. 2).
 
+Part of the CPU oracle: test infrastructure only (tests, smoke check, CPU baseline).
+
 The macro grid is the unit cube split into 2x2x2 sub-cubes of side 1/2, each cut
 into 6 tetrahedra along its (1,1,1) diagonal (48 macro tetrahedra; the paper's
 Sections 4-6 use a 48-tet macro grid of the unit cube).  Each refinement splits

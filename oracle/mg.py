@@ -1,5 +1,7 @@
 """Multigrid V-cycle and Krylov solvers on assembled free-DoF matrices.
 
+Part of the CPU oracle: test infrastructure only (tests, smoke check, CPU baseline).
+
 V-cycle (paper Section 4: one V-cycle approximates the inverse of the viscous
 block): damped Jacobi smoothing with the diagonal of the level operator,
 omega = 2/3, nu1 pre- and nu2 post-sweeps, restriction = P^T, interpolation = P

@@ -1,5 +1,7 @@
 """Grid transfers (paper Section 2.1, eq. (2.4)).
 
+Part of the CPU oracle: test infrastructure only (tests, smoke check, CPU baseline).
+
 Linear interpolation P_l^{l+1} between the nested P1 spaces: entry (i, j) is the
 value of coarse hat function phi_j at fine vertex i.  It is evaluated by point
 location: every fine vertex lies in (the closure of) the coarse tetrahedron whose

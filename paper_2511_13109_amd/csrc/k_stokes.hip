@@ -196,6 +196,88 @@ k_axpy_dev(int64_t n, const double* __restrict__ coef, double sign, const double
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) y[i] += a * x[i];
 }
 
+// Classical Gram-Schmidt against nv contiguous vectors V_i = V + i * ld (the FGMRES
+// basis): one pass over w and the basis for all the dot products, one for the update.
+// A workgroup owns GS_CHUNK consecutive entries; each thread keeps its GS_PER entries of
+// w in registers while the workgroup walks the basis, so w is read once.  The dots of
+// every workgroup are reduced in a fixed order (wavefront shuffles, then LDS), and the
+// partials of all workgroups by k_gs_sum, so the results are bitwise reproducible.
+constexpr int GS_PER = 8;
+constexpr int GS_CHUNK = NT * GS_PER;
+
+__device__ __forceinline__ double gs_wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// partial[i * gridDim.x + block] = sum over the block's entries of w V_i (i < nv), and
+// partial[nv * gridDim.x + block] = sum of w^2
+__global__ void __launch_bounds__(NT)
+k_gs_dots(int64_t n, const double* __restrict__ w, const double* __restrict__ V, int64_t ld, int nv,
+          double* __restrict__ partial) {
+    __shared__ double red[NT / 64];
+    const int64_t base = (int64_t)blockIdx.x * GS_CHUNK + threadIdx.x;
+    double wv[GS_PER];
+#pragma unroll
+    for (int m = 0; m < GS_PER; ++m) {
+        const int64_t j = base + (int64_t)m * NT;
+        wv[m] = j < n ? w[j] : 0.0;
+    }
+    for (int i = 0; i <= nv; ++i) {
+        double acc = 0.0;
+        if (i < nv) {
+            const double* v = V + (int64_t)i * ld;
+#pragma unroll
+            for (int m = 0; m < GS_PER; ++m) {
+                const int64_t j = base + (int64_t)m * NT;
+                acc += wv[m] * (j < n ? v[j] : 0.0);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < GS_PER; ++m) acc += wv[m] * wv[m];
+        }
+        acc = gs_wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int q = 0; q < NT / 64; ++q) t += red[q];
+            partial[(int64_t)i * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// out[i] = sum over the nb partials of row i (one workgroup per row, fixed order)
+__global__ void __launch_bounds__(NT)
+k_gs_sum(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+    __shared__ double red[NT / 64];
+    const double* row = partial + (int64_t)blockIdx.x * nb;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += NT) acc += row[b];
+    acc = gs_wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < NT / 64; ++q) t += red[q];
+        out[blockIdx.x] = t;
+    }
+}
+
+// w -= sum_i h[i] V_i (h on the device)
+__global__ void __launch_bounds__(NT)
+k_gs_update(int64_t n, double* __restrict__ w, const double* __restrict__ V, int64_t ld, int nv,
+            const double* __restrict__ h) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t j = blockIdx.x * (int64_t)NT + threadIdx.x; j < n; j += stride) {
+        double acc = 0.0;
+        for (int i = 0; i < nv; ++i) acc += h[i] * V[(int64_t)i * ld + j];
+        w[j] -= acc;
+    }
+}
+
 unsigned grid_for(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 unsigned grid_stride(int64_t n) {
     const int64_t g = (n + NT - 1) / NT;
@@ -238,6 +320,24 @@ hipError_t launch_div_elementwise(int64_t n, const double* num, const double* de
                                   hipStream_t st) {
     if (!num || !den || !out) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_div_elementwise, dim3(grid_stride(n)), dim3(NT), 0, st, n, num, den, out);
+    return hipGetLastError();
+}
+int gs_blocks(int64_t n) { return (int)((n + GS_CHUNK - 1) / GS_CHUNK); }
+hipError_t launch_gs_dots(int64_t n, const double* w, const double* V, int64_t ld, int nv,
+                          double* partial, hipStream_t st) {
+    if (!w || !V || !partial || n <= 0 || nv < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gs_dots, dim3((unsigned)gs_blocks(n)), dim3(NT), 0, st, n, w, V, ld, nv, partial);
+    return hipGetLastError();
+}
+hipError_t launch_gs_sum(const double* partial, int nb, int rows, double* out, hipStream_t st) {
+    if (!partial || !out || nb <= 0 || rows <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gs_sum, dim3((unsigned)rows), dim3(NT), 0, st, partial, nb, out);
+    return hipGetLastError();
+}
+hipError_t launch_gs_update(int64_t n, double* w, const double* V, int64_t ld, int nv, const double* h,
+                            hipStream_t st) {
+    if (!w || !V || !h || n <= 0 || nv <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gs_update, dim3(grid_stride(n)), dim3(NT), 0, st, n, w, V, ld, nv, h);
     return hipGetLastError();
 }
 hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,

@@ -438,8 +438,10 @@ def report_stokes(args, dev) -> dict:
     out = {"report": w.name, "description": w.description,
            "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3,
            "fgmres_restart": args.stokes_restart, "smoother": args.smoother}
-    for mg, solver, pc in (("f32", "fgmres", "triangular"), ("f64", "fgmres", "triangular"),
-                           ("f32", "minres", "diagonal"), ("f64", "minres", "diagonal")):
+    runs = [r for r in (("f32", "fgmres", "triangular"), ("f64", "fgmres", "triangular"),
+                        ("f32", "minres", "diagonal"), ("f64", "minres", "diagonal"))
+            if r[1] in args.stokes_solvers.split(",")]
+    for mg, solver, pc in runs:
         H = Hierarchy(L, 3, nus[L], nus[:L], mg_dtype=mg, mg_nu_dtype=("bf16" if mg == "f32" else "f64"),
                       smoother=args.smoother)
         S = Stokes(H)
@@ -599,7 +601,9 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print the markdown summary of a profiling directory and exit")
     ap.add_argument("--level", type=int, default=None, help="finest level of a report workload")
-    ap.add_argument("--stokes-max-iter", type=int, default=3000)
+    ap.add_argument("--stokes-max-iter", type=int, default=8000)
+    ap.add_argument("--stokes-solvers", default="fgmres,minres",
+                    help="comma-separated subset of fgmres (triangular) and minres (diagonal)")
     ap.add_argument("--stokes-restart", type=int, default=126)
     args = ap.parse_args()
     if args.summarize_profile:

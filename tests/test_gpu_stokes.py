@@ -128,3 +128,18 @@ def test_triangular_preconditioner(case, mg_dtype):
         assert st["iterations"] < sd["iterations"]
     with pytest.raises(Exception):
         G.solve(_dev(fu), solver="minres", tol=tol, precond="triangular")
+
+
+def test_fgmres_below_the_rounding_floor_stays_finite(case):
+    # asking for 1e-14 drives the Arnoldi process into near-dependent vectors (the
+    # classical Gram-Schmidt second pass runs there); the solve must stay finite and
+    # keep its residual at the rounding level
+    L, levels, H, S, fu, GS, _ = case
+    if L != 3:
+        pytest.skip("one size is enough")
+    b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
+    u, p, st = GS.solve(_dev(fu), solver="fgmres", restart=30, tol=1e-14, max_iter=700,
+                        precond="triangular", raise_on_noconv=False)
+    assert np.all(np.isfinite(st["history"]))
+    xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
+    assert np.linalg.norm(b - S.K @ xg) <= 1e-10 * np.linalg.norm(b)

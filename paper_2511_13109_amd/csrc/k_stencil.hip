@@ -35,7 +35,8 @@ k_stencil_assemble(int n, const double* __restrict__ nu, double scale, const int
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     const int c = blockIdx.y / NC, d = blockIdx.y % NC;
     if (p >= N) return;
-    const int x = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    int x, y, z;
+    node_coords(p, n, x, y, z);
     const bool interior = x > 0 && y > 0 && z > 0 && x < n && y < n && z < n;
     constexpr int M = 4 * NC;
     const int64_t cells = (int64_t)n * n * n;
@@ -86,7 +87,8 @@ k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     const int c = blockIdx.y;
     if (p >= N) return;
-    const int x = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    int x, y, z;
+    node_coords(p, n, x, y, z);
     const bool interior = x > 0 && y > 0 && z > 0 && x < n && y < n && z < n;
     if (!interior) {
         out[c * N + p] = T(0);

@@ -25,10 +25,7 @@ namespace {
 constexpr int NT = 256;
 
 __device__ __forceinline__ void node_xyz(int64_t p, int n, int& x, int& y, int& z) {
-    const int64_t n1 = n + 1;
-    x = (int)(p % n1);
-    y = (int)((p / n1) % n1);
-    z = (int)(p / (n1 * n1));
+    node_coords(p, n, x, y, z);
 }
 
 // cell of node (x,y,z) that has the node as its corner k, and whether it exists

@@ -26,7 +26,8 @@ k_restrict(int ncomp, int nc, const T* __restrict__ rf, T* __restrict__ rc) {
     const int64_t nf1 = 2 * nc + 1, Nf = nf1 * nf1 * nf1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (p >= Nc) return;
-    const int x = (int)(p % nc1), y = (int)((p / nc1) % nc1), z = (int)(p / (nc1 * nc1));
+    int x, y, z;
+    node_coords(p, nc, x, y, z);
     const bool interior = x > 0 && y > 0 && z > 0 && x < nc && y < nc && z < nc;
     const int64_t q = 2 * x + nf1 * (2 * y + nf1 * (int64_t)(2 * z));
     for (int c = 0; c < ncomp; ++c) {
@@ -53,7 +54,8 @@ k_prolong_add(int ncomp, int nf, const T* __restrict__ ec, T* __restrict__ xf) {
     const int64_t nf1 = nf + 1, Nf = nf1 * nf1 * nf1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (p >= Nf) return;
-    const int x = (int)(p % nf1), y = (int)((p / nf1) % nf1), z = (int)(p / (nf1 * nf1));
+    int x, y, z;
+    node_coords(p, nf, x, y, z);
     if (x == 0 || y == 0 || z == 0 || x == nf || y == nf || z == nf) return;
     const int dx = x & 1, dy = y & 1, dz = z & 1;
     const int64_t lo = ((x - dx) >> 1) + nc1 * (((y - dy) >> 1) + nc1 * (int64_t)((z - dz) >> 1));
@@ -248,7 +250,8 @@ __global__ void __launch_bounds__(NT) k_alternating(int ncomp, int n, double* __
     const int64_t n1 = n + 1, N = n1 * n1 * n1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (p >= N) return;
-    const int xx = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    int xx, y, z;
+    node_coords(p, n, xx, y, z);
     const bool in = xx > 0 && y > 0 && z > 0 && xx < n && y < n && z < n;
     const double v = in ? (((xx + y + z) & 1) ? -1.0 : 1.0) : 0.0;
     for (int c = 0; c < ncomp; ++c) x[c * N + p] = v;
@@ -276,7 +279,8 @@ __global__ void __launch_bounds__(NT) k_zero_boundary(int ncomp, int n, T* __res
     const int64_t n1 = n + 1, N = n1 * n1 * n1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (p >= N) return;
-    const int xx = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    int xx, y, z;
+    node_coords(p, n, xx, y, z);
     if (xx == 0 || y == 0 || z == 0 || xx == n || y == n || z == n)
         for (int c = 0; c < ncomp; ++c) x[c * N + p] = T(0);
 }
@@ -340,7 +344,8 @@ k_load_vector(int n, const double* __restrict__ f, double vol4, double* __restri
     const int64_t n1 = n + 1, N = n1 * n1 * n1, E = 6LL * n * n * n;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (p >= N) return;
-    const int x = (int)(p % n1), y = (int)((p / n1) % n1), z = (int)(p / (n1 * n1));
+    int x, y, z;
+    node_coords(p, n, x, y, z);
     const bool bd = x == 0 || y == 0 || z == 0 || x == n || y == n || z == n;
     double acc[NC];
 #pragma unroll

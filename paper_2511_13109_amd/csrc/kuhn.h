@@ -149,6 +149,17 @@ AGCA_HDC inline int64_t elem_index(int64_t e, int64_t cells) {
     return elem_slot((int)(e % 6), e / 6, cells);
 }
 
+// lattice coordinates of node p = x + (n+1)(y + (n+1) z) on a level with n cells per
+// axis, in 32-bit arithmetic (a level holds at most 1025^3 < 2^32 nodes; 64-bit
+// division would cost several times the instructions of the kernels that use this)
+AGCA_HDC inline void node_coords(int64_t p, int n, int& x, int& y, int& z) {
+    const uint32_t q = (uint32_t)p, n1 = (uint32_t)(n + 1);
+    const uint32_t r = q / n1;
+    x = (int)(q - r * n1);
+    y = (int)(r % n1);
+    z = (int)(r / n1);
+}
+
 // id of child k of element e on a level with n cells (children on the level with 2n cells)
 AGCA_HDC inline int64_t child_id(int64_t n, int64_t e, int k) {
     const int s = (int)(e % 6);

@@ -504,46 +504,53 @@ constexpr double kLanczosBreakdown = 1e-12;
 int32_t estimate_eigenvalues(agca_hier* h) {
     TRY(ensure_solver_vectors(h));
     const int L = h->cfg.L, nc = h->cfg.ncomp;
+    constexpr int K = kLanczosSteps;
+    static_assert(2 * K + 1 <= AGCA_RED_SLOTS, "reduction slots");
     h->lam.assign(L + 1, 0.0);
+    std::vector<double> co(2 * K + 1);
     for (int l = 1; l <= L; ++l) {
         const Level& lv = h->lv[l];
         const int64_t cnt = (int64_t)nc * lv.nodes;
         double *v = h->s_r, *vprev = h->s_z, *w = h->s_p, *y = h->s_q;
-        double s = 0.0;
+        // the whole process runs on the device (alpha_k in slot k, beta_k^2 in slot K + k,
+        // the start vector's D-norm^2 in slot 2K) and is read back once
         HIPCHK(h, launch_alternating(nc, lv.n, w, h->st));
         HIPCHK(h, launch_mul(cnt, lv.diag, w, y, h->st));
-        TRY(do_dot<double>(h, w, y, cnt, &s));
-        if (!(s > 0.0) || !std::isfinite(s)) return fail(AGCA_E_NUMERIC, "eigenvalue estimate failed");
-        HIPCHK(h, launch_axpby<double>(cnt, 1.0 / std::sqrt(s), w, 0.0, v, h->st));
-        std::vector<double> alpha, beta;
-        double b = 0.0;
+        HIPCHK(h, launch_dot_partial<double>(w, y, cnt, h->partial, h->nb_partial, h->st));
+        TRY(reduce_to(h, h->partial, h->nb_partial, 2 * K));
+        HIPCHK(h, launch_scale_rsqrt(cnt, w, h->red + 2 * K, v, h->st));
         const LevelOp<double> op = level_op<double>(h, l);
-        for (int k = 0; k < kLanczosSteps; ++k) {
-            double a = 0.0;
+        for (int k = 0; k < K; ++k) {
             if (op.sten) {
                 TRY(do_cube<double>(h, l, MODE_APPLY, v, nullptr, y, 0.0));
-                TRY(do_dot<double>(h, v, y, cnt, &a));
+                HIPCHK(h, launch_dot_partial<double>(v, y, cnt, h->partial, h->nb_partial, h->st));
+                TRY(reduce_to(h, h->partial, h->nb_partial, k));
             } else {
                 // element-loop level: y = A v with v . A v in the same pass
                 int nbq = 0;
-                double tmp[1];
                 HIPCHK(h, launch_cube_dot(nc, op, v, y, h->partial, &nbq, h->st));
-                TRY(reduce_to(h, h->partial, nbq, 0));
-                TRY(fetch(h, 1, tmp));
-                a = tmp[0];
+                TRY(reduce_to(h, h->partial, nbq, k));
             }
-            HIPCHK(h, launch_div_or_zero(cnt, y, lv.diag, w, h->st));
-            HIPCHK(h, launch_axpby<double>(cnt, -a, v, 1.0, w, h->st));
-            if (k > 0) HIPCHK(h, launch_axpby<double>(cnt, -b, vprev, 1.0, w, h->st));
-            alpha.push_back(a);
-            HIPCHK(h, launch_mul(cnt, lv.diag, w, y, h->st));
-            TRY(do_dot<double>(h, w, y, cnt, &s));
+            HIPCHK(h, launch_lanczos_step(cnt, y, lv.diag, v, k > 0 ? vprev : nullptr, h->red + k,
+                                          k > 0 ? h->red + K + k - 1 : nullptr, w, h->partial,
+                                          h->nb_partial, h->st));
+            TRY(reduce_to(h, h->partial, h->nb_partial, K + k));
+            // after a breakdown (beta_k = 0) the later steps compute non-finite values that
+            // are never read: the host cuts the sequence at the breakdown
+            HIPCHK(h, launch_scale_rsqrt(cnt, w, h->red + K + k, vprev, h->st));
+            std::swap(v, vprev);
+        }
+        TRY(fetch(h, 2 * K + 1, co.data()));
+        if (!(co[2 * K] > 0.0) || !std::isfinite(co[2 * K]))
+            return fail(AGCA_E_NUMERIC, "eigenvalue estimate failed");
+        std::vector<double> alpha, beta;
+        for (int k = 0; k < K; ++k) {
+            const double a = co[k], s = co[K + k];
             if (!std::isfinite(a) || !std::isfinite(s)) return fail(AGCA_E_NUMERIC, "eigenvalue estimate failed");
-            b = std::sqrt(std::max(s, 0.0));
+            alpha.push_back(a);
+            const double b = std::sqrt(std::max(s, 0.0));
             if (!(b > kLanczosBreakdown * std::fabs(a))) break;
             beta.push_back(b);
-            HIPCHK(h, launch_axpby<double>(cnt, 1.0 / b, w, 0.0, vprev, h->st));
-            std::swap(v, vprev);
         }
         beta.resize(alpha.size() - 1);
         h->lam[l] = tridiag_max_eigenvalue(alpha, beta);

@@ -97,6 +97,13 @@ hipError_t launch_dot2(int64_t n, const Z* z, const double* r, const double* q, 
 template <typename Z>
 hipError_t launch_zpbp(int64_t n, const Z* z, double beta, double* p, hipStream_t st);
 hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st);
+// Lanczos step with device coefficients: w = y / d - alpha[0] v - sqrt(beta2[0]) u (no u
+// term when u is null), partial sums of w . (d w) over nblocks workgroups
+hipError_t launch_lanczos_step(int64_t n, const double* y, const double* d, const double* v,
+                               const double* u, const double* alpha, const double* beta2, double* w,
+                               double* partial, int nblocks, hipStream_t st);
+// out = x / sqrt(s[0]) (s on the device)
+hipError_t launch_scale_rsqrt(int64_t n, const double* x, const double* s, double* out, hipStream_t st);
 template <typename T>
 hipError_t launch_zero_boundary(int ncomp, int n, T* x, hipStream_t st);
 template <typename T>

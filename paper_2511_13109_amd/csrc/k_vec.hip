@@ -200,6 +200,38 @@ k_zpbp(int64_t n, const Z* __restrict__ z, double beta, double* __restrict__ p) 
     }
 }
 
+// One Lanczos step for the pencil (A, D) with the coefficients on the device:
+// w = y / d - alpha v - beta u (0 where d = 0; beta = sqrt(beta2[0]), no u term when u is
+// null), and the partial sums of w . (d w).
+__global__ void __launch_bounds__(NT)
+k_lanczos_step(int64_t n, const double* __restrict__ y, const double* __restrict__ d,
+               const double* __restrict__ v, const double* __restrict__ u,
+               const double* __restrict__ alpha, const double* __restrict__ beta2,
+               double* __restrict__ w, double* __restrict__ partial) {
+    const double a = alpha[0];
+    const double b = u ? sqrt(fmax(beta2[0], 0.0)) : 0.0;
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
+        const double dv = d[i];
+        double wi = dv > 0.0 ? y[i] / dv : 0.0;
+        wi -= a * v[i];
+        if (u) wi -= b * u[i];
+        w[i] = wi;
+        acc += wi * (dv * wi);
+    }
+    block_sum_store(acc, partial + blockIdx.x);
+}
+
+// out = x / sqrt(s[0])
+__global__ void __launch_bounds__(NT)
+k_scale_rsqrt(int64_t n, const double* __restrict__ x, const double* __restrict__ s,
+              double* __restrict__ out) {
+    const double r = sqrt(s[0]);
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) out[i] = x[i] / r;
+}
+
 // FP64 -> BF16 with a single round-to-nearest-even: round to FP32 with
 // "round to odd" (truncate, then set the last bit if inexact), which keeps the
 // information a second rounding needs, then round that FP32 value to BF16.
@@ -441,6 +473,20 @@ hipError_t launch_zpbp(int64_t n, const Z* z, double beta, double* p, hipStream_
 }
 template hipError_t launch_zpbp<double>(int64_t, const double*, double, double*, hipStream_t);
 template hipError_t launch_zpbp<float>(int64_t, const float*, double, double*, hipStream_t);
+hipError_t launch_lanczos_step(int64_t n, const double* y, const double* d, const double* v,
+                               const double* u, const double* alpha, const double* beta2, double* w,
+                               double* partial, int nblocks, hipStream_t st) {
+    if (!y || !d || !v || !alpha || (u && !beta2) || !w || !partial || nblocks <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lanczos_step, dim3(nblocks), dim3(NT), 0, st, n, y, d, v, u, alpha, beta2, w,
+                       partial);
+    return hipGetLastError();
+}
+hipError_t launch_scale_rsqrt(int64_t n, const double* x, const double* s, double* out, hipStream_t st) {
+    if (!x || !s || !out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scale_rsqrt, dim3(grid_stride(n)), dim3(NT), 0, st, n, x, s, out);
+    return hipGetLastError();
+}
 hipError_t launch_cast(int from, int to, const void* src, void* dst, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (!src || !dst) return hipErrorInvalidValue;

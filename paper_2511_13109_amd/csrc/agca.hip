@@ -1229,8 +1229,8 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     } else if (rel > o->tol) {
         if (o->solver == AGCA_SOLVER_PCG || o->solver == AGCA_SOLVER_FCG) {
             // FCG(1): beta = z_k . (r_k - r_{k-1}) / (z_{k-1} . r_{k-1}), formed as
-            // -alpha z_k . q_{k-1} / (z_{k-1} . r_{k-1}) since r_k - r_{k-1} = -alpha q_{k-1}
-            // (no copy of the old residual).  With the FP32 V-cycle the residual update
+            // -alpha z_k . q_{k-1} / (z_{k-1} . r_{k-1}) = -z_k . q_{k-1} / (p_{k-1} . q_{k-1})
+            // since r_k - r_{k-1} = -alpha q_{k-1} (no copy of the old residual).  With the FP32 V-cycle the residual update
             // also writes the V-cycle's FP32 input, and z stays in FP32: the dot products
             // and the direction update widen it on the fly.
             const bool flex = o->solver == AGCA_SOLVER_FCG;
@@ -1247,42 +1247,45 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                 return mixed ? launch_zpbp<float>(cnt, z32, beta, p, h->st)
                              : launch_zpbp<double>(cnt, z, beta, p, h->st);
             };
-            double rz = 0.0, alpha = 0.0;
+            // The scalars stay in reduction slots on the device (alpha = rz / pq and beta are
+            // formed by the kernels that use them); the host reads p.q, r.r and z.r once per
+            // iteration for the stopping test and the breakdown checks.
+            auto direction_dev = [&](const double* num, const double* den, double sign) -> hipError_t {
+                return mixed ? launch_zpbp_dev<float>(cnt, z32, num, den, sign, p, h->st)
+                             : launch_zpbp_dev<double>(cnt, z, num, den, sign, p, h->st);
+            };
+            constexpr int PQ = 0, RR = 1, ZR = 2, ZQ = 3, RZ = 4;
+            double* red = h->red;
             bool restart = true;
-            double tmp[2];
+            double tmp[5];
             while (it < o->max_iter) {
                 if (restart) {
                     if (mixed) HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, r, r32, cnt, h->st));
                     TRY(vcycle());
                     HIPCHK(h, dots(nullptr));
-                    TRY(reduce_to(h, h->partial, h->nb_partial, 0));
-                    TRY(fetch(h, 1, tmp));
-                    rz = tmp[0];
+                    TRY(reduce_to(h, h->partial, h->nb_partial, RZ));
                     HIPCHK(h, direction(0.0));
                     restart = false;
-                }
-                if (!(rz > 0.0) || !std::isfinite(rz)) {
-                    status = fail(AGCA_E_NUMERIC, "preconditioned residual is not positive");
-                    break;
                 }
                 // q = A p fused with p . q
                 int nbq = 0;
                 HIPCHK(h, launch_cube_dot(h->cfg.ncomp, level_op<double>(h, L), p, q, h->partial, &nbq,
                                           h->st));
-                TRY(reduce_to(h, h->partial, nbq, 0));
-                TRY(fetch(h, 1, tmp));
-                const double pq = tmp[0];
-                if (!(pq > 0.0) || !std::isfinite(pq)) {
+                TRY(reduce_to(h, h->partial, nbq, PQ));
+                // x += alpha p, r -= alpha q (and its FP32 copy), fused with r . r
+                HIPCHK(h, launch_cg_update(cnt, red + RZ, red + PQ, p, q, x, r, mixed ? r32 : nullptr,
+                                           h->partial, h->nb_partial, h->st));
+                TRY(reduce_to(h, h->partial, h->nb_partial, RR));
+                TRY(fetch(h, 5, tmp));
+                if (!(tmp[RZ] > 0.0) || !std::isfinite(tmp[RZ])) {
+                    status = fail(AGCA_E_NUMERIC, "preconditioned residual is not positive");
+                    break;
+                }
+                if (!(tmp[PQ] > 0.0) || !std::isfinite(tmp[PQ])) {
                     status = fail(AGCA_E_NUMERIC, "search direction has non-positive energy");
                     break;
                 }
-                alpha = rz / pq;
-                // x += alpha p, r -= alpha q (and its FP32 copy), fused with r . r
-                HIPCHK(h, launch_cg_update(cnt, alpha, p, q, x, r, mixed ? r32 : nullptr, h->partial,
-                                           h->nb_partial, h->st));
-                TRY(reduce_to(h, h->partial, h->nb_partial, 0));
-                TRY(fetch(h, 1, tmp));
-                rr = tmp[0];
+                rr = tmp[RR];
                 ++it;
                 rel = rec_rel = std::sqrt(rr) / bn;
                 record(rel);
@@ -1300,13 +1303,11 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                 TRY(vcycle());
                 // z . r and, for FCG, z . q in one pass
                 HIPCHK(h, dots(flex ? q : nullptr));
-                TRY(reduce_to(h, h->partial, h->nb_partial, 0));
-                if (flex) TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, 1));
-                TRY(fetch(h, flex ? 2 : 1, tmp));
-                const double rz_new = tmp[0];
-                const double beta = flex ? -alpha * tmp[1] / rz : rz_new / rz;
-                rz = rz_new;
-                HIPCHK(h, direction(beta));
+                TRY(reduce_to(h, h->partial, h->nb_partial, ZR));
+                if (flex) TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, ZQ));
+                // FCG: beta = -alpha z.q / rz_old = -z.q / p.q; PCG: beta = z.r / rz_old
+                HIPCHK(h, flex ? direction_dev(red + ZQ, red + PQ, -1.0) : direction_dev(red + ZR, red + RZ, 1.0));
+                HIPCHK(h, hipMemcpyAsync(red + RZ, red + ZR, sizeof(double), hipMemcpyDeviceToDevice, h->st));
             }
         } else {
             // iterative refinement / stationary: x += B r, r = b - A x (the residual is exact)

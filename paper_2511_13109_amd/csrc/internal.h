@@ -85,10 +85,15 @@ hipError_t launch_dot_partial(const T* x, const T* y, int64_t n, double* partial
 hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t st);
 template <typename T>
 hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStream_t st);  // y = a x + b y
-// CG update: x += alpha p, r -= alpha q (and r32 = FP32 copy of the new r if r32 != null),
-// and partial sums of r . r over nblocks workgroups
-hipError_t launch_cg_update(int64_t n, double alpha, const double* p, const double* q, double* x,
-                            double* r, float* r32, double* partial, int nblocks, hipStream_t st);
+// CG update: x += alpha p, r -= alpha q with alpha = rz[0] / pq[0] on the device (and r32 =
+// FP32 copy of the new r if r32 != null), and partial sums of r . r over nblocks workgroups
+hipError_t launch_cg_update(int64_t n, const double* rz, const double* pq, const double* p,
+                            const double* q, double* x, double* r, float* r32, double* partial,
+                            int nblocks, hipStream_t st);
+// p = z + beta p with beta = sign num[0] / den[0] on the device
+template <typename Z>
+hipError_t launch_zpbp_dev(int64_t n, const Z* z, const double* num, const double* den, double sign,
+                           double* p, hipStream_t st);
 // partial sums of z . r and z . q (two arrays of nblocks; the second only if q != null)
 template <typename Z>
 hipError_t launch_dot2(int64_t n, const Z* z, const double* r, const double* q, double* partial,

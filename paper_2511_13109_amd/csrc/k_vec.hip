@@ -153,12 +153,14 @@ __device__ __forceinline__ void block_sum_store(double v, double* __restrict__ o
     __syncthreads();
 }
 
-// x += alpha p, r -= alpha q, and r . r; with r32 the new residual is also stored in
-// FP32 (the input of the FP32 V-cycle)
+// x += alpha p, r -= alpha q with alpha = rz / pq read from the device, and r . r; with
+// r32 the new residual is also stored in FP32 (the input of the FP32 V-cycle)
 __global__ void __launch_bounds__(NT)
-k_cg_update(int64_t n, double alpha, const double* __restrict__ p, const double* __restrict__ q,
+k_cg_update(int64_t n, const double* __restrict__ rz, const double* __restrict__ pq,
+            const double* __restrict__ p, const double* __restrict__ q,
             double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
             double* __restrict__ partial) {
+    const double alpha = rz[0] / pq[0];
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * NT;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
@@ -185,6 +187,17 @@ k_dot2(int64_t n, const Z* __restrict__ z, const double* __restrict__ r,
     }
     block_sum_store(a, partial + blockIdx.x);
     block_sum_store(b, partial + gridDim.x + blockIdx.x);
+}
+
+// p = z + beta p with beta = sign num[0] / den[0] read from the device
+template <typename Z>
+__global__ void __launch_bounds__(NT)
+k_zpbp_dev(int64_t n, const Z* __restrict__ z, const double* __restrict__ num,
+           const double* __restrict__ den, double sign, double* __restrict__ p) {
+    const double beta = sign * num[0] / den[0];
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride)
+        p[i] = (double)z[i] + beta * p[i];
 }
 
 // p = z + beta p (beta = 0: p = z without reading p), z in FP64 or FP32
@@ -447,12 +460,25 @@ hipError_t launch_axpby(int64_t n, double a, const T* x, double b, T* y, hipStre
     hipLaunchKernelGGL(k_axpby<T>, dim3(grid_stride(n)), dim3(NT), 0, st, n, a, x, b, y);
     return hipGetLastError();
 }
-hipError_t launch_cg_update(int64_t n, double alpha, const double* p, const double* q, double* x,
-                            double* r, float* r32, double* partial, int nblocks, hipStream_t st) {
-    if (!p || !q || !x || !r || !partial || nblocks <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cg_update, dim3(nblocks), dim3(NT), 0, st, n, alpha, p, q, x, r, r32, partial);
+hipError_t launch_cg_update(int64_t n, const double* rz, const double* pq, const double* p,
+                            const double* q, double* x, double* r, float* r32, double* partial,
+                            int nblocks, hipStream_t st) {
+    if (!rz || !pq || !p || !q || !x || !r || !partial || nblocks <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cg_update, dim3(nblocks), dim3(NT), 0, st, n, rz, pq, p, q, x, r, r32, partial);
     return hipGetLastError();
 }
+template <typename Z>
+hipError_t launch_zpbp_dev(int64_t n, const Z* z, const double* num, const double* den, double sign,
+                           double* p, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!z || !num || !den || !p) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zpbp_dev<Z>, dim3(grid_stride(n)), dim3(NT), 0, st, n, z, num, den, sign, p);
+    return hipGetLastError();
+}
+template hipError_t launch_zpbp_dev<double>(int64_t, const double*, const double*, const double*, double,
+                                            double*, hipStream_t);
+template hipError_t launch_zpbp_dev<float>(int64_t, const float*, const double*, const double*, double,
+                                           double*, hipStream_t);
 template <typename Z>
 hipError_t launch_dot2(int64_t n, const Z* z, const double* r, const double* q, double* partial,
                        int nblocks, hipStream_t st) {

@@ -114,8 +114,8 @@ SOLVER_KERNEL_BYTES = {
     "k_cg_update": ("x += a p, r -= a q, r.r (mixed: + FP32 r)", 3 * 6 * 8, 0),
     "k_dot2<double>": ("z.r (PCG)", 3 * 16, 0),
     "k_dot2<float>": ("z.r, z.q (FCG, FP32 z)", 3 * 20, 0),
-    "k_zpbp<double>": ("p = z + beta p", 3 * 24, 0),
-    "k_zpbp<float>": ("p = z + beta p (FP32 z)", 3 * 20, 0),
+    "k_zpbp_dev<double>": ("p = z + beta p", 3 * 24, 0),
+    "k_zpbp_dev<float>": ("p = z + beta p (FP32 z)", 3 * 20, 0),
     # per fine node; the coarse vector (1/8 of the nodes) is added below
     "k_restrict<double>": ("restriction 129^3 -> 65^3", 3 * 8, 0),
     "k_restrict<float>": ("restriction 129^3 -> 65^3, FP32", 3 * 4, 0),

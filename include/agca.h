@@ -266,7 +266,7 @@ typedef enum { AGCA_STOKES_FGMRES = 0, AGCA_STOKES_MINRES = 1 } agca_stokes_solv
 typedef enum { AGCA_STOKES_DIAGONAL = 0, AGCA_STOKES_TRIANGULAR = 1 } agca_stokes_precond;
 typedef struct {
     int32_t solver;          /* agca_stokes_solver                                          */
-    int32_t restart;         /* FGMRES restart length, 1..126                              */
+    int32_t restart;         /* FGMRES restart length, 1..510                              */
     int32_t max_iter;
     int32_t record_history;
     double tol;              /* stop when ||r||_2 <= tol ||(f, g)||_2 (eq. (4.3))           */

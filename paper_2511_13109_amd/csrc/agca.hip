@@ -97,7 +97,7 @@ namespace {
 
 // device reduction slots (and their pinned host mirror): Krylov coefficients of one
 // Arnoldi step at the largest Stokes restart length
-constexpr int AGCA_RED_SLOTS = 128;
+constexpr int AGCA_RED_SLOTS = 512;
 
 int64_t nodes_of(int n) { return (int64_t)(n + 1) * (n + 1) * (n + 1); }
 int64_t elems_of(int n) { return 6LL * n * n * n; }
@@ -1667,7 +1667,7 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     if (o->solver != AGCA_STOKES_FGMRES && o->solver != AGCA_STOKES_MINRES)
         return fail(AGCA_E_INVALID, "unknown Stokes solver");
     if (o->solver == AGCA_STOKES_FGMRES && (o->restart < 1 || o->restart > AGCA_RED_SLOTS - 2))
-        return fail(AGCA_E_INVALID, "restart must be in [1, 126]");
+        return fail(AGCA_E_INVALID, "restart must be in [1, " + std::to_string(AGCA_RED_SLOTS - 2) + "]");
     if (o->precond != AGCA_STOKES_DIAGONAL && o->precond != AGCA_STOKES_TRIANGULAR)
         return fail(AGCA_E_INVALID, "unknown Stokes preconditioner");
     if (o->precond == AGCA_STOKES_TRIANGULAR && o->solver != AGCA_STOKES_FGMRES)

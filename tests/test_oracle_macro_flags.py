@@ -11,6 +11,8 @@ and Fig. 9) and of AGCA with macro flags (eq. (2.9)).
 * All macros flagged reproduces pure Galerkin coarsening, none reproduces DCA.
 """
 
+import os
+
 import numpy as np
 import pytest
 
@@ -33,13 +35,26 @@ def test_linear_field_has_constant_gradient(L):
     assert np.allclose(g, np.linalg.norm(a), rtol=1e-12, atol=0)
 
 
+def _fig9():
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fig9_gca_macros.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
 @pytest.mark.parametrize("L", [2, 3, 4])
 def test_sharp_unaligned_cube_meets_24_of_48_macros(L):
+    fig9 = _fig9()
+    lo, hi = fig9["centre"] - fig9["half_width"], fig9["centre"] + fig9["half_width"]
     levels = mesh.hierarchy(L)
     X = _nodes(levels[L])
-    inside = np.all((X > 1.0 / 3.0) & (X < 7.0 / 12.0), axis=1)
+    inside = np.all((X > lo) & (X < hi), axis=1)
     g = agca.macro_gradient_max(levels, np.where(inside, 1e3, 1.0))
-    assert int((g > 0).sum()) == 24
+    assert g.size == int(fig9["macro_elements"])
+    assert int((g > 0).sum()) == int(fig9["gca_macro_elements"])
     # the flagged macros are the ones whose centroid-side of the box is right:
     # a macro meets the box iff it holds a node inside it
     lv0 = levels[0]

@@ -326,3 +326,23 @@ def _jacobi_twin(H):
     J.smoother = "jacobi"
     J.nu1 = J.nu2 = 2
     return J
+
+
+def test_stationary_mg_cube17():
+    # the scalar aligned-cube workload's solver: stationary V(2,2) iterations to 1e-10
+    H, G = _gpu(("cube", 3, 1))
+    try:
+        lv = H.levels[H.L]
+        b = fem.load_vector(lv, np.ones(lv.tets.shape[0]), 1)
+        m = interior_full(H, H.L)
+        ref = mg.stationary(H, b[m], 1e-10, maxit=3000)
+        assert ref.converged
+        x, st = G.solve(_dev(b), solver="stationary", tol=1e-10, max_iter=3000)
+        print(f"\n[stationary cube17] gpu {st['iterations']} it, oracle {ref.iterations} it", flush=True)
+        assert st["converged"] and st["rel_residual"] <= 1e-10
+        assert abs(st["iterations"] - ref.iterations) <= 1
+        k = min(len(st["history"]), len(ref.history), 50)
+        assert np.allclose(st["history"][:k], ref.history[:k], rtol=1e-6, atol=0)
+        assert rel_err(x.cpu().numpy()[m], ref.x) <= 1e-8
+    finally:
+        G.close()

@@ -452,7 +452,7 @@ def report_stokes(args, dev) -> dict:
                            max_iter=args.stokes_max_iter, record_history=False, raise_on_noconv=False,
                            precond=pc)
         out[f"{solver}_{pc}_{mg}_mg"] = {k: st[k] for k in ("iterations", "seconds", "rel_residual",
-                                                              "converged")}
+                                                              "converged", "floor_limited")}
         print(f"[stokes] {solver} {pc} {mg}-MG: {st['iterations']} it {st['seconds']:.2f} s "
               f"res {st['rel_residual']:.2e}", file=sys.stderr, flush=True)
         H.close()

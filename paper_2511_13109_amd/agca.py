@@ -313,6 +313,7 @@ class Stokes:
         rc = self.H._lib.agca_stokes_solve(self.H._h, C.byref(opts), _ptr(f), _ptr(g), _ptr(u), _ptr(p),
                                            C.byref(st))
         stats = {"iterations": st.iterations, "converged": bool(st.converged),
+                 "floor_limited": bool(st.floor_limited),
                  "rel_residual": st.rel_residual, "seconds": st.seconds, "status": rc,
                  "history": list(st.history[:min(st.iterations + 1, _lib.MAX_HISTORY)])
                  if record_history else []}

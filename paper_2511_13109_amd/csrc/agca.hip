@@ -1463,7 +1463,8 @@ static int32_t stokes_residual(agca_hier* h, const double* b, const double* x, d
 // sinker problems without changing a single iteration count, at twice the cost).
 constexpr double kDgks = 0.1;
 static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const double* b, double* x,
-                             double bn, double* rel_out, int* it_out, std::vector<double>& hist) {
+                             double bn, double* rel_out, int* it_out, std::vector<double>& hist,
+                             bool* floor_out) {
     const int64_t tot = stokes_dims(h).tot;
     const int m = o->restart;
     TRY(stokes_work(h, 2 * (int64_t)m + 3));
@@ -1480,6 +1481,7 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
     hist.push_back(rel);
     int it = 0;
     std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), col(m + 3);
+    std::vector<double> cycle_res;  // true residual after each restart cycle
     const int nb = gs_blocks(tot);
     if (h->st_gs_cap < (int64_t)(m + 2) * nb) {
         for (size_t i = 0; h->st_gs && i < h->allocs.size(); ++i)
@@ -1558,6 +1560,14 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
         rel /= bn;
         hist.back() = rel;
         if (rel <= o->tol) break;
+        // rounding floor: within 10x of the tolerance and less than 5 % better than four
+        // restart cycles ago (the true residual of an FP64 iterate stagnates there)
+        cycle_res.push_back(rel);
+        const size_t c = cycle_res.size();
+        if (c >= 5 && rel < 10.0 * o->tol && rel > 0.95 * cycle_res[c - 5]) {
+            *floor_out = true;
+            break;
+        }
     }
     *rel_out = rel;
     *it_out = it;
@@ -1692,12 +1702,13 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     std::vector<double> hist;
     double rel = 0.0;
     int it = 0;
+    bool floor_limited = false;
     if (bn == 0.0) {
         HIPCHK(h, launch_fill<double>(d.tot, 0.0, xvec, h->st));
         hist.push_back(0.0);
     } else {
         const int32_t rc = (o->solver == AGCA_STOKES_FGMRES)
-                               ? stokes_fgmres(h, o, bvec, xvec, bn, &rel, &it, hist)
+                               ? stokes_fgmres(h, o, bvec, xvec, bn, &rel, &it, hist, &floor_limited)
                                : stokes_minres(h, o, bvec, xvec, bn, &rel, &it, hist);
         h->st_tri = nullptr;
         if (rc != AGCA_OK) return rc;
@@ -1718,10 +1729,12 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     stats->rel_residual = rel;
     stats->recursive_rel_residual = hist.empty() ? rel : hist.back();
     stats->converged = rel <= o->tol || bn == 0.0;
+    stats->floor_limited = (!stats->converged && floor_limited) ? 1 : 0;
     for (size_t i = 0; i < hist.size() && i < (size_t)AGCA_MAX_HISTORY; ++i)
         if (o->record_history) stats->history[i] = hist[i];
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (!stats->converged) return fail(AGCA_E_NOCONV, "no convergence within max_iter");
+    if (!stats->converged && !stats->floor_limited)
+        return fail(AGCA_E_NOCONV, "no convergence within max_iter");
     return AGCA_OK;
 }
 

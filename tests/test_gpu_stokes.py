@@ -143,3 +143,34 @@ def test_fgmres_below_the_rounding_floor_stays_finite(case):
     assert np.all(np.isfinite(st["history"]))
     xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
     assert np.linalg.norm(b - S.K @ xg) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_fgmres_stops_at_the_rounding_floor(case):
+    # The true residual of an FP64 iterate cannot go below a floor set by rounding.
+    # Measure that floor with an unreachable tolerance, then ask for a third of it: the
+    # solve must stop by itself (floor_limited, AGCA_OK) long before max_iter, with a
+    # residual within 10x of the tolerance.
+    L, levels, H, S, fu, GS, _ = case
+    if L != 3:
+        pytest.skip("one size is enough")
+    b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
+    _, _, s0 = GS.solve(_dev(fu), solver="fgmres", restart=30, tol=1e-17, max_iter=1500,
+                        precond="triangular", raise_on_noconv=False)
+    assert not s0["converged"]
+    floor = s0["rel_residual"]
+    tol = floor / 3
+    u, p, st = GS.solve(_dev(fu), solver="fgmres", restart=30, tol=tol, max_iter=3000,
+                        precond="triangular")
+    print(f"[fgmres floor L={L}] floor {floor:.2e} ({s0['iterations']} it, "
+          f"floor_limited {s0['floor_limited']}); tol {tol:.2e}: {st['iterations']} it, "
+          f"rel {st['rel_residual']:.2e}, floor_limited {st['floor_limited']}", flush=True)
+    assert st["floor_limited"] and not st["converged"]
+    assert tol < st["rel_residual"] < 10 * tol
+    assert st["iterations"] < 3000
+    xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
+    # recomputed by the oracle (assembled K, another order of additions): the same floor
+    assert np.linalg.norm(b - S.K @ xg) <= 10 * floor * np.linalg.norm(b)
+    # a reachable tolerance converges and is not reported as floor limited
+    _, _, sr = GS.solve(_dev(fu), solver="fgmres", restart=30, tol=1e-9, max_iter=3000,
+                        precond="triangular")
+    assert sr["converged"] and not sr["floor_limited"]

@@ -314,28 +314,6 @@ def profile_apply(name: str, dev) -> None:
     print("profile-apply done", flush=True)
 
 
-def device_inputs(w, dev, chunk: int = 1 << 25):
-    """Coefficients of every level and the forcing, evaluated on the device (inputs too
-    large for the host generators); the same seeded field as the host evaluation."""
-    import torch
-    from workloads.lattice import element_centroids_torch
-    field = w.make_field()
-    nus = []
-    for l in range(w.L + 1):
-        E = 6 * (2 ** (l + 1)) ** 3
-        out = torch.empty(E, dtype=torch.float64, device=dev)
-        for s0 in range(0, E, chunk):
-            s1 = min(E, s0 + chunk)
-            out[s0:s1] = field.nu_torch(element_centroids_torch(l, s0, s1, dev))
-        nus.append(out)
-    E = nus[-1].numel()
-    f = torch.zeros((w.ncomp, E), dtype=torch.float64, device=dev)
-    for s0 in range(0, E, chunk):
-        s1 = min(E, s0 + chunk)
-        f[-1, s0:s1] = -field.xi_torch(element_centroids_torch(w.L, s0, s1, dev))
-    return nus, f.reshape(-1)
-
-
 def progress(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
@@ -364,6 +342,7 @@ def report_large(args, dev) -> dict:
     import torch
     from paper_2511_13109_amd import Hierarchy
     from workloads import workload
+    from workloads.device import device_inputs
     w = workload(args.workload, L=args.level)
     L, nc = w.L, w.ncomp
     t0 = time.perf_counter()
@@ -434,6 +413,7 @@ def report_stokes(args, dev) -> dict:
     import torch
     from paper_2511_13109_amd import Hierarchy, Stokes
     from workloads import workload
+    from workloads.device import device_inputs
     w = workload(args.workload, L=args.level)
     L = w.L
     nus, f = device_inputs(w, dev)

@@ -12,7 +12,9 @@ element's hat functions at the fine vertices.
 
 Operator rows at a node need every element around it; those are found by
 locating points just off the node in many directions and are checked to be
-complete (their solid angles at the node sum to 4 pi).
+complete (their solid angles at the node sum to 4 pi).  The Stokes rows (divergence,
+its transpose, the 1/nu pressure mass) integrate over the support of one pressure hat:
+the coarse star around the pressure node, each coarse element split into its children.
 """
 
 from __future__ import annotations
@@ -215,4 +217,84 @@ def coarse_apply_at_node(level: int, fine: int, node_xyz, nu_level_by_id: np.nda
         y = K @ ue
         for c in range(ncomp):
             out[c] += y[4 * c + a]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Generalized Stokes pieces (Section 3.1, the P1-iso-P2 / P1 pair of eqs. (3.3)-(3.5)):
+# velocity P1 on level ``fine``, pressure P1 on level ``fine - 1``.  B_kj is minus the
+# integral of psi_k div Phi_j with psi_k the pressure hat of node k; psi_k is linear on
+# every velocity element d, so that integral over d is |d| (div Phi_j)|_d times the mean
+# of psi_k at d's four vertices.
+# ---------------------------------------------------------------------------
+
+def _values_at(level: int, x, values_by_node: np.ndarray) -> float:
+    """Value at the point x of the level-``level`` P1 function with the given nodal values
+    (barycentric interpolation in an element containing x; every containing element
+    gives the same value, the function being continuous)."""
+    c4, nid, _ = locate(level, x)
+    return float(_bary(c4, np.asarray(x, dtype=np.float64)) @ values_by_node[nid])
+
+
+def _node_ids(coords: np.ndarray, level: int) -> np.ndarray:
+    n = 2 ** (level + 1)
+    q = np.rint(np.asarray(coords) * n).astype(np.int64)
+    return q[..., 0] + (n + 1) * (q[..., 1] + (n + 1) * q[..., 2])
+
+
+def pressure_support(fine: int, node_xyz, seed: int = 0):
+    """The level-``fine`` elements in the support of the pressure hat psi_k of the interior
+    level-(fine-1) node at node_xyz: list of (coords4, node ids (4,), element id, psi_k at
+    the four vertices).  The support is the star of coarse elements around the node,
+    each split into its eight Bey children."""
+    x = np.asarray(node_xyz, dtype=np.float64)
+    coarse = fine - 1
+    out = []
+    for c4, _, _, _ in elements_around(coarse, x, seed):
+        cc4, coords, tets, _, fids = descendants(coarse, fine, c4.mean(axis=0))
+        k = int(np.argmin(np.linalg.norm(cc4 - x, axis=1)))
+        for t in range(tets.shape[0]):
+            f4 = coords[tets[t]]
+            psi = np.array([_bary(cc4, v)[k] for v in f4])
+            out.append((f4, _node_ids(f4, fine), int(fids[t]), psi))
+    return out
+
+
+def div_at_pressure_node(fine: int, node_xyz, u_full: np.ndarray, seed: int = 0) -> float:
+    """(B u)_k at an interior pressure node: minus the sum over the velocity elements d in
+    the support of psi_k of |d| div(u)|_d times the mean of psi_k over d (u_full:
+    [3][(n+1)^3], boundary velocity values taken as zero)."""
+    n = 2 ** (fine + 1)
+    nn = (n + 1) ** 3
+    free = _free_mask(fine)
+    out = 0.0
+    for f4, nid, _, psi in pressure_support(fine, node_xyz, seed):
+        g, vol = fem.element_geometry(f4[None])
+        div = 0.0
+        for c in range(3):
+            div += float(g[0, :, c] @ np.where(free(nid), u_full[c * nn + nid], 0.0))
+        out -= vol[0] * div * psi.mean()
+    return out
+
+
+def mass_at_pressure_node(fine: int, node_xyz, nu_fine_by_id: np.ndarray, seed: int = 0) -> float:
+    """The 1/nu-weighted lumped pressure mass m_k = sum over the velocity elements d in the
+    support of psi_k of |d| / nu_d times psi_k at d's centroid (the mean at its vertices)."""
+    out = 0.0
+    for f4, _, eid, psi in pressure_support(fine, node_xyz, seed):
+        _, vol = fem.element_geometry(f4[None])
+        out += vol[0] / float(nu_fine_by_id[eid]) * psi.mean()
+    return out
+
+
+def grad_at_velocity_node(fine: int, node_xyz, p_coarse: np.ndarray, seed: int = 0) -> np.ndarray:
+    """(B^T p) at an interior velocity node j, components c = 0..2: minus the sum over the
+    level-``fine`` elements d around j of |d| (d lambda_j / d x_c)|_d times the mean over d
+    of the pressure p_h (the level fine-1 P1 function with nodal values p_coarse),
+    evaluated at d's vertices by interpolation on the pressure level."""
+    out = np.zeros(3)
+    for c4, _, _, a in elements_around(fine, node_xyz, seed):
+        g, vol = fem.element_geometry(c4[None])
+        ph = np.mean([_values_at(fine - 1, v, p_coarse) for v in c4])
+        out -= vol[0] * g[0, a, :] * ph
     return out

@@ -114,3 +114,33 @@ def test_input_centroids_are_geometric():
     from workloads.lattice import element_centroids
     for l in range(3):
         assert np.array_equal(element_centroids(l), mesh.centroids_canonical(mesh.hierarchy(l)[l]))
+
+
+def test_stokes_rows(case):
+    # the element-by-element divergence, its transpose and the 1/nu pressure mass (support
+    # of one pressure hat, interpolation on the pressure level) against the global oracle
+    # (B = -P^T B_L assembled over all elements, m = P^T m_L)
+    from oracle import stokes
+    levels, field, nu = case
+    coarse, fine = levels[L - 1], levels[L]
+    n, nc_n = fine.n, coarse.n
+    nn, npn = (n + 1) ** 3, (nc_n + 1) ** 3
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal(3 * nn)
+    fm = np.zeros(3 * nn, bool)
+    fm[fem.free_dofs(fine, 3)] = True
+    B = stokes.div_matrix(coarse, fine)
+    q = B @ np.where(fm, u, 0.0)
+    p = rng.standard_normal(npn)
+    v = B.T @ p
+    m = stokes.lumped_mass(coarse, fine, nu[L])
+    for node in [(1, 1, 1), (2, 5, 3), (4, 4, 4), (7, 1, 6)]:         # pressure nodes
+        k = node[0] + (nc_n + 1) * (node[1] + (nc_n + 1) * node[2])
+        x = np.array(node) / nc_n
+        assert abs(sample.div_at_pressure_node(L, x, u) - q[k]) <= 1e-13 * np.abs(q).max()
+        assert abs(sample.mass_at_pressure_node(L, x, nu[L]) - m[k]) <= 1e-13 * m[k]
+    for node in [(1, 1, 1), (3, 5, 7), (8, 8, 8), (15, 2, 9)]:        # velocity nodes
+        j = node[0] + (n + 1) * (node[1] + (n + 1) * node[2])
+        got = sample.grad_at_velocity_node(L, np.array(node) / n, p)
+        ref = np.array([v[c * nn + j] for c in range(3)])
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(v).max(), node

@@ -16,6 +16,14 @@ condition).  Readings taken here:
   m_L(v) = sum over d containing v of |d| / (4 nu_d).
 * The pressure is fixed up to a constant (B^T 1 = 0 on free velocities); solutions
   are reported with zero mean pressure (plain average over the pressure nodes).
+* The diag(A)-BFBT Schur approximation of eq. (4.2):
+  S~^-1 = Z^-1 (B W^-1 A W^-1 B^T) Z^-1 with W = diag(A) and Z = B W^-1 B^T, both
+  taken on the free velocity dofs.  Z has the constant pressure in its kernel; the
+  paper solves with Z by an algebraic multigrid cycle, which this build does not
+  have: here "Z^-1 r" means a fixed number k of Jacobi-preconditioned CG steps on
+  Z y = r from y = 0 (a step whose direction has zero Z-energy, as for r = 0, has
+  step size zero).  A fixed k keeps the map deterministic; it is not linear in r,
+  so it serves inside FGMRES only.
 * Preconditioners: block diagonal, diag(V-cycle of A, diag(m)^-1), and the upper
   block-triangular one of eq. (4.1).  With S~ an approximation of the positive
   B A^-1 B^T, the inverse of [[A, B^T], [0, -S~]] is
@@ -108,6 +116,49 @@ class StokesSystem:
             return np.concatenate([a_inv(ru + self.B.T @ q), -q])
         return M
 
+    def z_operator(self) -> sp.csr_matrix:
+        """Z = B W^-1 B^T over all pressure nodes, W = diag(A) on free velocity dofs."""
+        w = self.A.diagonal()
+        return (self.B @ sp.diags(1.0 / w) @ self.B.T).tocsr()
+
+    def z_solve(self, iters: int, Z: sp.csr_matrix = None) -> Callable:
+        """r -> k steps of Jacobi-preconditioned CG on Z y = r from y = 0."""
+        Z = self.z_operator() if Z is None else Z
+        dz = Z.diagonal()
+
+        def solve(r):
+            y = np.zeros_like(r)
+            res = r.copy()
+            z = res / dz
+            p = z.copy()
+            rz = res @ z
+            for k in range(iters):
+                q = Z @ p
+                pq = p @ q
+                alpha = rz / pq if pq != 0.0 else 0.0
+                y += alpha * p
+                res -= alpha * q
+                if k == iters - 1:
+                    break
+                z = res / dz
+                rz_new = res @ z
+                p = z + (rz_new / rz if rz != 0.0 else 0.0) * p
+                rz = rz_new
+            return y
+        return solve
+
+    def bfbt(self, iters: int = 0, z_solve: Callable = None) -> Callable:
+        """S~^-1 of eq. (4.2): Z^-1 B W^-1 A W^-1 B^T Z^-1, with Z^-1 the fixed-step
+        Jacobi-CG solve (or a given z_solve, e.g. an exact one)."""
+        w = self.A.diagonal()
+        zs = z_solve or self.z_solve(iters)
+
+        def s_inv(rp):
+            y1 = zs(rp)
+            t = self.A @ ((self.B.T @ y1) / w)
+            return zs(self.B @ (t / w))
+        return s_inv
+
     def direct(self, b: np.ndarray) -> np.ndarray:
         """Exact solution with zero mean pressure: the first pressure unknown is fixed at
         zero (the constant pressure spans the kernel), the rest solved by sparse LU, and
@@ -126,8 +177,16 @@ class StokesSystem:
         return x
 
     def solve(self, b: np.ndarray, solver: str, tol: float, restart: int = 30,
-              maxit: int = 500, precond: str = "diagonal") -> mg.SolveResult:
-        M = self.precond(precond)
+              maxit: int = 500, precond: str = "diagonal", schur: str = "mass",
+              schur_iters: int = 20) -> mg.SolveResult:
+        if schur == "mass":
+            M = self.precond(precond)
+        elif schur == "bfbt":
+            if solver != "fgmres":
+                raise ValueError("the BFBT approximation is not a fixed linear map: FGMRES only")
+            M = self.precond(precond, s_inv=self.bfbt(schur_iters))
+        else:
+            raise ValueError(schur)
         if solver == "fgmres":
             res = mg.fgmres(self.K, b, M, tol, restart=restart, maxit=maxit)
         elif solver == "minres":

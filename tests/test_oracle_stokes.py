@@ -136,3 +136,70 @@ def test_triangular_preconditioner_with_exact_blocks_takes_two_steps():
     it_d = S.solve(b0, "fgmres", tol=1e-8, restart=30, maxit=2000, precond="diagonal").iterations
     it_t = S.solve(b0, "fgmres", tol=1e-8, restart=30, maxit=2000, precond="triangular").iterations
     assert it_t < it_d, (it_t, it_d)
+
+
+def _sinker_system(L, contrast=1e4):
+    from workloads import Sinkers
+    levels = mesh.hierarchy(L)
+    field = Sinkers(3, 3, radius=0.2, width=2.0 / 2 ** (L + 1), contrast=contrast)
+    nu = [field.nu(mesh.centroids_canonical(lv)) for lv in levels]
+    H = mg.build(L, nu, 3, levels=levels)
+    S = stokes.StokesSystem(H)
+    f = np.asarray(field.force(mesh.centroids_canonical(levels[L]), 3))
+    b = np.concatenate([fem.load_vector(levels[L], f, 3)[H.free[L]], np.zeros(S.np_)])
+    return S, b
+
+
+def test_bfbt_is_the_exact_schur_inverse_when_a_is_diagonal():
+    # with A = W = diag(A), eq. (4.2) gives Z^+ (B W^-1 W W^-1 B^T) Z^+ = Z^+ and the
+    # Schur complement B A^-1 B^T is Z itself: BFBT is exact, and the block-triangular
+    # preconditioner with exact blocks makes K Q^-1 unipotent (two GMRES steps)
+    import scipy.sparse as sp
+    S, b = _sinker_system(2)
+    S.A = sp.diags(S.A.diagonal()).tocsr()
+    S.K = sp.bmat([[S.A, S.B.T], [S.B, None]]).tocsr()
+    Z = S.z_operator().toarray()
+    Zp = np.linalg.pinv(Z)
+    s_inv = S.bfbt(z_solve=lambda r: Zp @ r)
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal(S.np_)
+    assert np.allclose(s_inv(r), Zp @ r, rtol=0, atol=1e-10 * np.abs(Zp @ r).max())
+    w = S.A.diagonal()
+    M = S.precond("triangular", a_inv=lambda ru: ru / w, s_inv=s_inv)
+    res = mg.fgmres(S.K, b, M, 1e-10, restart=10, maxit=10)
+    assert res.converged and res.iterations <= 2, res.iterations
+
+
+def test_z_solve_fixed_steps():
+    S, _ = _sinker_system(2)
+    Z = S.z_operator()
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(S.np_)
+    r -= r.mean()                      # the range of Z: B^T 1 = 0, so Z 1 = 0
+    # Jacobi-preconditioned CG on the 125 pressure nodes (condition number about 900 on
+    # the range): 50 steps solve it to rounding (steps beyond convergence only add noise)
+    y = S.z_solve(50, Z)(r)
+    assert np.linalg.norm(Z @ y - r) <= 1e-8 * np.linalg.norm(r)
+    # fewer steps reduce the residual, monotonically in the Z-energy of the error
+    yp = np.linalg.pinv(Z.toarray()) @ r
+    errs = []
+    for k in (1, 4, 16):
+        e = S.z_solve(k, Z)(r) - yp
+        errs.append(float(e @ (Z @ e)))
+    assert errs[0] > errs[1] > errs[2]
+    # a zero right-hand side (the pressure part of FGMRES's first vector) gives zero
+    assert np.array_equal(S.z_solve(5, Z)(np.zeros(S.np_)), np.zeros(S.np_))
+
+
+def test_bfbt_beats_the_lumped_mass_at_high_contrast():
+    # the reason eq. (4.2) is used: with sharp viscosity jumps the 1/nu lumped mass is a
+    # poor Schur approximation; BFBT (with 20-step Z solves) needs far fewer iterations
+    S, b = _sinker_system(3, contrast=1e6)
+    its = {}
+    for schur in ("mass", "bfbt"):
+        res = S.solve(b, "fgmres", tol=1e-8, restart=50, maxit=2000, precond="triangular",
+                      schur=schur, schur_iters=20)
+        assert res.converged
+        its[schur] = res.iterations
+    print(its)
+    assert its["bfbt"] < 0.5 * its["mass"], its

@@ -264,6 +264,15 @@ typedef enum { AGCA_STOKES_FGMRES = 0, AGCA_STOKES_MINRES = 1 } agca_stokes_solv
  *              positive B A^-1 B^T (the sign of the pressure block for which exact
  *              blocks make the preconditioned matrix unipotent); FGMRES only. */
 typedef enum { AGCA_STOKES_DIAGONAL = 0, AGCA_STOKES_TRIANGULAR = 1 } agca_stokes_precond;
+/* The Schur approximation S in either preconditioner:
+ * MASS : S = diag(m), the 1/nu-weighted lumped pressure mass.
+ * BFBT : the diag(A)-BFBT least-squares commutator of eq. (4.2),
+ *        S^-1 = Z^-1 (B W^-1 A W^-1 B^T) Z^-1, W = diag(A), Z = B W^-1 B^T, where each
+ *        Z^-1 is schur_iters steps of Jacobi-preconditioned CG on Z from zero (a step
+ *        of zero Z-energy has step size zero).  diag(Z) is formed exactly at the first
+ *        solve after every coefficient rebuild (27 products with Z, one per colour of
+ *        the nodes by coordinates mod 3).  Not linear in r: FGMRES only. */
+typedef enum { AGCA_SCHUR_MASS = 0, AGCA_SCHUR_BFBT = 1 } agca_stokes_schur;
 typedef struct {
     int32_t solver;          /* agca_stokes_solver                                          */
     int32_t restart;         /* FGMRES restart length, 1..510                              */
@@ -271,16 +280,20 @@ typedef struct {
     int32_t record_history;
     double tol;              /* stop when ||r||_2 <= tol ||(f, g)||_2 (eq. (4.3))           */
     int32_t precond;         /* agca_stokes_precond                                         */
+    int32_t schur;           /* agca_stokes_schur                                           */
+    int32_t schur_iters;     /* BFBT: CG steps per Z solve, 1..1000 (ignored for MASS)      */
 } agca_stokes_opts;
 
 /* Solve [[A, B^T], [B, 0]] (u, p) = (f, g) in FP64 with a block preconditioner built
- * from one AGCA V-cycle of A and diag(m) (opts->precond): FGMRES(restart), right
- * preconditioned with modified Gram-Schmidt (any mg_dtype: the FP32 V-cycle makes the
+ * from one AGCA V-cycle of A and a Schur approximation (opts->precond, opts->schur):
+ * FGMRES(restart), right preconditioned, classical Gram-Schmidt with a second pass where
+ * the first loses more than 90 % of the norm (any mg_dtype: the FP32 V-cycle makes the
  * preconditioner non-linear), or MINRES with the block-diagonal one (its theory needs a
  * fixed SPD preconditioner, which the FP32 V-cycle is only up to FP32 rounding; the true
  * residual is checked every step, so a run that stagnates reports AGCA_E_NOCONV, never a
  * false convergence).  The returned p has zero mean over the pressure nodes.  Work
- * space: 2 restart + 5 (FGMRES; one more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy.
+ * space: 2 restart + 5 (FGMRES; one more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy;
+ * BFBT adds 3 velocity and 8 pressure vectors.
  * FGMRES stops early with stats->floor_limited when the true residual after a restart
  * cycle is within 10x of tol and less than 5 % below its value four cycles earlier (the
  * rounding floor of an FP64 iterate).

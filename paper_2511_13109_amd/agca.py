@@ -300,10 +300,15 @@ class Stokes:
 
     def solve(self, f: torch.Tensor, g: Optional[torch.Tensor] = None, solver: str = "fgmres",
               restart: int = 30, tol: float = 1e-8, max_iter: int = 1000, record_history: bool = True,
-              raise_on_noconv: bool = True, precond: str = "diagonal"):
+              raise_on_noconv: bool = True, precond: str = "diagonal", schur: str = "mass",
+              schur_iters: int = 20):
+        """schur: 'mass' (1/nu lumped mass) or 'bfbt' (eq. (4.2), FGMRES only, each Z solve
+        schur_iters Jacobi-CG steps)."""
         opts = _lib.StokesOpts()
         opts.solver = {"fgmres": _lib.STOKES_FGMRES, "minres": _lib.STOKES_MINRES}[solver]
         opts.precond = {"diagonal": _lib.STOKES_DIAGONAL, "triangular": _lib.STOKES_TRIANGULAR}[precond]
+        opts.schur = {"mass": _lib.SCHUR_MASS, "bfbt": _lib.SCHUR_BFBT}[schur]
+        opts.schur_iters = schur_iters
         opts.restart, opts.max_iter, opts.tol = restart, max_iter, tol
         opts.record_history = 1 if record_history else 0
         g = self.pvec() if g is None else g

@@ -85,6 +85,9 @@ struct agca_hier {
     double* st_qf = nullptr;     // fine-level scalar scratch (fine divergence)
     double* st_work = nullptr;   // Krylov vectors, st_work_vecs of them
     double* st_tri = nullptr;    // during a triangular-preconditioned solve: one Stokes vector
+    double* st_bfbt = nullptr;   // BFBT Schur approximation: W^-1, diag(Z) and work vectors
+    int64_t bfbt_version = -1;   // nu_version diag(Z) was formed for
+    int st_schur_iters = 0;      // during a BFBT-preconditioned solve: CG steps per Z solve
     double* st_gs = nullptr;     // Gram-Schmidt partial sums, st_gs_cap doubles
     int64_t st_gs_cap = 0;
     int64_t st_work_vecs = 0;
@@ -1421,19 +1424,116 @@ static int32_t stokes_apply(agca_hier* h, const double* x, double* y) {
     TRY(stokes_div(h, x, y + d.nu));
     return AGCA_OK;
 }
-// z = diag(V-cycle, mass^-1) r, or with the upper block-triangular preconditioner of
-// eq. (4.1), z = [[V, V B^T S^-1], [0, -S^-1]] r with S = diag(mass) approximating the
-// positive B A^-1 B^T: q = r_p / m, z_u = V(r_u + B^T q), z_p = -q.
+// ---------------------------------------------------------------------------
+// diag(A)-BFBT Schur approximation (eq. (4.2)): S^-1 = Z^-1 (B W^-1 A W^-1 B^T) Z^-1,
+// W = diag(A) on the free velocity dofs, Z = B W^-1 B^T on the pressure nodes.  Z has
+// the constant pressure in its kernel; Z^-1 is a fixed number of Jacobi-preconditioned
+// CG steps from zero (the paper uses an algebraic multigrid cycle there).
+// ---------------------------------------------------------------------------
+struct Bfbt {
+    double *winv, *v1, *v2;                            // velocity vectors
+    double *zdiag, *y1, *y2, *zr, *zz, *zp, *zq, *ztmp;  // pressure vectors
+    double* zred;                                      // CG scalars (device)
+};
+static Bfbt bfbt_bufs(agca_hier* h) {
+    const StokesDims d = stokes_dims(h);
+    Bfbt w;
+    double* p = h->st_bfbt;
+    for (double** v : {&w.winv, &w.v1, &w.v2}) { *v = p; p += d.nu; }
+    for (double** v : {&w.zdiag, &w.y1, &w.y2, &w.zr, &w.zz, &w.zp, &w.zq, &w.ztmp}) { *v = p; p += d.np; }
+    w.zred = p;
+    return w;
+}
+// out = Z y = B (W^-1 (B^T y))
+static int32_t z_apply(agca_hier* h, const Bfbt& w, const double* y, double* out) {
+    const StokesDims d = stokes_dims(h);
+    HIPCHK(h, launch_fill<double>(d.nu, 0.0, w.v1, h->st));
+    TRY(stokes_grad_add(h, y, w.v1));
+    HIPCHK(h, launch_mul_elementwise(d.nu, w.v1, w.winv, w.v1, h->st));
+    TRY(stokes_div(h, w.v1, out));
+    return AGCA_OK;
+}
+// W^-1 (0 on boundary velocity dofs) and diag(Z), once per coefficient rebuild.  Two
+// pressure nodes of one colour (coordinates equal mod 3) are at least 3 pressure cells
+// apart, while B^T e_k lives on the velocity nodes within one pressure cell of node k:
+// Z_km = 0 for distinct k, m of one colour, so Z applied to a colour's indicator holds
+// Z_kk on that colour's nodes.
+static int32_t bfbt_ready(agca_hier* h) {
+    const StokesDims d = stokes_dims(h);
+    if (!h->st_bfbt) TRY(alloc_t(h, &h->st_bfbt, (size_t)(3 * d.nu + 8 * d.np + 8)));
+    if (h->bfbt_version == h->nu_version) return AGCA_OK;
+    const Bfbt w = bfbt_bufs(h);
+    HIPCHK(h, launch_invert_diag<double>(d.nu, h->lv[h->cfg.L].diag, w.winv, h->st));
+    for (int c = 0; c < 27; ++c) {
+        HIPCHK(h, launch_colour(d.nc, c, 0, nullptr, w.ztmp, h->st));
+        TRY(z_apply(h, w, w.ztmp, w.zq));
+        HIPCHK(h, launch_colour(d.nc, c, 1, w.zq, w.zdiag, h->st));
+    }
+    h->bfbt_version = h->nu_version;
+    return AGCA_OK;
+}
+// y = iters steps of Jacobi-preconditioned CG on Z y = r from y = 0.  The scalars stay
+// on the device: r.z alternates between zred[0] and zred[1], p.q is zred[2]; a step of
+// zero Z-energy (r = 0) has step size zero (the update kernels' guards).
+static int32_t z_solve(agca_hier* h, const Bfbt& w, const double* r, double* y, int iters) {
+    const int64_t np = stokes_dims(h).np;
+    const int nb = h->nb_partial;
+    HIPCHK(h, launch_fill<double>(np, 0.0, y, h->st));
+    HIPCHK(h, launch_axpby<double>(np, 1.0, r, 0.0, w.zr, h->st));
+    HIPCHK(h, launch_div_elementwise(np, w.zr, w.zdiag, w.zz, h->st));
+    HIPCHK(h, launch_dot2<double>(np, w.zz, w.zr, nullptr, h->partial, nb, h->st));
+    HIPCHK(h, launch_sum_partials(h->partial, nb, w.zred, h->st));
+    HIPCHK(h, launch_axpby<double>(np, 1.0, w.zz, 0.0, w.zp, h->st));
+    int cur = 0;
+    for (int k = 0; k < iters; ++k) {
+        TRY(z_apply(h, w, w.zp, w.zq));
+        HIPCHK(h, launch_dot2<double>(np, w.zp, w.zq, nullptr, h->partial, nb, h->st));
+        HIPCHK(h, launch_sum_partials(h->partial, nb, w.zred + 2, h->st));
+        HIPCHK(h, launch_cg_update(np, w.zred + cur, w.zred + 2, w.zp, w.zq, y, w.zr, nullptr,
+                                   h->partial, nb, h->st));
+        if (k == iters - 1) break;
+        HIPCHK(h, launch_div_elementwise(np, w.zr, w.zdiag, w.zz, h->st));
+        HIPCHK(h, launch_dot2<double>(np, w.zz, w.zr, nullptr, h->partial, nb, h->st));
+        HIPCHK(h, launch_sum_partials(h->partial, nb, w.zred + (1 - cur), h->st));
+        HIPCHK(h, launch_zpbp_dev<double>(np, w.zz, w.zred + (1 - cur), w.zred + cur, 1.0, w.zp, h->st));
+        cur = 1 - cur;
+    }
+    return AGCA_OK;
+}
+// q = S^-1 rp, S the BFBT approximation
+static int32_t bfbt_apply(agca_hier* h, const double* rp, double* q, int iters) {
+    const StokesDims d = stokes_dims(h);
+    const Bfbt w = bfbt_bufs(h);
+    TRY(z_solve(h, w, rp, w.y1, iters));
+    HIPCHK(h, launch_fill<double>(d.nu, 0.0, w.v2, h->st));
+    TRY(stokes_grad_add(h, w.y1, w.v2));
+    HIPCHK(h, launch_mul_elementwise(d.nu, w.v2, w.winv, w.v2, h->st));
+    TRY(do_cube<double>(h, h->cfg.L, MODE_APPLY, w.v2, nullptr, w.v1, 0.0));
+    HIPCHK(h, launch_mul_elementwise(d.nu, w.v1, w.winv, w.v1, h->st));
+    TRY(stokes_div(h, w.v1, w.y2));
+    TRY(z_solve(h, w, w.y2, q, iters));
+    return AGCA_OK;
+}
+// q = S^-1 rp: the lumped 1/nu mass, or BFBT during a solve that asked for it
+static int32_t schur_inv(agca_hier* h, const double* rp, double* q) {
+    if (h->st_schur_iters > 0) return bfbt_apply(h, rp, q, h->st_schur_iters);
+    HIPCHK(h, launch_div_elementwise(stokes_dims(h).np, rp, h->st_mass, q, h->st));
+    return AGCA_OK;
+}
+
+// z = diag(V-cycle, S^-1) r, or with the upper block-triangular preconditioner of
+// eq. (4.1), z = [[V, V B^T S^-1], [0, -S^-1]] r with S approximating the positive
+// B A^-1 B^T (diag(mass) or BFBT): q = S^-1 r_p, z_u = V(r_u + B^T q), z_p = -q.
 static int32_t stokes_precond(agca_hier* h, const double* r, double* z) {
     const StokesDims d = stokes_dims(h);
     if (!h->st_tri) {
         TRY(precondition(h, r, z));
-        HIPCHK(h, launch_div_elementwise(d.np, r + d.nu, h->st_mass, z + d.nu, h->st));
+        TRY(schur_inv(h, r + d.nu, z + d.nu));
         return AGCA_OK;
     }
     double* tu = h->st_tri;
     double* q = tu + d.nu;
-    HIPCHK(h, launch_div_elementwise(d.np, r + d.nu, h->st_mass, q, h->st));
+    TRY(schur_inv(h, r + d.nu, q));
     HIPCHK(h, launch_axpby<double>(d.nu, 1.0, r, 0.0, tu, h->st));
     TRY(stokes_grad_add(h, q, tu));
     TRY(precondition(h, tu, z));
@@ -1682,6 +1782,13 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
         return fail(AGCA_E_INVALID, "unknown Stokes preconditioner");
     if (o->precond == AGCA_STOKES_TRIANGULAR && o->solver != AGCA_STOKES_FGMRES)
         return fail(AGCA_E_INVALID, "the triangular preconditioner is not symmetric: FGMRES only");
+    if (o->schur != AGCA_SCHUR_MASS && o->schur != AGCA_SCHUR_BFBT)
+        return fail(AGCA_E_INVALID, "unknown Schur approximation");
+    const bool bfbt = o->schur == AGCA_SCHUR_BFBT;
+    if (bfbt && (o->schur_iters < 1 || o->schur_iters > 1000))
+        return fail(AGCA_E_INVALID, "schur_iters must be in [1, 1000]");
+    if (bfbt && o->solver != AGCA_STOKES_FGMRES)
+        return fail(AGCA_E_INVALID, "the BFBT approximation is not a fixed linear map: FGMRES only");
     TRY(ensure_solver_vectors(h));
     std::memset(stats, 0, sizeof(*stats));
     const StokesDims d = stokes_dims(h);
@@ -1692,6 +1799,9 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     double* bvec = h->st_work + kry * d.tot;
     double* xvec = bvec + d.tot;
     h->st_tri = tri ? xvec + d.tot : nullptr;
+    h->st_schur_iters = 0;
+    if (bfbt) TRY(bfbt_ready(h));
+    h->st_schur_iters = bfbt ? o->schur_iters : 0;
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(h, hipMemcpyAsync(bvec, f, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, h->st));
     HIPCHK(h, launch_zero_boundary<double>(3, d.nf, bvec, h->st));
@@ -1711,9 +1821,11 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
                                ? stokes_fgmres(h, o, bvec, xvec, bn, &rel, &it, hist, &floor_limited)
                                : stokes_minres(h, o, bvec, xvec, bn, &rel, &it, hist);
         h->st_tri = nullptr;
+        h->st_schur_iters = 0;
         if (rc != AGCA_OK) return rc;
     }
     h->st_tri = nullptr;
+    h->st_schur_iters = 0;
     // pressure with zero mean (the constant is the kernel of B^T on free velocities)
     double psum = 0.0;
     {

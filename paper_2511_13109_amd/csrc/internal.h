@@ -188,6 +188,11 @@ hipError_t launch_stokes_grad_fine_add(int n, const double* pf, double* out, hip
 hipError_t launch_stokes_mass_fine(int n, const double* nu, double* mf, hipStream_t st);
 hipError_t launch_restrict_all(int n_coarse, const double* qf, double* out, hipStream_t st);
 hipError_t launch_prolong_all(int n_fine, const double* pc, double* pf, hipStream_t st);
+hipError_t launch_mul_elementwise(int64_t n, const double* a, const double* b, double* out,
+                                  hipStream_t st);
+// 27-colouring of a level's nodes by (x mod 3, y mod 3, z mod 3): mode 0 writes the
+// colour's indicator, mode 1 copies src into out on the colour's nodes only
+hipError_t launch_colour(int n, int colour, int mode, const double* src, double* out, hipStream_t st);
 hipError_t launch_div_elementwise(int64_t n, const double* num, const double* den, double* out,
                                   hipStream_t st);
 hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,

@@ -184,6 +184,32 @@ k_div_elementwise(int64_t n, const double* __restrict__ num, const double* __res
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) out[i] = num[i] / den[i];
 }
 
+// out = a * b elementwise
+__global__ void __launch_bounds__(NT)
+k_mul_elementwise(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                  double* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) out[i] = a[i] * b[i];
+}
+
+// Colour (x mod 3) + 3 (y mod 3) + 9 (z mod 3) of the nodes of a level with n cells per
+// axis.  mode 0: out = indicator of the colour; mode 1: out = src on the colour's nodes
+// (others untouched).
+__global__ void __launch_bounds__(NT)
+k_colour(int n, int colour, int mode, const double* __restrict__ src, double* __restrict__ out) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x; p < N; p += stride) {
+        int x, y, z;
+        node_coords(p, n, x, y, z);
+        const bool on = (x % 3) + 3 * (y % 3) + 9 * (z % 3) == colour;
+        if (mode == 0)
+            out[p] = on ? 1.0 : 0.0;
+        else if (on)
+            out[p] = src[p];
+    }
+}
+
 // y += sign * coef[0] * x with the coefficient read from device memory
 __global__ void __launch_bounds__(NT)
 k_axpy_dev(int64_t n, const double* __restrict__ coef, double sign, const double* __restrict__ x,
@@ -317,6 +343,21 @@ hipError_t launch_div_elementwise(int64_t n, const double* num, const double* de
                                   hipStream_t st) {
     if (!num || !den || !out) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_div_elementwise, dim3(grid_stride(n)), dim3(NT), 0, st, n, num, den, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mul_elementwise(int64_t n, const double* a, const double* b, double* out,
+                                  hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (!a || !b || !out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mul_elementwise, dim3(grid_stride(n)), dim3(NT), 0, st, n, a, b, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_colour(int n, int colour, int mode, const double* src, double* out, hipStream_t st) {
+    if (n < 1 || colour < 0 || colour > 26 || !out || (mode == 1 && !src)) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_colour, dim3(grid_stride(N)), dim3(NT), 0, st, n, colour, mode, src, out);
     return hipGetLastError();
 }
 int gs_blocks(int64_t n) { return (int)((n + GS_CHUNK - 1) / GS_CHUNK); }

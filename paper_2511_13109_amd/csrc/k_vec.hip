@@ -160,7 +160,8 @@ k_cg_update(int64_t n, const double* __restrict__ rz, const double* __restrict__
             const double* __restrict__ p, const double* __restrict__ q,
             double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
             double* __restrict__ partial) {
-    const double alpha = rz[0] / pq[0];
+    // a direction of zero energy (p = 0) takes no step; the caller tests p . q
+    const double alpha = pq[0] != 0.0 ? rz[0] / pq[0] : 0.0;
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * NT;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride) {
@@ -194,7 +195,7 @@ template <typename Z>
 __global__ void __launch_bounds__(NT)
 k_zpbp_dev(int64_t n, const Z* __restrict__ z, const double* __restrict__ num,
            const double* __restrict__ den, double sign, double* __restrict__ p) {
-    const double beta = sign * num[0] / den[0];
+    const double beta = den[0] != 0.0 ? sign * num[0] / den[0] : 0.0;
     const int64_t stride = (int64_t)gridDim.x * NT;
     for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += stride)
         p[i] = (double)z[i] + beta * p[i];

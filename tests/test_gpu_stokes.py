@@ -130,6 +130,39 @@ def test_triangular_preconditioner(case, mg_dtype):
         G.solve(_dev(fu), solver="minres", tol=tol, precond="triangular")
 
 
+@pytest.mark.parametrize("mg_dtype", ["f64", "f32"])
+def test_bfbt_schur_approximation(case, mg_dtype):
+    # eq. (4.2) with 20-step Jacobi-CG Z solves, in both preconditioners: FP64 V-cycle
+    # against the oracle's FGMRES (history prefix, iteration count), FP32 V-cycle by its
+    # residual recomputed by the oracle
+    L, levels, H, S, fu, GS, GS32 = case
+    G = GS if mg_dtype == "f64" else GS32
+    b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
+    tol = 1e-9 if mg_dtype == "f64" else 1e-8
+    for precond in ("triangular", "diagonal"):
+        u, p, st = G.solve(_dev(fu), solver="fgmres", restart=30, tol=tol, max_iter=3000,
+                           precond=precond, schur="bfbt", schur_iters=20)
+        print(f"[fgmres {precond} BFBT {mg_dtype} L={L}] {st['iterations']} it", flush=True)
+        assert st["converged"] and st["rel_residual"] <= tol
+        xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
+        assert np.linalg.norm(b - S.K @ xg) <= 1.0001 * tol * np.linalg.norm(b)
+        if mg_dtype == "f64":
+            ref = S.solve(b, "fgmres", tol=tol, restart=30, maxit=3000, precond=precond,
+                          schur="bfbt", schur_iters=20)
+            assert ref.converged
+            k = min(len(st["history"]), len(ref.history), 20)
+            assert np.allclose(st["history"][:k], ref.history[:k], rtol=1e-6, atol=1e-14)
+            assert abs(st["iterations"] - ref.iterations) <= max(1, int(0.05 * ref.iterations))
+    if mg_dtype == "f64":
+        _, _, sm = G.solve(_dev(fu), solver="fgmres", restart=30, tol=tol, max_iter=3000,
+                           precond="triangular")
+        print(f"[fgmres triangular mass L={L}] {sm['iterations']} it", flush=True)
+    with pytest.raises(Exception):
+        G.solve(_dev(fu), solver="minres", tol=tol, schur="bfbt")
+    with pytest.raises(Exception):
+        G.solve(_dev(fu), solver="fgmres", tol=tol, schur="bfbt", schur_iters=0)
+
+
 def test_fgmres_below_the_rounding_floor_stays_finite(case):
     # asking for 1e-14 drives the Arnoldi process into near-dependent vectors (the
     # classical Gram-Schmidt second pass runs there); the solve must stay finite and

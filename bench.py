@@ -408,8 +408,9 @@ def report_large(args, dev) -> dict:
 
 def report_stokes(args, dev) -> dict:
     """Generalized Stokes, velocity 257^3 / pressure 129^3, 16 sinkers: FGMRES with the
-    upper block-triangular preconditioner (eq. (4.1)) and MINRES with the block-diagonal
-    one, each with the FP32 V-cycle against the FP64 V-cycle, to 1e-8."""
+    upper block-triangular preconditioner (eq. (4.1)) and the BFBT Schur approximation
+    (eq. (4.2)) or the 1/nu lumped mass, and MINRES with the block-diagonal one (lumped
+    mass), each with the FP32 V-cycle against the FP64 V-cycle, to 1e-8."""
     import torch
     from paper_2511_13109_amd import Hierarchy, Stokes
     from workloads import workload
@@ -419,21 +420,27 @@ def report_stokes(args, dev) -> dict:
     nus, f = device_inputs(w, dev)
     out = {"report": w.name, "description": w.description,
            "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3,
-           "fgmres_restart": args.stokes_restart, "smoother": args.smoother}
-    runs = [r for r in (("f32", "fgmres", "triangular"), ("f64", "fgmres", "triangular"),
-                        ("f32", "minres", "diagonal"), ("f64", "minres", "diagonal"))
-            if r[1] in args.stokes_solvers.split(",")]
-    for mg, solver, pc in runs:
+           "fgmres_restart": args.stokes_restart, "smoother": args.smoother,
+           "bfbt_z_cg_steps": args.schur_iters}
+    runs = [r for r in (("bfbt", "f32", "fgmres", "triangular", "bfbt"),
+                        ("bfbt", "f64", "fgmres", "triangular", "bfbt"),
+                        ("fgmres", "f32", "fgmres", "triangular", "mass"),
+                        ("fgmres", "f64", "fgmres", "triangular", "mass"),
+                        ("minres", "f32", "minres", "diagonal", "mass"),
+                        ("minres", "f64", "minres", "diagonal", "mass"))
+            if r[0] in args.stokes_solvers.split(",")]
+    for _, mg, solver, pc, schur in runs:
         H = Hierarchy(L, 3, nus[L], nus[:L], mg_dtype=mg, mg_nu_dtype=("bf16" if mg == "f32" else "f64"),
                       smoother=args.smoother)
         S = Stokes(H)
         fu = H.load_vector(f)
         _, _, st = S.solve(fu, solver=solver, restart=args.stokes_restart, tol=w.tol,
                            max_iter=args.stokes_max_iter, record_history=False, raise_on_noconv=False,
-                           precond=pc)
-        out[f"{solver}_{pc}_{mg}_mg"] = {k: st[k] for k in ("iterations", "seconds", "rel_residual",
-                                                              "converged", "floor_limited")}
-        print(f"[stokes] {solver} {pc} {mg}-MG: {st['iterations']} it {st['seconds']:.2f} s "
+                           precond=pc, schur=schur, schur_iters=args.schur_iters)
+        key = f"{solver}_{pc}" + ("_bfbt" if schur == "bfbt" else "") + f"_{mg}_mg"
+        out[key] = {k: st[k] for k in ("iterations", "seconds", "rel_residual", "converged",
+                                       "floor_limited")}
+        print(f"[stokes] {solver} {pc} {schur} {mg}-MG: {st['iterations']} it {st['seconds']:.2f} s "
               f"res {st['rel_residual']:.2e}", file=sys.stderr, flush=True)
         H.close()
         torch.cuda.empty_cache()
@@ -585,7 +592,10 @@ def main():
     ap.add_argument("--level", type=int, default=None, help="finest level of a report workload")
     ap.add_argument("--stokes-max-iter", type=int, default=8000)
     ap.add_argument("--stokes-solvers", default="fgmres,minres",
-                    help="comma-separated subset of fgmres (triangular) and minres (diagonal)")
+                    help="comma-separated subset of bfbt (FGMRES, triangular, BFBT), fgmres "
+                         "(triangular, lumped mass) and minres (diagonal, lumped mass)")
+    ap.add_argument("--schur-iters", type=int, default=20,
+                    help="Jacobi-CG steps per Z solve of the BFBT Schur approximation")
     ap.add_argument("--stokes-restart", type=int, default=126)
     args = ap.parse_args()
     if args.summarize_profile:

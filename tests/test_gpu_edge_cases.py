@@ -1,7 +1,8 @@
 """Degenerate and boundary cases of the GPU path through the C ABI: the smallest
 hierarchy (L = 1: 5^3 nodes, one free node on level 0), a zero right-hand side, a
 start at the exact solution, a zero iteration budget, a constant coefficient (no
-flags; DCA equals Galerkin coarsening), and a zero Stokes right-hand side.
+flags; DCA equals Galerkin coarsening), a zero Stokes right-hand side (every
+preconditioner, BFBT included), and BFBT on the smallest Stokes hierarchy.
 """
 
 import numpy as np
@@ -108,9 +109,43 @@ def test_stokes_zero_rhs():
     try:
         S = Stokes(G)
         f = torch.zeros(3 * (levels[L].n + 1) ** 3, dtype=torch.float64, device="cuda")
-        for solver, pc in (("fgmres", "diagonal"), ("fgmres", "triangular"), ("minres", "diagonal")):
-            u, p, st = S.solve(f, solver=solver, precond=pc, tol=1e-8)
+        for solver, pc, schur in (("fgmres", "diagonal", "mass"), ("fgmres", "triangular", "mass"),
+                                  ("minres", "diagonal", "mass"), ("fgmres", "triangular", "bfbt")):
+            u, p, st = S.solve(f, solver=solver, precond=pc, tol=1e-8, schur=schur)
             assert st["converged"] and st["iterations"] == 0
             assert float(u.abs().max()) == 0.0 and float(p.abs().max()) == 0.0
+    finally:
+        G.close()
+
+
+def test_stokes_smallest_hierarchy_bfbt():
+    # L = 2 (the smallest Stokes hierarchy: 9^3 velocity, 5^3 pressure nodes), BFBT with
+    # one and with 20 CG steps per Z solve, against the oracle's FGMRES
+    from oracle import stokes
+    from paper_2511_13109_amd import Hierarchy, Stokes
+    L = 2
+    levels = mesh.hierarchy(L)
+    nu_h = [_sinker_nu(mesh.centroids_canonical(lv)) for lv in levels]
+    H = mg.build(L, nu_h, 3, levels=levels)
+    S = stokes.StokesSystem(H)
+    from workloads import Sinkers
+    f = np.asarray(Sinkers(2, 7, radius=0.2, width=0.05, contrast=1e4).force(
+        mesh.centroids_canonical(levels[L]), 3))
+    fu = fem.load_vector(levels[L], f, 3)
+    b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
+    G = Hierarchy(L, 3, _dev(nu_h[L]), [_dev(v) for v in nu_h[:L]])
+    try:
+        for k in (1, 20):
+            u, p, st = Stokes(G).solve(_dev(fu), solver="fgmres", restart=20, tol=1e-10,
+                                       max_iter=500, precond="triangular", schur="bfbt",
+                                       schur_iters=k)
+            ref = S.solve(b, "fgmres", tol=1e-10, restart=20, maxit=500, precond="triangular",
+                          schur="bfbt", schur_iters=k)
+            assert st["converged"] and ref.converged
+            n = min(len(st["history"]), len(ref.history), 15)
+            assert np.allclose(st["history"][:n], ref.history[:n], rtol=1e-6, atol=1e-14), k
+            assert abs(st["iterations"] - ref.iterations) <= 1, (k, st["iterations"], ref.iterations)
+            xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
+            assert np.linalg.norm(b - S.K @ xg) <= 1.0001e-10 * np.linalg.norm(b)
     finally:
         G.close()

@@ -662,8 +662,8 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
             return AGCA_OK;
         };
         auto release = [&]() {
-            hipStreamSynchronize(h->st);
-            for (void* p : tmp) hipFree(p);
+            (void)hipStreamSynchronize(h->st);
+            for (void* p : tmp) (void)hipFree(p);
             tmp.clear();
         };
         uint64_t macro_bits = 0;
@@ -788,7 +788,7 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
                     rc = fail(AGCA_E_HIP, std::string("Galerkin kernels: ") + hipGetErrorString(e));
                 }
             }
-            for (void* p : tmp) hipFree(p);
+            for (void* p : tmp) (void)hipFree(p);
             h->trans[0] = h->trans[1] = nullptr;
             if (rc != AGCA_OK) return rc;
         }
@@ -827,11 +827,13 @@ int32_t build_operators(agca_hier* h, const double* nu_fine, const double* const
     return AGCA_OK;
 }
 
+// Teardown and re-allocation paths release memory on a best-effort basis: an error
+// reported by hipFree there leaves nothing for the caller to act on, so it is dropped.
 void free_all(agca_hier* h) {
-    if (h->st) hipStreamSynchronize(h->st);
-    for (void* p : h->allocs) hipFree(p);
+    if (h->st) (void)hipStreamSynchronize(h->st);
+    for (void* p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
-    if (h->red_host) hipHostFree(h->red_host);
+    if (h->red_host) (void)hipHostFree(h->red_host);
     h->red_host = nullptr;
 }
 
@@ -842,7 +844,7 @@ int32_t free_blocks(agca_hier* h) {
             if (!p) continue;
             for (size_t i = 0; i < h->allocs.size(); ++i)
                 if (h->allocs[i] == p) {
-                    hipFree(p);
+                    (void)hipFree(p);
                     h->allocs.erase(h->allocs.begin() + i);
                     break;
                 }
@@ -887,7 +889,7 @@ int32_t agca_macro_gradient(int32_t L, const double* eta_nodes, double* gmax, vo
     if (e == hipSuccess) e = launch_macro_grad_max(L, eta_nodes, d, st);
     if (e == hipSuccess) e = hipMemcpyAsync(bits, d, sizeof(bits), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(d);
+    (void)hipFree(d);
     if (e != hipSuccess) return fail(AGCA_E_HIP, std::string("macro gradient: ") + hipGetErrorString(e));
     for (int k = 0; k < 48; ++k) {
         double v;
@@ -1389,7 +1391,7 @@ static int32_t stokes_work(agca_hier* h, int64_t vecs) {
     if (h->st_work) {
         for (size_t i = 0; i < h->allocs.size(); ++i)
             if (h->allocs[i] == h->st_work) {
-                hipFree(h->st_work);
+                (void)hipFree(h->st_work);
                 h->allocs.erase(h->allocs.begin() + i);
                 h->bytes -= h->st_work_vecs * stokes_dims(h).tot * (int64_t)sizeof(double);
                 break;
@@ -1586,7 +1588,7 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
     if (h->st_gs_cap < (int64_t)(m + 2) * nb) {
         for (size_t i = 0; h->st_gs && i < h->allocs.size(); ++i)
             if (h->allocs[i] == h->st_gs) {
-                hipFree(h->st_gs);
+                (void)hipFree(h->st_gs);
                 h->allocs.erase(h->allocs.begin() + i);
                 h->bytes -= h->st_gs_cap * (int64_t)sizeof(double);
                 break;

@@ -1,7 +1,7 @@
 """Benchmark of the AGCA multigrid hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-    python bench.py --workload sinker513|stokes257|adjoint129|coarsening [--level L]
+    python bench.py --workload sinker513|stokes257|adjoint129|coarsening|roofline [--level L]
                                                             (report lines)
 
 Workload (default): the vector viscous block -div(2 nu eps(u)) = f on 129^3
@@ -489,6 +489,72 @@ def report_adjoint(args, dev) -> dict:
     return out
 
 
+def report_roofline(args, dev) -> dict:
+    """Apply roofline sweep: the scalar and the vector fine-grid apply at 129^3, 257^3 and
+    513^3 nodes (the 513^3 workload's coefficient generator, 64 sinkers) in FP64, FP32
+    with an FP32 coefficient and FP32 with a BF16 coefficient; u ~ N(0, 1) (seed 0) on
+    the free DoFs.  Median of 20 HIP-event timings after 3 warm-ups, with the Infinity
+    Cache flushed before each (cold) and without (warm)."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy
+    from workloads import workload
+    from workloads.device import device_inputs
+    levels = [int(v) for v in args.roofline_levels.split(",")]
+    flush = torch.ones(512 * 1024 * 1024 // 8, dtype=torch.float64, device=dev)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def timed(H, L, u, v, cold):
+        for _ in range(3):
+            H.apply(L, u, v)
+        ts = []
+        for _ in range(20):
+            if cold:
+                sink.add_(flush.sum())
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            H.apply(L, u, v)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        return float(np.median(ts))
+
+    rows = []
+    for L in levels:
+        w = workload("sinker513", L=L)
+        nus, f = device_inputs(w, dev)
+        del f
+        n = 2 ** (L + 1)
+        N = (n + 1) ** 3
+        gen = torch.Generator(device=dev).manual_seed(0)
+        for nc in (1, 3):
+            free = nc * (n - 1) ** 3
+            u = torch.randn(nc * N, generator=gen, device=dev, dtype=torch.float64)
+            v = torch.empty_like(u)
+            for nu_dt in ("f32", "bf16"):
+                H = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype=nu_dt)
+                cases = [("f64", u, v, 8, 8)] if nu_dt == "f32" else []
+                u32 = u.float()
+                cases.append((f"f32/{nu_dt}", u32, torch.empty_like(u32), 4, 4 if nu_dt == "f32" else 2))
+                for label, uu, vv, vb, nb in cases:
+                    byt = apply_bytes(L, nc, vb, nb)
+                    rec = {"nodes": f"{n + 1}^3", "ncomp": nc, "precision": label,
+                           "bytes_per_launch": byt}
+                    for mode in ("cold", "warm"):
+                        t = timed(H, L, uu, vv, mode == "cold")
+                        rec[f"{mode}_us"] = round(t, 2)
+                        rec[f"{mode}_GDoF_s"] = round(free / t / 1e3, 2)
+                        rec[f"{mode}_frac_hbm_peak"] = round(byt / t / 1e3 / HBM_PEAK_GBS, 4)
+                    rows.append(rec)
+                    progress(f"[roofline] {n + 1}^3 ncomp={nc} {label}: cold {rec['cold_us']} us "
+                             f"({rec['cold_frac_hbm_peak']:.3f} of peak), warm {rec['warm_us']} us")
+                H.close()
+                torch.cuda.empty_cache()
+        del nus
+        torch.cuda.empty_cache()
+    return {"report": "roofline", "coefficient": "64 sinkers, radii 0.02-0.06, contrast 1e6",
+            "hbm_peak_GB_s": HBM_PEAK_GBS, "rows": rows}
+
+
 def report_coarsening(args, dev) -> dict:
     """Direct against adaptive against Galerkin coarsening (Sections 2.3, 4.2-4.3): PCG
     iterations to 1e-8 of the vector viscous block with the FP64 V-cycle for the
@@ -590,6 +656,8 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print the markdown summary of a profiling directory and exit")
     ap.add_argument("--level", type=int, default=None, help="finest level of a report workload")
+    ap.add_argument("--roofline-levels", default="6,7,8",
+                    help="finest levels of the apply roofline sweep (6: 129^3, 7: 257^3, 8: 513^3)")
     ap.add_argument("--stokes-max-iter", type=int, default=8000)
     ap.add_argument("--stokes-solvers", default="fgmres,minres",
                     help="comma-separated subset of bfbt (FGMRES, triangular, BFBT), fgmres "
@@ -621,7 +689,7 @@ def main():
     # the other workloads print a report line of their own (the benchmark line is the
     # 129^3 sinker workload)
     reports = {"sinker513": report_large, "stokes257": report_stokes, "adjoint129": report_adjoint,
-               "coarsening": report_coarsening}
+               "coarsening": report_coarsening, "roofline": report_roofline}
     if args.workload in reports:
         print(json.dumps(reports[args.workload](args, dev)), flush=True)
         return

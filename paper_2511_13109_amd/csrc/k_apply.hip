@@ -10,18 +10,21 @@
 // cells (32 x 8 by default) and marches up through a chunk of z layers.  At every
 // step a thread evaluates its cell's 6 simplices once (cube_math.h), producing
 // contributions to the cell's 8 corners.  Corner sums are formed without atomics:
-//   * x neighbours are adjacent lanes -> DPP wave_shr:1 (row_shr:1 for 16-wide tiles),
+//   * x neighbours are adjacent lanes -> DPP wave_shr:1,
 //   * y neighbours go through a small LDS buffer,
 //   * the z direction is carried in registers from one step to the next.
 // Each node is therefore finalised by exactly one thread; the first row and column
 // of threads compute the halo cells needed by the tile's first nodes ((TX-1) x (TY-1)
-// nodes finalised per workgroup).  The u values of the cell corners come from a
+// nodes finalised per workgroup).  Where a few node columns are left over in x after
+// the last full tile (5 of 129), they are covered by tall 8 x 32 strip tiles in the
+// same launch instead of a row of mostly idle 32 x 8 tiles.  The u values of the cell corners come from a
 // three-layer LDS ring filled a step ahead, so one barrier per z step suffices; the
 // global loads of a step are issued before its arithmetic and consumed after it.
 // Every output node is written once, with coalesced stores.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <type_traits>
 
 #include "cube_math.h"
 #include "internal.h"
@@ -29,32 +32,41 @@
 namespace agca {
 namespace {
 
-// TX x TY cells per workgroup, TX * TY = 256; 32-wide rows read 264-byte segments of
-// u per node row (16-wide ones 136 bytes), which measured faster beyond 129^3 nodes.
+// Main tiles: TX x TY cells per workgroup, TX * TY = 256; 32-wide rows read 264-byte
+// segments of u per node row (16-wide ones 136 bytes), which measured faster beyond
+// 129^3 nodes.  A tile finalises (TX-1) x (TY-1) node columns.
 #ifndef AGCA_CUBE_TX
 #define AGCA_CUBE_TX 32
 #endif
 constexpr int TX = AGCA_CUBE_TX;
 constexpr int TY = 256 / TX;
-constexpr int NTHREADS = TX * TY;
+constexpr int NTHREADS = 256;
+// Strip tiles of SX x SY cells: when the node columns left after the last full main
+// tile in x are fewer than SX (129 = 4 x 31 + 5), they go to narrow, tall tiles
+// instead of a row of mostly idle main tiles, so fewer workgroups cover the level and
+// each marches fewer z steps.  Both shapes have (T+1)(256/T+1) tile nodes, so they
+// share one LDS layout.
+constexpr int SX = 8;
+constexpr int SY = 256 / SX;
 
-// x neighbour exchange: DPP row_shr:1 within 16-lane rows when a tile row is 16 lanes,
-// wave_shr:1 across the wavefront when it is 32 or 64 lanes (the first lane of every
-// tile row is a halo column whose shifted-in value is never used)
-constexpr int kShr1 = TX == 16 ? 0x111 : 0x138;
+// x neighbour exchange: DPP wave_shr:1, the value of the lane one to the left in the
+// wavefront (0 for its first lane).  Tile rows are tw consecutive lanes and every
+// wavefront starts a row, so the only lanes whose shifted-in value comes from another
+// row are the rows' first lanes, the halo column, whose value is never used.
+constexpr int kWaveShr1 = 0x138;
 template <typename T>
 __device__ __forceinline__ T shr1_row(T v) {
-    // value of the lane one to the left in the same 16-lane row (0 for the row's first lane)
+    constexpr int ctrl = kWaveShr1;
     if constexpr (sizeof(T) == 8) {
         const unsigned long long bits = __double_as_longlong(v);
         int lo = (int)(bits & 0xffffffffull);
         int hi = (int)(bits >> 32);
-        lo = __builtin_amdgcn_update_dpp(0, lo, kShr1, 0xF, 0xF, true);
-        hi = __builtin_amdgcn_update_dpp(0, hi, kShr1, 0xF, 0xF, true);
+        lo = __builtin_amdgcn_update_dpp(0, lo, ctrl, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_update_dpp(0, hi, ctrl, 0xF, 0xF, true);
         return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
     } else {
         int b = __float_as_int(v);
-        b = __builtin_amdgcn_update_dpp(0, b, kShr1, 0xF, 0xF, true);
+        b = __builtin_amdgcn_update_dpp(0, b, ctrl, 0xF, 0xF, true);
         return __int_as_float(b);
     }
 }
@@ -122,19 +134,14 @@ struct RawNu<uint16_t> {
 // to the 8 XCDs, each with its own L2; remapping the linear id so that every XCD
 // receives one contiguous range of tiles (x fastest, then y, then z chunks)
 // keeps the halo rows that neighbouring tiles share in the same L2.
-__device__ __forceinline__ void tile_of(int gx, int gy, int gz, int& bx, int& by, int& bz) {
-    const int total = gx * gy * gz;
+// cols tile columns per z chunk, gz chunks (negative: no remapping)
+__device__ __forceinline__ int tile_lin(int cols, int gz) {
     const int b = blockIdx.x;
-    int lin = b;
-    if (gz > 0) {
-        const int q = total >> 3, r = total & 7;
-        const int xcd = b & 7, j = b >> 3;
-        lin = xcd * q + min(xcd, r) + j;
-    }
-    gz = gz > 0 ? gz : -gz;
-    bx = lin % gx;
-    by = (lin / gx) % gy;
-    bz = lin / (gx * gy);
+    if (gz <= 0) return b;
+    const int total = cols * gz;
+    const int q = total >> 3, r = total & 7;
+    const int xcd = b & 7, j = b >> 3;
+    return xcd * q + min(xcd, r) + j;
 }
 
 #ifndef AGCA_CUBE_PREFETCH_NODE
@@ -161,27 +168,32 @@ struct CubePrefetchNode {
                                                               : AGCA_CUBE_PREFETCH_NODE;
 };
 
+// One tile of tw x 256/tw cells (tw = TX or SX, uniform over the workgroup) whose first
+// finalised node column is (X0, Y0), marching through the z layers Z0 .. Z0 + zc - 1.
+// The shape is a runtime value so that both shapes share one body (and one register
+// allocation).  ubuf_raw / ybuf_raw: the workgroup's LDS ring of u layers and its
+// y-exchange buffer.
 template <int NC, typename T, typename NT, int MODE, bool BLK>
-__global__ void __launch_bounds__(NTHREADS)
-__attribute__((amdgpu_waves_per_eu(CubeWaves<NC, T>::value > 0 ? CubeWaves<NC, T>::value : 1)))
-k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
-       const T* __restrict__ u, const NT* __restrict__ nu, const int32_t* __restrict__ blk,
-       const T* __restrict__ yblk, const T* __restrict__ b, const T* __restrict__ dinv,
-       T* __restrict__ out, const T scale, const T omega, const T alpha, const T gamma,
-       const T omega0, const T* __restrict__ xprev, double* __restrict__ partial) {
+__device__ __forceinline__ void cube_tile(T* __restrict__ ubuf_raw, T* __restrict__ ybuf_raw,
+                                          double& dot_acc, const int tw, const int X0, const int Y0,
+                                          const int Z0,
+                                          const int n, const int zc, const T* __restrict__ u,
+                                          const NT* __restrict__ nu, const int32_t* __restrict__ blk,
+                                          const T* __restrict__ yblk, const T* __restrict__ b,
+                                          const T* __restrict__ dinv, T* __restrict__ out,
+                                          const T scale, const T omega, const T alpha, const T gamma,
+                                          const T omega0, const T* __restrict__ xprev) {
     // node layers of u: layer j lives in buffer (j + 3) % 3, so a step reads two
     // buffers while the third receives the layer two steps ahead
-    // (TX+1) x (TY+1) nodes per layer and component, x fastest, plus 64 slots that
-    // absorb the second tile store of the wavefronts that have no second entry
-    __shared__ T ubuf[3][NC][(TX + 1) * (TY + 1) + 64];
-    __shared__ T ybuf[2][NC][2][TY][TX];
-    double dot_acc = 0.0;  // MODE_APPLY_DOT: this thread's share of u . (A u)
-
-    int bx, by, bz;
-    tile_of(gx, gy, gz, bx, by, bz);
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int tid = tx + TX * ty;
-    const int X0 = bx * (TX - 1), Y0 = by * (TY - 1), Z0 = bz * zc;
+    // (tw+1) x (256/tw+1) nodes per layer and component (297 for either shape), x
+    // fastest, plus 64 slots that absorb the second tile store of the wavefronts that
+    // have no second entry
+    constexpr int UB = (TX + 1) * (TY + 1) + 64;
+    auto ubuf = reinterpret_cast<T (*)[NC][UB]>(ubuf_raw);
+    // y exchange: [buffer][component][dz][thread]; the thread above is tid - tw
+    auto ybuf = reinterpret_cast<T (*)[NC][2][NTHREADS]>(ybuf_raw);
+    const int tid = threadIdx.x;
+    const int tx = tid & (tw - 1), ty = tid >> __builtin_ctz(tw);  // tw is a power of two
     const int cx = X0 - 1 + tx, cy = Y0 - 1 + ty;
     const int64_t n1 = n + 1;
     const int64_t N = n1 * n1 * n1;
@@ -197,8 +209,8 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
     // for the first wavefronts.  Every thread issues the second load (the others at a
     // clamped duplicate address, a cache hit) so that no branch surrounds the loads
     // and the prefetched values stay in registers; only the first wavefronts store it.
-    constexpr int TW = TX + 1;
-    constexpr int TE = (TX + 1) * (TY + 1);
+    const int TW = tw + 1;
+    constexpr int TE = (TX + 1) * (TY + 1);  // the same for both shapes
     constexpr int NB = ((TE - NTHREADS + 63) / 64) * 64;  // whole wavefronts
     const int qa = tid;
     const int qb = min(NTHREADS + tid, TE - 1);
@@ -326,16 +338,26 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
 #pragma unroll
     for (int c = 0; c < NC; ++c) carry[c] = T(0);
 
+    const int lq = ty * TW + tx;  // this thread's cell corner 0 in a ring layer
     for (int z = Z0 - 1; z <= zend; ++z) {
         const int lo = bidx(z), hi = bidx(z + 1);  // buffers holding layers z and z+1
         T U[8][NC];
+        // the cell's corners in the ring: the row pitch is a constant of each shape (a
+        // branch that is uniform over the workgroup), so the reads take immediate offsets
+        auto gather = [&](auto pitch) {
+            constexpr int PW = decltype(pitch)::value;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                U[k][c] = ubuf[lo][c][(ty + (k >> 1)) * (TX + 1) + tx + (k & 1)];
-                U[k + 4][c] = ubuf[hi][c][(ty + (k >> 1)) * (TX + 1) + tx + (k & 1)];
-            }
+                for (int c = 0; c < NC; ++c) {
+                    U[k][c] = ubuf[lo][c][lq + (k >> 1) * PW + (k & 1)];
+                    U[k + 4][c] = ubuf[hi][c][lq + (k >> 1) * PW + (k & 1)];
+                }
+        };
+        if (tw == TX)
+            gather(std::integral_constant<int, TX + 1>{});
+        else
+            gather(std::integral_constant<int, SX + 1>{});
         T w_cur[6];
         int32_t bi_cur[6];
         decode_cell(rc, w_cur, bi_cur);
@@ -375,8 +397,8 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
         const int yb = z & 1;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            ybuf[yb][c][0][ty][tx] = P[1][0][c];
-            ybuf[yb][c][1][ty][tx] = P[1][1][c];
+            ybuf[yb][c][0][tid] = P[1][0][c];
+            ybuf[yb][c][1][tid] = P[1][1][c];
         }
         // held layer z-1, read last step; after the last step nothing reads this buffer
         // again, so the store needs no condition (a branch would pull the loads into it)
@@ -391,8 +413,8 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
             T s0[NC], s1[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                s0[c] = P[0][0][c] + ybuf[yb][c][0][ty - 1][tx];
-                s1[c] = P[0][1][c] + ybuf[yb][c][1][ty - 1][tx];
+                s0[c] = P[0][0][c] + ybuf[yb][c][0][tid - tw];
+                s1[c] = P[0][1][c] + ybuf[yb][c][1][tid - tw];
             }
             if (z >= Z0) {
                 const int64_t p = col + (int64_t)z * layer;
@@ -431,11 +453,37 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gz,
             }
         }
     }
+}
+
+template <int NC, typename T, typename NT, int MODE, bool BLK>
+__global__ void __launch_bounds__(NTHREADS)
+__attribute__((amdgpu_waves_per_eu(CubeWaves<NC, T>::value > 0 ? CubeWaves<NC, T>::value : 1)))
+k_cube(const int n, const int zc, const int gx, const int gy, const int gs, const int gz,
+       const T* __restrict__ u, const NT* __restrict__ nu, const int32_t* __restrict__ blk,
+       const T* __restrict__ yblk, const T* __restrict__ b, const T* __restrict__ dinv,
+       T* __restrict__ out, const T scale, const T omega, const T alpha, const T gamma,
+       const T omega0, const T* __restrict__ xprev, double* __restrict__ partial) {
+    constexpr int UB = (TX + 1) * (TY + 1) + 64;
+    static_assert((SX + 1) * (SY + 1) + 64 == UB && SX * SY == 256, "tile shapes share the LDS layout");
+    __shared__ T ubuf[3 * NC * UB];
+    __shared__ T ybuf[2 * NC * 2 * 256];
+    double dot_acc = 0.0;  // MODE_APPLY_DOT: this thread's share of u . (A u)
+    // per z chunk: gx x gy main tiles, then gs strip tiles (one column of them in x)
+    const int cols = gx * gy + gs;
+    const int lin = tile_lin(cols, gz);
+    const int bz = lin / cols, c = lin - bz * cols;
+    const bool main_tile = c < gx * gy;
+    const int tw = main_tile ? TX : SX;
+    const int X0 = main_tile ? (c % gx) * (TX - 1) : gx * (TX - 1);
+    const int Y0 = main_tile ? (c / gx) * (TY - 1) : (c - gx * gy) * (SY - 1);
+    cube_tile<NC, T, NT, MODE, BLK>(ubuf, ybuf, dot_acc, tw, X0, Y0, bz * zc, n, zc, u, nu, blk, yblk, b,
+                                    dinv, out, scale, omega, alpha, gamma, omega0, xprev);
     if constexpr (MODE == MODE_APPLY_DOT) {
         // fixed-order workgroup reduction: wavefront shuffle, then the 4 wavefronts
         __shared__ double red[NTHREADS / 64];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) dot_acc += __shfl_down(dot_acc, off, 64);
+        const int tid = threadIdx.x;
         if ((tid & 63) == 0) red[tid >> 6] = dot_acc;
         __syncthreads();
         if (tid == 0) {
@@ -485,7 +533,34 @@ k_block_products(const int n, const int64_t nflag, const int32_t* __restrict__ i
     y[t] = acc;
 }
 
-int tile_columns(int n) { return ((n + 1 + TX - 2) / (TX - 1)) * ((n + 1 + TY - 2) / (TY - 1)); }
+// Tile columns of a level with n cells per axis: gx x gy main tiles and gs strip tiles
+// (gs = 0 when the node columns left after the last full main tile in x are none or
+// more than a strip tile finalises).  AGCA_CUBE_STRIP=0 keeps main tiles only.
+struct CubeGrid {
+    int gx, gy, gs;
+};
+CubeGrid cube_grid(int n) {
+    static const bool strip = [] {
+        const char* e = getenv("AGCA_CUBE_STRIP");
+        return e ? atoi(e) != 0 : true;
+    }();
+    const int nodes = n + 1;
+    const int full = nodes / (TX - 1), rest = nodes - full * (TX - 1);
+    CubeGrid g;
+    g.gy = (nodes + TY - 2) / (TY - 1);
+    if (strip && full >= 1 && rest >= 1 && rest <= SX - 1) {
+        g.gx = full;
+        g.gs = (nodes + SY - 2) / (SY - 1);
+    } else {
+        g.gx = (nodes + TX - 2) / (TX - 1);
+        g.gs = 0;
+    }
+    return g;
+}
+int tile_columns(int n) {
+    const CubeGrid g = cube_grid(n);
+    return g.gx * g.gy + g.gs;
+}
 
 // z layers per workgroup.  Chunks of about 16 layers amortise the halo layer each chunk
 // recomputes; small levels use shorter chunks to expose more workgroups; when the
@@ -503,7 +578,10 @@ int pick_zc(int n, int slots) {
     while (zc > 2 && blocks(zc) < 512) zc /= 2;
     if (slots > 0 && blocks(zc) > slots && blocks(zc) <= slots + slots / 4)
         while (blocks(zc) > slots && zc < n + 1) ++zc;
-    return zc;
+    // the shortest chunk that gives the same number of chunks (fewer z steps per
+    // workgroup for the same workgroups)
+    const int gz = (n + 1 + zc - 1) / zc;
+    return (n + 1 + gz - 1) / gz;
 }
 
 // workgroups of one kernel that the GPU runs at once (occupancy x compute units)
@@ -525,10 +603,11 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, const 
     const int n = op.n;
     static const int slots = resident_slots(k_cube<NC, T, NT, MODE, BLK>);
     const int zc = pick_zc(n, slots);
-    dim3 block(TX, TY, 1);
-    const int gx = (n + 1 + TX - 2) / (TX - 1), gy = (n + 1 + TY - 2) / (TY - 1),
-              gz = (n + 1 + zc - 1) / zc;
-    dim3 grid((unsigned)(gx * gy * gz), 1, 1);
+    const CubeGrid g = cube_grid(n);
+    const int gz = (n + 1 + zc - 1) / zc;
+    const int nwg = (g.gx * g.gy + g.gs) * gz;
+    dim3 block(NTHREADS, 1, 1);
+    dim3 grid((unsigned)nwg, 1, 1);
     const T scale = T(1.0 / (6.0 * n));
     if constexpr (BLK && MODE != MODE_JACOBI0) {
         if (op.nflag > 0) {
@@ -543,8 +622,8 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, const 
         const char* e = getenv("AGCA_CUBE_XCD");
         return e ? atoi(e) != 0 : true;
     }();
-    if (nblocks) *nblocks = gx * gy * gz;
-    hipLaunchKernelGGL((k_cube<NC, T, NT, MODE, BLK>), grid, block, 0, st, n, zc, gx, gy,
+    if (nblocks) *nblocks = nwg;
+    hipLaunchKernelGGL((k_cube<NC, T, NT, MODE, BLK>), grid, block, 0, st, n, zc, g.gx, g.gy, g.gs,
                        xcd_map ? gz : -gz, u,
                        reinterpret_cast<const NT*>(op.nu), op.blk, op.yblk, b, op.dinv, out,
                        scale, sw.omega, sw.alpha, sw.gamma, sw.omega0, sw.xprev, partial);

@@ -37,9 +37,13 @@ def full():
 
 
 def _nodes(field, level, rng, k_random=3):
-    """Interior nodes: random ones plus nodes on the surfaces of the first sinkers."""
+    """Interior nodes: random ones, nodes on the surfaces of the first sinkers, and nodes
+    in the last node columns in x (past the last full 31-wide tile of the element loop,
+    where the narrow strip tiles work) and at the edges of the lattice."""
     n = 2 ** (level + 1)
     pts = [tuple(rng.integers(1, n, 3)) for _ in range(k_random)]
+    pts += [(n - 1, int(rng.integers(1, n)), int(rng.integers(1, n))),
+            (n - 3, int(rng.integers(1, n)), n - 1), (31 * (n // 31), 1, 1), (n - 1, n - 1, n - 1)]
     for c, r in zip(field.centres[:3], field.radii[:3]):
         d = rng.standard_normal(3)
         d /= np.linalg.norm(d)

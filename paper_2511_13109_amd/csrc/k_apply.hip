@@ -168,6 +168,15 @@ struct CubePrefetchNode {
                                                               : AGCA_CUBE_PREFETCH_NODE;
 };
 
+// Whether a mode's launches use strip tiles.  The fused first two passes from zero hold
+// the inverse diagonal of the prefetched layer as well and are at the register limit
+// of 3 wavefronts per SIMD: the runtime tile shape would make them spill, so they keep
+// the main tiles only (the shape then folds to a constant).
+template <int MODE>
+struct CubeStrip {
+    static constexpr bool value = MODE != MODE_JACOBI0;
+};
+
 // One tile of tw x 256/tw cells (tw = TX or SX, uniform over the workgroup) whose first
 // finalised node column is (X0, Y0), marching through the z layers Z0 .. Z0 + zc - 1.
 // The shape is a runtime value so that both shapes share one body (and one register
@@ -354,7 +363,7 @@ __device__ __forceinline__ void cube_tile(T* __restrict__ ubuf_raw, T* __restric
                     U[k + 4][c] = ubuf[hi][c][lq + (k >> 1) * PW + (k & 1)];
                 }
         };
-        if (tw == TX)
+        if (!CubeStrip<MODE>::value || tw == TX)
             gather(std::integral_constant<int, TX + 1>{});
         else
             gather(std::integral_constant<int, SX + 1>{});
@@ -472,7 +481,7 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gs, cons
     const int cols = gx * gy + gs;
     const int lin = tile_lin(cols, gz);
     const int bz = lin / cols, c = lin - bz * cols;
-    const bool main_tile = c < gx * gy;
+    const bool main_tile = !CubeStrip<MODE>::value || c < gx * gy;
     const int tw = main_tile ? TX : SX;
     const int X0 = main_tile ? (c % gx) * (TX - 1) : gx * (TX - 1);
     const int Y0 = main_tile ? (c / gx) * (TY - 1) : (c - gx * gy) * (SY - 1);
@@ -539,11 +548,12 @@ k_block_products(const int n, const int64_t nflag, const int32_t* __restrict__ i
 struct CubeGrid {
     int gx, gy, gs;
 };
-CubeGrid cube_grid(int n) {
-    static const bool strip = [] {
+CubeGrid cube_grid(int n, bool allow_strip) {
+    static const bool strip_env = [] {
         const char* e = getenv("AGCA_CUBE_STRIP");
         return e ? atoi(e) != 0 : true;
     }();
+    const bool strip = allow_strip && strip_env;
     const int nodes = n + 1;
     const int full = nodes / (TX - 1), rest = nodes - full * (TX - 1);
     CubeGrid g;
@@ -557,8 +567,8 @@ CubeGrid cube_grid(int n) {
     }
     return g;
 }
-int tile_columns(int n) {
-    const CubeGrid g = cube_grid(n);
+int tile_columns(int n, bool allow_strip = true) {
+    const CubeGrid g = cube_grid(n, allow_strip);
     return g.gx * g.gy + g.gs;
 }
 
@@ -566,13 +576,13 @@ int tile_columns(int n) {
 // recomputes; small levels use shorter chunks to expose more workgroups; when the
 // workgroups slightly exceed what the GPU holds at once (slots), the chunks grow
 // until they fit, rather than leaving a short second round.
-int pick_zc(int n, int slots) {
+int pick_zc(int n, int slots, bool allow_strip) {
     static const int forced = [] {
         const char* e = getenv("AGCA_CUBE_ZC");
         return e ? atoi(e) : 0;
     }();
     if (forced > 0) return forced;
-    const int64_t cols = tile_columns(n);
+    const int64_t cols = tile_columns(n, allow_strip);
     auto blocks = [&](int zc) { return cols * ((n + 1 + zc - 1) / zc); };
     int zc = 16;
     while (zc > 2 && blocks(zc) < 512) zc /= 2;
@@ -602,8 +612,8 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, const 
                     hipStream_t st, double* partial = nullptr, int* nblocks = nullptr) {
     const int n = op.n;
     static const int slots = resident_slots(k_cube<NC, T, NT, MODE, BLK>);
-    const int zc = pick_zc(n, slots);
-    const CubeGrid g = cube_grid(n);
+    const int zc = pick_zc(n, slots, CubeStrip<MODE>::value);
+    const CubeGrid g = cube_grid(n, CubeStrip<MODE>::value);
     const int gz = (n + 1 + zc - 1) / zc;
     const int nwg = (g.gx * g.gy + g.gs) * gz;
     dim3 block(NTHREADS, 1, 1);

@@ -201,8 +201,11 @@ __device__ __forceinline__ void cube_tile(T* __restrict__ ubuf_raw, T* __restric
     auto ubuf = reinterpret_cast<T (*)[NC][UB]>(ubuf_raw);
     // y exchange: [buffer][component][dz][thread]; the thread above is tid - tw
     auto ybuf = reinterpret_cast<T (*)[NC][2][NTHREADS]>(ybuf_raw);
-    const int tid = threadIdx.x;
-    const int tx = tid & (tw - 1), ty = tid >> __builtin_ctz(tw);  // tw is a power of two
+    // launches without strip tiles use a TX x TY block (the hardware supplies tx, ty);
+    // the others a flat block of 256, split by the tile shape (tw is a power of two)
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    const int tx = CubeStrip<MODE>::value ? tid & (tw - 1) : (int)threadIdx.x;
+    const int ty = CubeStrip<MODE>::value ? tid >> __builtin_ctz(tw) : (int)threadIdx.y;
     const int cx = X0 - 1 + tx, cy = Y0 - 1 + ty;
     const int64_t n1 = n + 1;
     const int64_t N = n1 * n1 * n1;
@@ -492,7 +495,7 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gs, cons
         __shared__ double red[NTHREADS / 64];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) dot_acc += __shfl_down(dot_acc, off, 64);
-        const int tid = threadIdx.x;
+        const int tid = threadIdx.x + TX * threadIdx.y;
         if ((tid & 63) == 0) red[tid >> 6] = dot_acc;
         __syncthreads();
         if (tid == 0) {
@@ -616,7 +619,7 @@ hipError_t launch_t(const LevelOp<T>& op, const T* u, const T* b, T* out, const 
     const CubeGrid g = cube_grid(n, CubeStrip<MODE>::value);
     const int gz = (n + 1 + zc - 1) / zc;
     const int nwg = (g.gx * g.gy + g.gs) * gz;
-    dim3 block(NTHREADS, 1, 1);
+    const dim3 block = CubeStrip<MODE>::value ? dim3(NTHREADS, 1, 1) : dim3(TX, TY, 1);
     dim3 grid((unsigned)nwg, 1, 1);
     const T scale = T(1.0 / (6.0 * n));
     if constexpr (BLK && MODE != MODE_JACOBI0) {

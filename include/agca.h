@@ -294,9 +294,10 @@ typedef struct {
  * false convergence).  The returned p has zero mean over the pressure nodes.  Work
  * space: 2 restart + 5 (FGMRES; one more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy;
  * BFBT adds 3 velocity and 8 pressure vectors.
- * FGMRES stops early with stats->floor_limited when the true residual after a restart
- * cycle is within 10x of tol and less than 5 % below its value four cycles earlier (the
- * rounding floor of an FP64 iterate).
+ * FGMRES stops early with stats->floor_limited when a restart cycle's residual
+ * estimate reached tol but the true residual after it is above tol, within 10x of it
+ * and less than 5 % below its value four cycles earlier (the rounding floor of an FP64
+ * iterate).
  * Returns AGCA_OK when converged or floor_limited, AGCA_E_NOCONV (u, p, stats filled)
  * otherwise;
  * stats->history holds the FGMRES residual estimates (true residual at restarts)

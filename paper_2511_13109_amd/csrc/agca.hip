@@ -1658,15 +1658,18 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
         }
         for (int i = 0; i < k_done; ++i) HIPCHK(h, launch_axpby<double>(tot, y[i], vec(Z, i), 1.0, x, h->st));
         TRY(stokes_residual(h, b, x, r));
+        const bool estimate_reached = hist.back() <= o->tol;
         TRY(stokes_norm(h, r, &rel));
         rel /= bn;
         hist.back() = rel;
         if (rel <= o->tol) break;
-        // rounding floor: within 10x of the tolerance and less than 5 % better than four
-        // restart cycles ago (the true residual of an FP64 iterate stagnates there)
+        // rounding floor: the cycle's recurrence reached the tolerance but the true
+        // residual did not, it is within 10x of the tolerance and less than 5 % better
+        // than four restart cycles ago (the true residual of an FP64 iterate stagnates
+        // there while each cycle's estimate keeps converging)
         cycle_res.push_back(rel);
         const size_t c = cycle_res.size();
-        if (c >= 5 && rel < 10.0 * o->tol && rel > 0.95 * cycle_res[c - 5]) {
+        if (estimate_reached && c >= 5 && rel < 10.0 * o->tol && rel > 0.95 * cycle_res[c - 5]) {
             *floor_out = true;
             break;
         }

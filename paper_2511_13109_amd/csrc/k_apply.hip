@@ -174,7 +174,9 @@ struct CubePrefetchNode {
 // the main tiles only (the shape then folds to a constant).
 template <int MODE>
 struct CubeStrip {
-    static constexpr bool value = MODE != MODE_JACOBI0;
+    // strips need the same number of tile nodes as the main tiles (one LDS layout);
+    // a main tile width other than 32 (AGCA_CUBE_TX) turns them off
+    static constexpr bool value = MODE != MODE_JACOBI0 && (SX + 1) * (SY + 1) == (TX + 1) * (TY + 1);
 };
 
 // One tile of tw x 256/tw cells (tw = TX or SX, uniform over the workgroup) whose first
@@ -476,7 +478,7 @@ k_cube(const int n, const int zc, const int gx, const int gy, const int gs, cons
        T* __restrict__ out, const T scale, const T omega, const T alpha, const T gamma,
        const T omega0, const T* __restrict__ xprev, double* __restrict__ partial) {
     constexpr int UB = (TX + 1) * (TY + 1) + 64;
-    static_assert((SX + 1) * (SY + 1) + 64 == UB && SX * SY == 256, "tile shapes share the LDS layout");
+    static_assert(SX * SY == NTHREADS && TX * TY == NTHREADS, "both tile shapes have 256 cells");
     __shared__ T ubuf[3 * NC * UB];
     __shared__ T ybuf[2 * NC * 2 * 256];
     double dot_acc = 0.0;  // MODE_APPLY_DOT: this thread's share of u . (A u)
@@ -677,7 +679,9 @@ hipError_t dispatch_nu(const LevelOp<T>& op, const T* u, const T* b, T* out, con
 }  // namespace
 
 int cube_grid_blocks(int n) {
-    return tile_columns(n) * (n + 1);  // upper bound: one z layer per workgroup
+    // upper bound of any launch's workgroups: main tiles only (at least as many
+    // columns as with strips), one z layer per workgroup
+    return tile_columns(n, false) * (n + 1);
 }
 
 hipError_t launch_cube_dot(int ncomp, const LevelOp<double>& op, const double* u, double* out,

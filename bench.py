@@ -664,7 +664,7 @@ def main():
                          "(triangular, lumped mass) and minres (diagonal, lumped mass)")
     ap.add_argument("--schur-iters", type=int, default=20,
                     help="Jacobi-CG steps per Z solve of the BFBT Schur approximation")
-    ap.add_argument("--stokes-restart", type=int, default=126)
+    ap.add_argument("--stokes-restart", type=int, default=64)
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile, ""))

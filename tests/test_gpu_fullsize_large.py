@@ -7,7 +7,8 @@ recomputed by the element-by-element oracle (oracle/sample.py):
   coarse levels, the FP64 Galerkin blocks behind them, and the energy-norm contraction
   of one V-cycle;
 * Stokes with velocity 257^3 / pressure 129^3 nodes and 16 sinkers: the divergence B,
-  its transpose and the 1/nu lumped pressure mass at sampled interior nodes.
+  its transpose and the 1/nu lumped pressure mass at sampled interior nodes, and the
+  velocity block's fine apply at sampled nodes.
 
 The inputs are generated on the device (workloads.device, the same seeded fields as
 the host evaluation) and only the entries a sample needs are read back.
@@ -191,3 +192,23 @@ def test_stokes_rows_sampled_257(stokes257):
         got = g[idx].cpu().numpy()
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), j
     print(f"[stokes257] B, mass at {len(pres)} pressure nodes; B^T at velocity nodes", flush=True)
+
+
+def test_fine_apply_sampled_257(stokes257):
+    # the velocity block's element loop at 257^3 nodes, including the last, partly
+    # filled tiles in x (9 node columns after eight full 31-wide tiles)
+    w, field, nus, S = stokes257
+    L, n = w.L, w.n
+    nn = (n + 1) ** 3
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    u = torch.randn(3 * nn, generator=gen, device="cuda", dtype=torch.float64)
+    v = S.H.apply(L, u)
+    rng = np.random.default_rng(5)
+    nodes = _nodes(field, n, rng, k_random=2, k_sinkers=2)
+    nodes += [(n - 1, int(rng.integers(1, n)), int(rng.integers(1, n))), (248, 17, 200),
+              (252, n - 1, 1), (247, 1, n - 1)]
+    for node in nodes:
+        idx = torch.tensor([c * nn + _pid(node, n) for c in range(3)], device="cuda")
+        ref = sample.apply_at_node(L, np.array(node) / n, _Gather(nus[L]), 3, _Gather(u))
+        got = v[idx].cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), node

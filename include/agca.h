@@ -258,11 +258,12 @@ int32_t agca_stokes_grad(agca_hier* h, const double* p, double* v);
 int32_t agca_stokes_mass(agca_hier* h, double* m);
 
 typedef enum { AGCA_STOKES_FGMRES = 0, AGCA_STOKES_MINRES = 1 } agca_stokes_solver;
-/* DIAGONAL   : diag(V-cycle, diag(m)^-1).
+/* DIAGONAL   : diag(V-cycle, S^-1).
  * TRIANGULAR : the upper block-triangular preconditioner of eq. (4.1) with the same
- *              blocks, [[V, V B^T S^-1], [0, -S^-1]], S = diag(m) approximating the
- *              positive B A^-1 B^T (the sign of the pressure block for which exact
- *              blocks make the preconditioned matrix unipotent); FGMRES only. */
+ *              blocks, [[V, V B^T S^-1], [0, -S^-1]] (the sign of the pressure block
+ *              for which exact blocks make the preconditioned matrix unipotent);
+ *              FGMRES only.
+ * S approximates the positive Schur complement B A^-1 B^T (agca_stokes_schur). */
 typedef enum { AGCA_STOKES_DIAGONAL = 0, AGCA_STOKES_TRIANGULAR = 1 } agca_stokes_precond;
 /* The Schur approximation S in either preconditioner:
  * MASS : S = diag(m), the 1/nu-weighted lumped pressure mass.

@@ -46,9 +46,13 @@ k_restrict(int ncomp, int nc, const T* __restrict__ rf, T* __restrict__ rc) {
     }
 }
 
-template <typename T>
+// x_f += P e_c at one fine node per thread, all components: the midpoint rule
+// 0.5 (e(lo) + e(hi)) with lo = hi at the fine nodes that coincide with coarse ones
+// (there 0.5 (e + e) = e exactly), so every thread runs the same code; all loads are
+// issued before the stores.
+template <int NC, typename T>
 __global__ void __launch_bounds__(NT)
-k_prolong_add(int ncomp, int nf, const T* __restrict__ ec, T* __restrict__ xf) {
+k_prolong_add(int nf, const T* __restrict__ ec, T* __restrict__ xf) {
     const int nc = nf / 2;
     const int64_t nc1 = nc + 1, Nc = nc1 * nc1 * nc1;
     const int64_t nf1 = nf + 1, Nf = nf1 * nf1 * nf1;
@@ -60,12 +64,15 @@ k_prolong_add(int ncomp, int nf, const T* __restrict__ ec, T* __restrict__ xf) {
     const int dx = x & 1, dy = y & 1, dz = z & 1;
     const int64_t lo = ((x - dx) >> 1) + nc1 * (((y - dy) >> 1) + nc1 * (int64_t)((z - dz) >> 1));
     const int64_t hi = ((x + dx) >> 1) + nc1 * (((y + dy) >> 1) + nc1 * (int64_t)((z + dz) >> 1));
-    const bool even = (dx | dy | dz) == 0;
-    for (int c = 0; c < ncomp; ++c) {
-        const T* e = ec + c * Nc;
-        const T v = even ? e[lo] : T(0.5) * (e[lo] + e[hi]);
-        xf[c * Nf + p] += v;
+    T a[NC], b[NC], v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        a[c] = ec[c * Nc + lo];
+        b[c] = ec[c * Nc + hi];
+        v[c] = xf[c * Nf + p];
     }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xf[c * Nf + p] = v[c] + T(0.5) * (a[c] + b[c]);
 }
 
 // level 0 has n = 2: a single free node (1,1,1), id 13 of 27
@@ -434,7 +441,10 @@ template <typename T>
 hipError_t launch_prolong_add(int ncomp, int n_fine, const T* ec, T* xf, hipStream_t st) {
     if (!ec || !xf || n_fine < 4) return hipErrorInvalidValue;
     const int64_t Nf = (int64_t)(n_fine + 1) * (n_fine + 1) * (n_fine + 1);
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(Nf)), dim3(NT), 0, st, ncomp, n_fine, ec, xf);
+    if (ncomp == 1)
+        hipLaunchKernelGGL((k_prolong_add<1, T>), dim3(grid_for(Nf)), dim3(NT), 0, st, n_fine, ec, xf);
+    else
+        hipLaunchKernelGGL((k_prolong_add<3, T>), dim3(grid_for(Nf)), dim3(NT), 0, st, n_fine, ec, xf);
     return hipGetLastError();
 }
 template <typename T>

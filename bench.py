@@ -119,8 +119,8 @@ SOLVER_KERNEL_BYTES = {
     "k_zpbp_dev<double>": ("p = z + beta p", 3 * 24, 0),
     "k_zpbp_dev<float>": ("p = z + beta p (FP32 z)", 3 * 20, 0),
     # per fine node; the coarse vector (1/8 of the nodes) is added below
-    "k_restrict<double>": ("restriction 129^3 -> 65^3", 3 * 8, 0),
-    "k_restrict<float>": ("restriction 129^3 -> 65^3, FP32", 3 * 4, 0),
+    "k_restrict<3, double>": ("restriction 129^3 -> 65^3", 3 * 8, 0),
+    "k_restrict<3, float>": ("restriction 129^3 -> 65^3, FP32", 3 * 4, 0),
     "k_prolong_add<3, double>": ("prolongation 65^3 -> 129^3", 3 * 16, 0),
     "k_prolong_add<3, float>": ("prolongation 65^3 -> 129^3, FP32", 3 * 8, 0),
 }

@@ -19,9 +19,12 @@ constexpr int NT = 256;
 // Restriction is the transpose: a coarse node Y collects r(2Y) plus half of
 // r(2Y + d) and r(2Y - d) for the 7 offsets d.  Boundary nodes stay zero.
 // ---------------------------------------------------------------------------
-template <typename T>
+// r_c = P^T r_f at one coarse node per thread, all components (the summation order of
+// each component is fixed: the node itself plus half of its 14 lattice neighbours,
+// pairwise by direction)
+template <int NC, typename T>
 __global__ void __launch_bounds__(NT)
-k_restrict(int ncomp, int nc, const T* __restrict__ rf, T* __restrict__ rc) {
+k_restrict(int nc, const T* __restrict__ rf, T* __restrict__ rc) {
     const int64_t nc1 = nc + 1, Nc = nc1 * nc1 * nc1;
     const int64_t nf1 = 2 * nc + 1, Nf = nf1 * nf1 * nf1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
@@ -29,20 +32,22 @@ k_restrict(int ncomp, int nc, const T* __restrict__ rf, T* __restrict__ rc) {
     int x, y, z;
     node_coords(p, nc, x, y, z);
     const bool interior = x > 0 && y > 0 && z > 0 && x < nc && y < nc && z < nc;
-    const int64_t q = 2 * x + nf1 * (2 * y + nf1 * (int64_t)(2 * z));
-    for (int c = 0; c < ncomp; ++c) {
-        T acc = T(0);
-        if (interior) {
-            const T* f = rf + c * Nf;
-            T half = T(0);
+    if (!interior) {
 #pragma unroll
-            for (int d = 1; d < 8; ++d) {
-                const int64_t off = (d & 1) + nf1 * (((d >> 1) & 1) + nf1 * ((d >> 2) & 1));
-                half += f[q + off] + f[q - off];
-            }
-            acc = f[q] + T(0.5) * half;
+        for (int c = 0; c < NC; ++c) rc[c * Nc + p] = T(0);
+        return;
+    }
+    const int64_t q = 2 * x + nf1 * (2 * y + nf1 * (int64_t)(2 * z));
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const T* f = rf + c * Nf;
+        T half = T(0);
+#pragma unroll
+        for (int d = 1; d < 8; ++d) {
+            const int64_t off = (d & 1) + nf1 * (((d >> 1) & 1) + nf1 * ((d >> 2) & 1));
+            half += f[q + off] + f[q - off];
         }
-        rc[c * Nc + p] = acc;
+        rc[c * Nc + p] = f[q] + T(0.5) * half;
     }
 }
 
@@ -434,7 +439,10 @@ hipError_t launch_restrict(int ncomp, int n_fine, const T* rf, T* rc, hipStream_
     if (!rf || !rc || n_fine < 4) return hipErrorInvalidValue;
     const int nc = n_fine / 2;
     const int64_t Nc = (int64_t)(nc + 1) * (nc + 1) * (nc + 1);
-    hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(Nc)), dim3(NT), 0, st, ncomp, nc, rf, rc);
+    if (ncomp == 1)
+        hipLaunchKernelGGL((k_restrict<1, T>), dim3(grid_for(Nc)), dim3(NT), 0, st, nc, rf, rc);
+    else
+        hipLaunchKernelGGL((k_restrict<3, T>), dim3(grid_for(Nc)), dim3(NT), 0, st, nc, rf, rc);
     return hipGetLastError();
 }
 template <typename T>

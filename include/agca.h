@@ -213,25 +213,46 @@ typedef struct {
 typedef struct {
     int32_t iterations;
     int32_t converged;       /* the true FP64 residual of x is <= tol                       */
-    int32_t floor_limited;   /* the recurrence reached tol but the true residual stagnated
-                                above it after residual replacement: FP64 cannot represent
-                                an x with a smaller residual (rounding floor)               */
-    int32_t replacements;    /* restarts from the true residual                             */
-    double rel_residual;     /* final ||b - A x|| / ||b|| in FP64 with FP64 coefficients    */
+    int32_t floor_limited;   /* PCG/FCG: the recurrence reached tol, the true residual
+                                stopped improving above it, and it is within 2x of
+                                max(tol, floor_estimate): FP64 rounding of x, not the
+                                solver, limits it (Stokes FGMRES: see agca_stokes_solve)    */
+    int32_t replacements;    /* times the true residual replaced the recurrence's           */
+    double rel_residual;     /* final ||b - A x|| / ||b|| in FP64 with FP64 coefficients,
+                                norms over the free dofs                                    */
     double recursive_rel_residual; /* the Krylov recurrence's last residual estimate        */
+    double floor_estimate;   /* agca_solve: rounding floor rho of the returned x
+                                (agca_residual_floor); Stokes FGMRES: the velocity block's
+                                part at the last floor test (0 if none ran)                 */
     double seconds;          /* wall time of the solve (after setup)                        */
     double history[AGCA_MAX_HISTORY]; /* recurrence residuals, one per iteration           */
 } agca_solve_stats;
 
 /* Solve A_L x = b with the AGCA V-cycle as preconditioner inside an FP64 outer
  * loop (PCG for an FP64 V-cycle; FCG(1) or iterative refinement around an FP32
- * V-cycle; stationary V-cycle iteration).  b, x: device FP64 level vectors.
- * Stopping: when the recurrence's residual reaches tol the true residual
- * b - A x is recomputed; if it is above tol the iteration restarts from it
- * (at most 3 times, while it keeps halving).  Returns AGCA_OK when converged or
- * floor_limited, AGCA_E_NOCONV when max_iter is reached first. */
+ * V-cycle; stationary V-cycle iteration).  b, x: device FP64 level vectors (boundary
+ * slots of b are ignored; norms are taken over the free dofs).
+ * Stopping (eq. (4.3)): PCG and FCG replace their recurrence's residual by the true
+ * residual b - A x whenever the recurrence has fallen tenfold since the last
+ * replacement, and when it reaches tol (the search direction is kept).  If the true
+ * residual is then above tol the iteration continues; it stops with floor_limited only
+ * when the true residual has stopped improving (two end checks in a row without a
+ * 10 % gain, or 8 end checks) and is within 2x of max(tol, rho), rho the rounding
+ * floor of x (agca_residual_floor).  Returns AGCA_OK when converged or floor_limited;
+ * AGCA_E_NOCONV (x and stats filled) when max_iter is reached first or the true
+ * residual stalls above 2 max(tol, rho). */
 int32_t agca_solve(agca_hier* h, const agca_solve_opts* opts, const double* b, double* x,
                    agca_solve_stats* stats);
+
+/* Rounding floor of the relative residual of x (stopping test of eq. (4.3) in FP64):
+ *   *rho = u || |b| + sum_e |A_e| |x_e| ||_2 / ||b||_2,   u = 2^-53,
+ * norms over the free dofs of level L, |A_e| the entrywise absolute element matrix of
+ * the finest operator.  Rounding each entry of x once more moves b - A x by at most
+ * u sum_e |A_e| |x_e| entrywise, so relative residuals much below rho cannot be
+ * certified for an FP64 iterate near x.  b, x: device FP64 level vectors on level L
+ * (boundary slots ignored).  Synchronises the stream.  *rho = 0 when b = 0 on the
+ * free dofs. */
+int32_t agca_residual_floor(agca_hier* h, const double* b, const double* x, double* rho);
 
 /* Adjoint gradient (not in the paper): g_e = -w_e^T A_e u_e for every finest
  * element, i.e. dJ/dlog nu_e when w solves A w = u - u_obs.
@@ -296,9 +317,11 @@ typedef struct {
  * space: 2 restart + 5 (FGMRES; one more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy;
  * BFBT adds 3 velocity and 8 pressure vectors.
  * FGMRES stops early with stats->floor_limited when a restart cycle's residual
- * estimate reached tol but the true residual after it is above tol, within 10x of it
- * and less than 5 % below its value four cycles earlier (the rounding floor of an FP64
- * iterate).
+ * estimate reached tol but the true residual after it is above tol, less than 5 %
+ * below its value four cycles earlier, and within 2x of max(tol, rho_A), rho_A the
+ * rounding floor of the velocity block (the terms of agca_residual_floor for A and
+ * f, over the norm of the whole right-hand side; a lower bound of the system's
+ * floor), reported in stats->floor_estimate.
  * Returns AGCA_OK when converged or floor_limited, AGCA_E_NOCONV (u, p, stats filled)
  * otherwise;
  * stats->history holds the FGMRES residual estimates (true residual at restarts)

@@ -334,46 +334,62 @@ def fgmres(A, b, M: Callable, tol: float, restart: int = 30, maxit: int = 500) -
 
 
 def minres(A, b, M: Callable, tol: float, maxit: int = 500) -> SolveResult:
-    """Preconditioned MINRES (Paige-Saunders) for symmetric A and SPD M."""
+    """MINRES (Paige and Saunders, SIAM J. Numer. Anal. 12, 1975) for a symmetric,
+    possibly indefinite or singular but consistent A, with a symmetric positive definite
+    preconditioner M (z = M(r)), in its plainest form: the Lanczos process and, at every
+    step, an explicit least-squares solve of the small tridiagonal system.
+
+    Write M = C C^T.  MINRES for C^T A C y = C^T b, x = C y, builds the Lanczos vectors
+    q_j of C^T A C; this routine keeps w_j = C^-T q_j (residual space) and u_j = C q_j =
+    M w_j (solution space), so C itself is never needed:
+        beta_1 = sqrt(b . M b),  w_1 = b / beta_1,  u_1 = M b / beta_1,
+        v = A u_j - beta_j w_(j-1),  alpha_j = u_j . v,  v -= alpha_j w_j,
+        beta_(j+1) = sqrt(v . M v),  w_(j+1) = v / beta_(j+1),  u_(j+1) = M v / beta_(j+1).
+    Then A U_k = W_(k+1) T_k with T_k the (k+1) x k tridiagonal matrix (alpha on the
+    diagonal, beta_(j+1) below and above it), and the iterate x_k = U_k t with
+    t = argmin ||beta_1 e_1 - T_k t||_2 minimises the M-norm of b - A x over the
+    preconditioned Krylov space.  The stopping test is eq. (4.3) on the true residual
+    b - A x_k, recomputed from x_k at every step (its 2-norm need not decrease
+    monotonically).  A step with beta_(j+1) = 0 has reached an invariant space, where
+    x_k solves the system."""
     n = b.size
     bn = np.linalg.norm(b)
     x = np.zeros(n)
-    r1 = b.copy()
-    y = M(r1)
-    beta1 = np.sqrt(r1 @ y)
     hist = [1.0]
-    if beta1 == 0:
+    mb = M(b)
+    beta1 = float(np.sqrt(b @ mb))
+    if beta1 == 0.0:
         return SolveResult(x, 0, hist, True)
-    oldb, beta, dbar, epsln, phibar = 0.0, beta1, 0.0, 0.0, beta1
-    cs, sn = -1.0, 0.0
-    w = np.zeros(n)
-    w2 = np.zeros(n)
-    r2 = r1.copy()
-    for it in range(1, maxit + 1):
-        s = 1.0 / beta
-        v = s * y
-        y = A @ v
-        if it >= 2:
-            y = y - (beta / oldb) * r1
-        alfa = v @ y
-        y = y - (alfa / beta) * r2
-        r1, r2 = r2, y
-        y = M(r2)
-        oldb, beta = beta, np.sqrt(r2 @ y)
-        oldeps = epsln
-        delta = cs * dbar + sn * alfa
-        gbar = sn * dbar - cs * alfa
-        epsln = sn * beta
-        dbar = -cs * beta
-        gamma = max(np.hypot(gbar, beta), 1e-300)
-        cs, sn = gbar / gamma, beta / gamma
-        phi = cs * phibar
-        phibar = sn * phibar
-        w1, w2 = w2, w
-        w = (v - oldeps * w1 - delta * w2) / gamma
-        x = x + phi * w
+    U = np.zeros((n, 16))
+    alphas: List[float] = []
+    betas: List[float] = [beta1]           # betas[j] = beta_(j+1)
+    w_prev = np.zeros(n)
+    w = b / beta1
+    u = mb / beta1
+    for k in range(1, maxit + 1):
+        if k > U.shape[1]:
+            U = np.concatenate([U, np.zeros_like(U)], axis=1)
+        U[:, k - 1] = u
+        v = A @ u - (betas[k - 1] * w_prev if k > 1 else 0.0)
+        a = float(u @ v)
+        v = v - a * w
+        mv = M(v)
+        bnext = float(np.sqrt(max(v @ mv, 0.0)))
+        alphas.append(a)
+        betas.append(bnext)
+        T = np.zeros((k + 1, k))
+        for j in range(k):
+            T[j, j] = alphas[j]
+            T[j + 1, j] = betas[j + 1]
+            if j > 0:
+                T[j - 1, j] = betas[j]
+        rhs = np.zeros(k + 1)
+        rhs[0] = beta1
+        t = np.linalg.lstsq(T, rhs, rcond=None)[0]
+        x = U[:, :k] @ t
         rel = _rel(b - A @ x, bn)
         hist.append(rel)
-        if rel <= tol:
-            return SolveResult(x, it, hist, True)
+        if rel <= tol or bnext == 0.0:
+            return SolveResult(x, k, hist, rel <= tol)
+        w_prev, w, u = w, v / bnext, mv / bnext
     return SolveResult(x, maxit, hist, False)

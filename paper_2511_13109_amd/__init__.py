@@ -2,11 +2,8 @@
 hand-written HIP kernels behind a C ABI (include/agca.h).
 
 Paper: "Large-scale multigrid with adaptive Galerkin coarsening" (Boehm, Kohl,
-Koestler, Ruede).  ``Hierarchy`` is the entry point; ``grid`` holds the
-canonical numbering of the refined lattice.
+Koestler, Ruede).  ``Hierarchy`` is the entry point.
 """
-
-from . import grid  # noqa: F401
 
 
 def __getattr__(name):

@@ -54,7 +54,8 @@ SCHUR_MASS, SCHUR_BFBT = 0, 1
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("floor_limited", C.c_int32),
                 ("replacements", C.c_int32), ("rel_residual", C.c_double),
-                ("recursive_rel_residual", C.c_double), ("seconds", C.c_double),
+                ("recursive_rel_residual", C.c_double), ("floor_estimate", C.c_double),
+                ("seconds", C.c_double),
                 ("history", C.c_double * MAX_HISTORY)]
 
 
@@ -86,6 +87,7 @@ SIGNATURES = {
     "agca_cast": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64]),
     "agca_solve": (C.c_int32, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
                                C.POINTER(SolveStats)]),
+    "agca_residual_floor": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "agca_grad_log_nu": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "agca_load_vector": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "agca_stokes_div": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),

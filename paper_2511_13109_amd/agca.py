@@ -250,12 +250,20 @@ class Hierarchy:
         stats = {"iterations": st.iterations, "converged": bool(st.converged),
                  "floor_limited": bool(st.floor_limited), "replacements": st.replacements,
                  "rel_residual": st.rel_residual,
-                 "recursive_rel_residual": st.recursive_rel_residual, "seconds": st.seconds,
+                 "recursive_rel_residual": st.recursive_rel_residual,
+                 "floor_estimate": st.floor_estimate, "seconds": st.seconds,
                  "history": list(st.history[:min(st.iterations + 1, _lib.MAX_HISTORY)])
                  if record_history else [], "status": rc}
         if rc != _lib.AGCA_OK and (rc != _lib.AGCA_E_NOCONV or raise_on_noconv):
             check(rc, "agca_solve")
         return x, stats
+
+    def residual_floor(self, b: torch.Tensor, x: torch.Tensor) -> float:
+        """Rounding floor rho of the relative residual of x (agca_residual_floor)."""
+        out = C.c_double()
+        check(self._lib.agca_residual_floor(self._h, _ptr(b), _ptr(x), C.byref(out)),
+              "agca_residual_floor")
+        return out.value
 
     def grad_log_nu(self, u: torch.Tensor, w: torch.Tensor, g: Optional[torch.Tensor] = None):
         g = torch.empty(6 * self.n(self.L) ** 3, dtype=torch.float64, device=u.device) if g is None else g
@@ -329,7 +337,7 @@ class Stokes:
 
 def coefficients_from_field(field, L: int, device="cuda") -> List[torch.Tensor]:
     """Sample a coefficient field at the element centroids of every level 0..L (host evaluation)."""
-    from .grid import element_centroids
+    from workloads.lattice import element_centroids
     out = []
     for l in range(L + 1):
         out.append(torch.from_numpy(np.ascontiguousarray(field.nu(element_centroids(l)))).to(device))

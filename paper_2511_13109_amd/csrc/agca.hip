@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "cube_math.h"
+#include "stop_rule.h"
 #include "internal.h"
 
 using namespace agca;
@@ -402,11 +403,54 @@ int32_t reduce_to(agca_hier* h, const double* partial, int nb, int slot) {
     HIPCHK(h, launch_sum_partials(partial, nb, h->red + slot, h->st));
     return AGCA_OK;
 }
-// copy red[0..k) to the host and wait
-int32_t fetch(agca_hier* h, int k, double* out) {
-    HIPCHK(h, hipMemcpyAsync(h->red_host, h->red, sizeof(double) * k, hipMemcpyDeviceToHost, h->st));
+// copy red[first .. first + k) to the host and wait
+int32_t fetch(agca_hier* h, int k, double* out, int first = 0) {
+    HIPCHK(h, hipMemcpyAsync(h->red_host + first, h->red + first, sizeof(double) * k,
+                             hipMemcpyDeviceToHost, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
-    for (int i = 0; i < k; ++i) out[i] = h->red_host[i];
+    for (int i = 0; i < k; ++i) out[i] = h->red_host[first + i];
+    return AGCA_OK;
+}
+
+// reduction slots of the two helpers below, clear of the solvers' scalars (slots 0..4)
+constexpr int kSlotFloor = 8;
+
+// ||b||_2 over the free dofs of a finest-level vector (boundary slots are not part of it)
+int32_t interior_norm(agca_hier* h, const double* b, double* out) {
+    const int L = h->cfg.L;
+    HIPCHK(h, launch_interior_dot<double>(h->cfg.ncomp, h->lv[L].n, b, b, h->partial, h->nb_partial,
+                                          h->st));
+    TRY(reduce_to(h, h->partial, h->nb_partial, kSlotFloor));
+    double v = 0.0;
+    TRY(fetch(h, 1, &v, kSlotFloor));
+    *out = std::sqrt(v);
+    return AGCA_OK;
+}
+
+// Rounding floor of the relative residual of x (eq. (4.3) evaluated in FP64):
+//   rho = u || |b| + sum_e |A_e| |x_e| ||_2 / ||b||_2  over the free dofs, u = 2^-53.
+// Rounding every entry of x once more moves b - A x by at most u sum_e |A_e| |x_e|
+// entrywise, so no solver can certify a relative residual much below rho for an FP64
+// iterate near x.
+constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
+// the two sums: s_sq = sum (|b_i| + (sum_e |A_e||x_e|)_i)^2, b_sq = sum b_i^2 (free dofs)
+int32_t floor_sums(agca_hier* h, const double* b, const double* x, double* s_sq, double* b_sq) {
+    const int L = h->cfg.L;
+    const Level& lv = h->lv[L];
+    HIPCHK(h, launch_floor_terms(h->cfg.ncomp, lv.n, lv.nu64, 1.0 / (6.0 * lv.n), b, x, h->partial,
+                                 h->nb_partial, h->st));
+    TRY(reduce_to(h, h->partial, h->nb_partial, kSlotFloor));
+    TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, kSlotFloor + 1));
+    double v[2] = {0.0, 0.0};
+    TRY(fetch(h, 2, v, kSlotFloor));
+    *s_sq = v[0];
+    *b_sq = v[1];
+    return AGCA_OK;
+}
+int32_t residual_floor(agca_hier* h, const double* b, const double* x, double* rho) {
+    double s_sq = 0.0, b_sq = 0.0;
+    TRY(floor_sums(h, b, x, &s_sq, &b_sq));
+    *rho = b_sq > 0.0 ? kUnitRoundoff * std::sqrt(s_sq) / std::sqrt(b_sq) : 0.0;
     return AGCA_OK;
 }
 
@@ -1147,6 +1191,12 @@ int32_t agca_cast(agca_hier* h, int32_t from, int32_t to, const void* src, void*
 
 int64_t agca_device_bytes(const agca_hier* h) { return h ? h->bytes : 0; }
 
+int32_t agca_residual_floor(agca_hier* h, const double* b, const double* x, double* rho) {
+    TRY(check_level(h, 0));
+    if (!b || !x || !rho) return fail(AGCA_E_INVALID, "null pointer");
+    return residual_floor(h, b, x, rho);
+}
+
 int32_t agca_grad_log_nu(agca_hier* h, const double* u, const double* w, double* g) {
     TRY(check_level(h, 0));
     if (!u || !w || !g) return fail(AGCA_E_INVALID, "null pointer");
@@ -1178,6 +1228,17 @@ static int32_t precondition(agca_hier* h, const double* r, double* z) {
     return AGCA_OK;
 }
 
+// Residual replacement and the stopping rule of the Krylov solvers.  The recurrence's
+// residual drifts away from the true residual b - A x by the rounding of every update,
+// so the true residual replaces it whenever the recurrence has fallen by kReplaceEvery
+// since the last replacement (the search direction is kept: no restart; van der Vorst
+// and Ye, SIAM J. Sci. Comput. 22, 2000), and when it reaches tol.  If the true
+// residual is then still above tol the iteration continues from it; it ends at the
+// rounding floor (floor_limited) only under the rule of stop_rule.h (the true residual
+// stopped improving and lies within kFloorFactor of max(tol, rho), rho the rounding
+// floor of the iterate, residual_floor).  A stall above that is AGCA_E_NOCONV.
+constexpr double kReplaceEvery = 0.1;
+
 int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, double* x,
                    agca_solve_stats* stats) {
     TRY(check_level(h, 0));
@@ -1193,9 +1254,8 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     auto t0 = std::chrono::steady_clock::now();
     if (!o->use_x0) HIPCHK(h, launch_fill<double>(cnt, 0.0, x, h->st));
     HIPCHK(h, launch_zero_boundary<double>(h->cfg.ncomp, h->lv[L].n, x, h->st));
-    double bb = 0.0;
-    TRY(do_dot<double>(h, b, b, cnt, &bb));
-    const double bn = std::sqrt(bb);
+    double bn = 0.0;
+    TRY(interior_norm(h, b, &bn));
     if (!std::isfinite(bn)) return fail(AGCA_E_NUMERIC, "non-finite right-hand side");
     TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
     double rr = 0.0;
@@ -1207,26 +1267,10 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     };
     record(rel);
     int it = 0, replacements = 0;
-    bool floor_limited = false;
-    double last_true = rel;
+    bool floor_limited = false, stalled = false;
+    EndChecks ends;
+    double rho = 0.0;
     int32_t status = AGCA_OK;
-    // called when the recurrence reached tol: recompute the true residual into r and decide
-    // whether to stop (returns true) or to restart from it
-    auto true_check = [&](bool* stop) -> int32_t {
-        TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
-        TRY(do_dot<double>(h, r, r, cnt, &rr));
-        const double rel_true = std::sqrt(rr) / bn;
-        *stop = true;
-        if (rel_true <= o->tol) return AGCA_OK;
-        if (replacements >= 3 || rel_true > 0.5 * last_true) {
-            floor_limited = true;
-            return AGCA_OK;
-        }
-        last_true = rel_true;
-        ++replacements;
-        *stop = false;
-        return AGCA_OK;
-    };
     double rec_rel = rel;
     if (bn == 0.0) {
         HIPCHK(h, launch_fill<double>(cnt, 0.0, x, h->st));
@@ -1261,17 +1305,14 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
             };
             constexpr int PQ = 0, RR = 1, ZR = 2, ZQ = 3, RZ = 4;
             double* red = h->red;
-            bool restart = true;
             double tmp[5];
+            double anchor = rel;  // true residual at the last replacement
+            if (mixed) HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, r, r32, cnt, h->st));
+            TRY(vcycle());
+            HIPCHK(h, dots(nullptr));
+            TRY(reduce_to(h, h->partial, h->nb_partial, RZ));
+            HIPCHK(h, direction(0.0));
             while (it < o->max_iter) {
-                if (restart) {
-                    if (mixed) HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, r, r32, cnt, h->st));
-                    TRY(vcycle());
-                    HIPCHK(h, dots(nullptr));
-                    TRY(reduce_to(h, h->partial, h->nb_partial, RZ));
-                    HIPCHK(h, direction(0.0));
-                    restart = false;
-                }
                 // q = A p fused with p . q
                 int nbq = 0;
                 HIPCHK(h, launch_cube_dot(h->cfg.ncomp, level_op<double>(h, L), p, q, h->partial, &nbq,
@@ -1298,12 +1339,28 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     status = fail(AGCA_E_NUMERIC, "residual diverged");
                     break;
                 }
-                if (rel <= o->tol) {
-                    bool stop = false;
-                    TRY(true_check(&stop));
-                    if (stop) break;
-                    restart = true;
-                    continue;
+                if (rel <= o->tol || rel <= kReplaceEvery * anchor) {
+                    // residual replacement: r = b - A x (and its FP32 copy)
+                    TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
+                    TRY(do_dot<double>(h, r, r, cnt, &rr));
+                    if (mixed) HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, r, r32, cnt, h->st));
+                    const double rel_true = std::sqrt(rr) / bn;
+                    ++replacements;
+                    anchor = rel_true;
+                    if (rel <= o->tol) {
+                        if (rel_true <= o->tol) {
+                            rel = rel_true;
+                            break;
+                        }
+                        if (ends.stagnated(rel_true)) {
+                            TRY(residual_floor(h, b, x, &rho));
+                            rel = rel_true;
+                            floor_limited = at_floor(rel_true, o->tol, rho);
+                            stalled = !floor_limited;
+                            break;
+                        }
+                    }
+                    rel = rec_rel = rel_true;
                 }
                 TRY(vcycle());
                 // z . r and, for FCG, z . q in one pass
@@ -1332,17 +1389,22 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
             }
         }
     }
-    // final FP64 residual with FP64 coefficients
+    // final FP64 residual with FP64 coefficients, and the rounding floor of x
     TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
     TRY(do_dot<double>(h, r, r, cnt, &rr));
     stats->rel_residual = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+    if (bn > 0) TRY(residual_floor(h, b, x, &rho));
+    stats->floor_estimate = rho;
     stats->recursive_rel_residual = rec_rel;
     stats->iterations = it;
     stats->replacements = replacements;
     stats->converged = stats->rel_residual <= o->tol || bn == 0.0;
-    stats->floor_limited = (!stats->converged && floor_limited) ? 1 : 0;
+    stats->floor_limited = (!stats->converged && floor_limited && at_floor(stats->rel_residual, o->tol, rho)) ? 1 : 0;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (status != AGCA_OK) return status;
+    if (stalled && !stats->converged)
+        return fail(AGCA_E_NOCONV, "the true residual stalled above " + std::to_string(kFloorFactor) +
+                                       " x max(tol, rounding floor)");
     if (!stats->converged && !stats->floor_limited)
         return fail(AGCA_E_NOCONV, "no convergence within max_iter");
     return AGCA_OK;
@@ -1566,7 +1628,7 @@ static int32_t stokes_residual(agca_hier* h, const double* b, const double* x, d
 constexpr double kDgks = 0.1;
 static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const double* b, double* x,
                              double bn, double* rel_out, int* it_out, std::vector<double>& hist,
-                             bool* floor_out) {
+                             bool* floor_out, double* rho_out) {
     const int64_t tot = stokes_dims(h).tot;
     const int m = o->restart;
     TRY(stokes_work(h, 2 * (int64_t)m + 3));
@@ -1664,14 +1726,22 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
         hist.back() = rel;
         if (rel <= o->tol) break;
         // rounding floor: the cycle's recurrence reached the tolerance but the true
-        // residual did not, it is within 10x of the tolerance and less than 5 % better
-        // than four restart cycles ago (the true residual of an FP64 iterate stagnates
-        // there while each cycle's estimate keeps converging)
+        // residual did not, it is less than 5 % better than four restart cycles ago
+        // (the true residual of an FP64 iterate stagnates there while each cycle's
+        // estimate keeps converging), and it is within kFloorFactor of max(tol, rho_A),
+        // rho_A the rounding floor of the velocity block alone (the residual_floor
+        // terms of A and the velocity right-hand side over the whole system's norm: a
+        // lower bound of the full system's floor, which adds the B and B^T terms)
         cycle_res.push_back(rel);
         const size_t c = cycle_res.size();
-        if (estimate_reached && c >= 5 && rel < 10.0 * o->tol && rel > 0.95 * cycle_res[c - 5]) {
-            *floor_out = true;
-            break;
+        if (estimate_reached && c >= 5 && rel > 0.95 * cycle_res[c - 5]) {
+            double s_sq = 0.0, b_sq = 0.0;
+            TRY(floor_sums(h, b, x, &s_sq, &b_sq));
+            *rho_out = kUnitRoundoff * std::sqrt(s_sq) / bn;
+            if (at_floor(rel, o->tol, *rho_out)) {
+                *floor_out = true;
+                break;
+            }
         }
     }
     *rel_out = rel;
@@ -1679,77 +1749,101 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
     return AGCA_OK;
 }
 
-// Preconditioned MINRES (Paige-Saunders) with the true residual checked every step.
+// MINRES (Paige and Saunders, SIAM J. Numer. Anal. 12, 1975) with the block-diagonal
+// preconditioner P (SPD), derived here as follows.  With P = C C^T, MINRES for
+// C^T K C y = C^T b runs the Lanczos process on C^T K C; its vectors q_j are kept as
+// w_j = C^-T q_j (residual space) and u_j = C q_j = P w_j (solution space):
+//   v = K u_j - beta_j w_{j-1},  alpha_j = u_j . v,  v -= alpha_j w_j,
+//   beta_{j+1} = sqrt(v . P v),  w_{j+1} = v / beta_{j+1},  u_{j+1} = P v / beta_{j+1},
+// so that K U_k = W_{k+1} T_k, T_k tridiagonal ((k+1) x k).  The iterate x_k = U_k t_k
+// minimises ||beta_1 e_1 - T_k t||.  T_k is reduced to upper triangular R_k by Givens
+// rotations G_j = [[c_j, s_j], [-s_j, c_j]] on rows (j, j+1): column k holds beta_k,
+// alpha_k, beta_{k+1} in rows k-1, k, k+1; G_{k-2} turns (0, beta_k) into
+// (eps_k, c_{k-2} beta_k), G_{k-1} turns (c_{k-2} beta_k, alpha_k) into (sig_k, gam_k),
+// and G_k (c_k = gam_k / rho_k, s_k = beta_{k+1} / rho_k, rho_k = |(gam_k, beta_{k+1})|)
+// annihilates beta_{k+1}.  The same rotations take beta_1 e_1 to (tau_1 .. tau_k, gbar):
+// tau_k = c_k gbar, gbar <- -s_k gbar.  With the directions D_k = U_k R_k^-1,
+//   d_k = (u_k - sig_k d_{k-1} - eps_k d_{k-2}) / rho_k,   x_k = x_{k-1} + tau_k d_k.
+// The stopping test (eq. (4.3)) uses the true residual b - K x_k, recomputed at every
+// step (the method minimises the P^-1-norm of the residual, not its 2-norm).
 static int32_t stokes_minres(agca_hier* h, const agca_stokes_opts* o, const double* b, double* x,
                              double bn, double* rel_out, int* it_out, std::vector<double>& hist) {
     const int64_t tot = stokes_dims(h).tot;
     TRY(stokes_work(h, 8));
-    double* buf[8];
-    for (int i = 0; i < 8; ++i) buf[i] = h->st_work + (int64_t)i * tot;
-    double *r1 = buf[0], *r2 = buf[1], *y = buf[2], *v = buf[3], *w = buf[4], *w1 = buf[5],
-           *w2 = buf[6], *res = buf[7];
+    auto vecn = [&](int i) { return h->st_work + (int64_t)i * tot; };
+    double *w_prev = vecn(0), *w = vecn(1), *u = vecn(2), *v = vecn(3), *pv = vecn(4),
+           *d_last = vecn(5), *d_older = vecn(6), *res = vecn(7);
     HIPCHK(h, launch_fill<double>(tot, 0.0, x, h->st));
-    HIPCHK(h, launch_axpby<double>(tot, 1.0, b, 0.0, r1, h->st));
-    TRY(stokes_precond(h, r1, y));
-    double t = 0.0;
-    TRY(do_dot<double>(h, r1, y, tot, &t));
-    const double beta1 = std::sqrt(t);
     hist.push_back(1.0);
-    double rel = 1.0;
-    int it = 0;
+    *rel_out = 1.0;
+    *it_out = 0;
+    // beta_1 = sqrt(b . P b), w_1 = b / beta_1, u_1 = P b / beta_1
+    TRY(stokes_precond(h, b, pv));
+    double t = 0.0;
+    TRY(do_dot<double>(h, b, pv, tot, &t));
+    if (!(t >= 0.0) || !std::isfinite(t)) return fail(AGCA_E_NUMERIC, "MINRES: preconditioner is not positive");
+    const double beta1 = std::sqrt(t);
     if (beta1 == 0.0) {
         *rel_out = 0.0;
-        *it_out = 0;
         return AGCA_OK;
     }
-    double oldb = 0.0, beta = beta1, dbar = 0.0, epsln = 0.0, phibar = beta1, cs = -1.0, sn = 0.0;
-    HIPCHK(h, launch_fill<double>(tot, 0.0, w, h->st));
-    HIPCHK(h, launch_fill<double>(tot, 0.0, w2, h->st));
-    HIPCHK(h, launch_axpby<double>(tot, 1.0, r1, 0.0, r2, h->st));
-    for (it = 1; it <= o->max_iter; ++it) {
-        HIPCHK(h, launch_axpby<double>(tot, 1.0 / beta, y, 0.0, v, h->st));
-        TRY(stokes_apply(h, v, y));
-        if (it >= 2) HIPCHK(h, launch_axpby<double>(tot, -beta / oldb, r1, 1.0, y, h->st));
-        double alfa = 0.0;
-        TRY(do_dot<double>(h, v, y, tot, &alfa));
-        HIPCHK(h, launch_axpby<double>(tot, -alfa / beta, r2, 1.0, y, h->st));
-        // r1 <- r2, r2 <- y, y <- preconditioned r2 (into the old r1 storage)
-        double* old_r1 = r1;
-        r1 = r2;
-        r2 = y;
-        y = old_r1;
-        TRY(stokes_precond(h, r2, y));
-        oldb = beta;
-        TRY(do_dot<double>(h, r2, y, tot, &t));
-        beta = std::sqrt(t);
-        const double oldeps = epsln;
-        const double delta = cs * dbar + sn * alfa;
-        const double gbar = sn * dbar - cs * alfa;
-        epsln = sn * beta;
-        dbar = -cs * beta;
-        const double gamma = std::max(std::hypot(gbar, beta), 1e-300);
-        cs = gbar / gamma;
-        sn = beta / gamma;
-        const double phi = cs * phibar;
-        phibar = sn * phibar;
-        // w1 <- w2, w2 <- w, w <- (v - oldeps w1 - delta w2) / gamma (into the old w1 storage)
-        double* old_w1 = w1;
-        w1 = w2;
-        w2 = w;
-        w = old_w1;
-        HIPCHK(h, launch_axpby<double>(tot, 1.0 / gamma, v, 0.0, w, h->st));
-        HIPCHK(h, launch_axpby<double>(tot, -oldeps / gamma, w1, 1.0, w, h->st));
-        HIPCHK(h, launch_axpby<double>(tot, -delta / gamma, w2, 1.0, w, h->st));
-        HIPCHK(h, launch_axpby<double>(tot, phi, w, 1.0, x, h->st));
+    HIPCHK(h, launch_axpby<double>(tot, 1.0 / beta1, b, 0.0, w, h->st));
+    HIPCHK(h, launch_axpby<double>(tot, 1.0 / beta1, pv, 0.0, u, h->st));
+    HIPCHK(h, launch_fill<double>(tot, 0.0, d_last, h->st));
+    HIPCHK(h, launch_fill<double>(tot, 0.0, d_older, h->st));
+    double beta = beta1;            // beta_k
+    double c1 = 1.0, s1 = 0.0;      // rotation k-1
+    double c2 = 1.0, s2 = 0.0;      // rotation k-2
+    double gbar = beta1;            // last entry of the rotated right-hand side
+    double rel = 1.0;
+    int k = 0;
+    while (k < o->max_iter) {
+        ++k;
+        // Lanczos: v = K u_k - beta_k w_{k-1} - alpha_k w_k, P v, beta_{k+1}
+        TRY(stokes_apply(h, u, v));
+        if (k > 1) HIPCHK(h, launch_axpby<double>(tot, -beta, w_prev, 1.0, v, h->st));
+        double alpha = 0.0;
+        TRY(do_dot<double>(h, u, v, tot, &alpha));
+        HIPCHK(h, launch_axpby<double>(tot, -alpha, w, 1.0, v, h->st));
+        TRY(stokes_precond(h, v, pv));
+        TRY(do_dot<double>(h, v, pv, tot, &t));
+        if (!std::isfinite(t) || !std::isfinite(alpha)) return fail(AGCA_E_NUMERIC, "MINRES breakdown");
+        // v . P v can only vanish (or lose its sign to rounding) in an invariant space
+        const double beta_next = t > 0.0 ? std::sqrt(t) : 0.0;
+        // QR update of the new column (beta_k, alpha_k, beta_{k+1})
+        const double bk = k > 1 ? beta : 0.0;
+        const double eps = s2 * bk;
+        const double bt = c2 * bk;
+        const double sig = c1 * bt + s1 * alpha;
+        const double gam = -s1 * bt + c1 * alpha;
+        const double rho = std::hypot(gam, beta_next);
+        if (!(rho > 0.0)) return fail(AGCA_E_NUMERIC, "MINRES: singular tridiagonal factor");
+        const double c = gam / rho, s = beta_next / rho;
+        const double tau = c * gbar;
+        gbar = -s * gbar;
+        // d_k = (u_k - sig d_{k-1} - eps d_{k-2}) / rho, written over d_{k-2}
+        HIPCHK(h, launch_axpby<double>(tot, 1.0 / rho, u, -eps / rho, d_older, h->st));
+        HIPCHK(h, launch_axpby<double>(tot, -sig / rho, d_last, 1.0, d_older, h->st));
+        std::swap(d_last, d_older);
+        HIPCHK(h, launch_axpby<double>(tot, tau, d_last, 1.0, x, h->st));
+        c2 = c1;
+        s2 = s1;
+        c1 = c;
+        s1 = s;
         TRY(stokes_residual(h, b, x, res));
         TRY(stokes_norm(h, res, &rel));
         rel /= bn;
         hist.push_back(rel);
         if (!std::isfinite(rel)) return fail(AGCA_E_NUMERIC, "MINRES breakdown");
-        if (rel <= o->tol) break;
+        if (rel <= o->tol || beta_next == 0.0) break;
+        // advance the Lanczos vectors: w_{k+1} into the buffer of w_{k-1}, u_{k+1} over u_k
+        HIPCHK(h, launch_axpby<double>(tot, 1.0 / beta_next, v, 0.0, w_prev, h->st));
+        std::swap(w_prev, w);
+        HIPCHK(h, launch_axpby<double>(tot, 1.0 / beta_next, pv, 0.0, u, h->st));
+        beta = beta_next;
     }
     *rel_out = rel;
-    *it_out = std::min(it, o->max_iter);
+    *it_out = k;
     return AGCA_OK;
 }
 
@@ -1818,12 +1912,13 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     double rel = 0.0;
     int it = 0;
     bool floor_limited = false;
+    double rho_a = 0.0;
     if (bn == 0.0) {
         HIPCHK(h, launch_fill<double>(d.tot, 0.0, xvec, h->st));
         hist.push_back(0.0);
     } else {
         const int32_t rc = (o->solver == AGCA_STOKES_FGMRES)
-                               ? stokes_fgmres(h, o, bvec, xvec, bn, &rel, &it, hist, &floor_limited)
+                               ? stokes_fgmres(h, o, bvec, xvec, bn, &rel, &it, hist, &floor_limited, &rho_a)
                                : stokes_minres(h, o, bvec, xvec, bn, &rel, &it, hist);
         h->st_tri = nullptr;
         h->st_schur_iters = 0;
@@ -1847,6 +1942,7 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     stats->recursive_rel_residual = hist.empty() ? rel : hist.back();
     stats->converged = rel <= o->tol || bn == 0.0;
     stats->floor_limited = (!stats->converged && floor_limited) ? 1 : 0;
+    stats->floor_estimate = rho_a;
     for (size_t i = 0; i < hist.size() && i < (size_t)AGCA_MAX_HISTORY; ++i)
         if (o->record_history) stats->history[i] = hist[i];
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -199,6 +199,14 @@ hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const dou
                            hipStream_t st);
 
 // adjoint gradient and load vector (finest level)
+// rounding-floor terms of the residual: partial[0..nblocks) = sums of (|b_i| + (sum_e |A_e||x_e|)_i)^2,
+// partial[nblocks..2 nblocks) = sums of b_i^2, both over free dofs (finest level, FP64)
+hipError_t launch_floor_terms(int ncomp, int n, const double* nu, double scale, const double* b,
+                              const double* x, double* partial, int nblocks, hipStream_t st);
+// partial sums of x . y over the free dofs of a level vector
+template <typename T>
+hipError_t launch_interior_dot(int ncomp, int n, const T* x, const T* y, double* partial, int nblocks,
+                               hipStream_t st);
 hipError_t launch_grad(int ncomp, int n, const double* nu, double scale, const double* u,
                        const double* w, double* g, hipStream_t st);
 hipError_t launch_load_vector(int ncomp, int n, const double* f, double vol4, double* b,

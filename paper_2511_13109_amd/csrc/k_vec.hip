@@ -76,8 +76,16 @@ k_prolong_add(int nf, const T* __restrict__ ec, T* __restrict__ xf) {
         b[c] = ec[c * Nc + hi];
         v[c] = xf[c * Nf + p];
     }
+    // coarse boundary slots are not part of the input (they hold 0 in every vector the
+    // library writes, but a caller's may not): a coarse endpoint on the boundary counts 0
+    auto on_bd = [nc](int cx, int cy, int cz) {
+        return cx == 0 || cy == 0 || cz == 0 || cx == nc || cy == nc || cz == nc;
+    };
+    const bool lo_bd = on_bd((x - dx) >> 1, (y - dy) >> 1, (z - dz) >> 1);
+    const bool hi_bd = on_bd((x + dx) >> 1, (y + dy) >> 1, (z + dz) >> 1);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) xf[c * Nf + p] = v[c] + T(0.5) * (a[c] + b[c]);
+    for (int c = 0; c < NC; ++c)
+        xf[c * Nf + p] = v[c] + T(0.5) * ((lo_bd ? T(0) : a[c]) + (hi_bd ? T(0) : b[c]));
 }
 
 // level 0 has n = 2: a single free node (1,1,1), id 13 of 27
@@ -355,6 +363,106 @@ k_count_invalid(const double* __restrict__ v, int64_t n, int* __restrict__ count
 }
 
 // ---------------------------------------------------------------------------
+// Rounding floor of the residual (stopping test of eq. (4.3)).  Replacing every entry of
+// x by a value within relative u = 2^-53 of it (one FP64 rounding) moves b - A x by at
+// most u (sum_e |A_e| |x_e|) entrywise, and forming b - A x element by element adds
+// errors of the same order; per free dof i this kernel forms
+//   s_i = |b_i| + (sum_e |A_e| |x_e|)_i
+// (|A_e| the entrywise absolute element matrix, nu_e h/6 times the absolute unit matrix)
+// and the workgroup's partial sums of s_i^2, and also of b_i^2 over free dofs.  One
+// thread per node in a grid-stride loop over a fixed grid: a fixed summation order.
+// ---------------------------------------------------------------------------
+// vertex index (0..3) of cell corner k on the path of simplex s, -1 if it is not on it
+AGCA_HDC constexpr int path_vertex(int s, int k) {
+    return path_corner(s, 0) == k ? 0
+         : path_corner(s, 1) == k ? 1
+         : path_corner(s, 2) == k ? 2
+         : path_corner(s, 3) == k ? 3 : -1;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(NT)
+k_floor_terms(int n, const double* __restrict__ nu, double scale, const double* __restrict__ b,
+              const double* __restrict__ x, double* __restrict__ partial) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1, cells = (int64_t)n * n * n;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    double acc_s = 0.0, acc_b = 0.0;
+    for (int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x; p < N; p += stride) {
+        int px, py, pz;
+        node_coords(p, n, px, py, pz);
+        if (px == 0 || py == 0 || pz == 0 || px == n || py == n || pz == n) continue;
+        // |x| on the 3 x 3 x 3 nodes around p (boundary slots count 0)
+        double ax[27][NC];
+#pragma unroll
+        for (int j = 0; j < 27; ++j) {
+            const int qx = px + j % 3 - 1, qy = py + (j / 3) % 3 - 1, qz = pz + j / 9 - 1;
+            const bool bd = qx == 0 || qy == 0 || qz == 0 || qx == n || qy == n || qz == n;
+            const int64_t q = qx + n1 * (qy + n1 * (int64_t)qz);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ax[j][c] = bd ? 0.0 : fabs(x[c * N + q]);
+        }
+        double s[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s[c] = 0.0;
+        // p is corner k of the cell whose minimum corner is p - offset(k)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
+            const int64_t cell = (px - kx) + (int64_t)n * ((py - ky) + (int64_t)n * (pz - kz));
+#pragma unroll
+            for (int sx = 0; sx < 6; ++sx) {
+                const int a = path_vertex(sx, k);
+                if (a < 0) continue;
+                const double w = nu[elem_slot(sx, cell, cells)] * scale;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int bv = 0; bv < 4; ++bv) {
+                        const int m = path_corner(sx, bv);
+                        // node of corner m relative to p, in the 3 x 3 x 3 block
+                        const int j = ((m & 1) - kx + 1) + 3 * (((m >> 1) & 1) - ky + 1) +
+                                      9 * ((m >> 2) - kz + 1);
+#pragma unroll
+                        for (int d = 0; d < NC; ++d) {
+                            const int e = elem_entry(NC, sx, c, a, d, bv);
+                            t += (double)(e < 0 ? -e : e) * ax[j][d];
+                        }
+                    }
+                    s[c] = fma(w, t, s[c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double bi = b[c * N + p];
+            const double si = fabs(bi) + s[c];
+            acc_s = fma(si, si, acc_s);
+            acc_b = fma(bi, bi, acc_b);
+        }
+    }
+    block_sum_store(acc_s, partial + blockIdx.x);
+    block_sum_store(acc_b, partial + gridDim.x + blockIdx.x);
+}
+
+// partial sums of x . y over the free dofs only (boundary slots are not part of a vector)
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_interior_dot(int ncomp, int n, const T* __restrict__ x, const T* __restrict__ y,
+               double* __restrict__ partial) {
+    const int64_t n1 = n + 1, N = n1 * n1 * n1;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    double acc = 0.0;
+    for (int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x; p < N; p += stride) {
+        int px, py, pz;
+        node_coords(p, n, px, py, pz);
+        if (px == 0 || py == 0 || pz == 0 || px == n || py == n || pz == n) continue;
+        for (int c = 0; c < ncomp; ++c) acc += (double)x[c * N + p] * (double)y[c * N + p];
+    }
+    block_sum_store(acc, partial + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint gradient g_e = -w_e^T A_e u_e = -(nu_e h/6) * energy(u_e, w_e), one
 // thread per cell (6 simplices, 6 consecutive outputs).
 // ---------------------------------------------------------------------------
@@ -589,6 +697,26 @@ hipError_t launch_to_internal(int64_t cells, const double* by_id, double* intern
                        internal, exponentiate ? 1 : 0);
     return hipGetLastError();
 }
+hipError_t launch_floor_terms(int ncomp, int n, const double* nu, double scale, const double* b,
+                              const double* x, double* partial, int nblocks, hipStream_t st) {
+    if (!nu || !b || !x || !partial || nblocks <= 0 || n < 2) return hipErrorInvalidValue;
+    if (ncomp == 1)
+        hipLaunchKernelGGL(k_floor_terms<1>, dim3(nblocks), dim3(NT), 0, st, n, nu, scale, b, x, partial);
+    else
+        hipLaunchKernelGGL(k_floor_terms<3>, dim3(nblocks), dim3(NT), 0, st, n, nu, scale, b, x, partial);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_interior_dot(int ncomp, int n, const T* x, const T* y, double* partial, int nblocks,
+                               hipStream_t st) {
+    if (!x || !y || !partial || nblocks <= 0 || n < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_interior_dot<T>, dim3(nblocks), dim3(NT), 0, st, ncomp, n, x, y, partial);
+    return hipGetLastError();
+}
+template hipError_t launch_interior_dot<double>(int, int, const double*, const double*, double*, int,
+                                                hipStream_t);
+template hipError_t launch_interior_dot<float>(int, int, const float*, const float*, double*, int,
+                                               hipStream_t);
 hipError_t launch_grad(int ncomp, int n, const double* nu, double scale, const double* u,
                        const double* w, double* g, hipStream_t st) {
     if (!nu || !u || !w || !g) return hipErrorInvalidValue;

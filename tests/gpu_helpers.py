@@ -58,3 +58,30 @@ def rel_err(a, b) -> float:
     b = np.asarray(b, dtype=np.float64)
     den = max(np.abs(b).max(), 1e-300)
     return float(np.abs(a - b).max() / den)
+
+
+def vcycle_extended(H, b_free: np.ndarray) -> np.ndarray:
+    """The oracle's V-cycle (mg.vcycle, the same steps) evaluated in 80-bit extended
+    precision: every level matrix, interpolation and diagonal converted to np.longdouble
+    (the 1x1 / 3x3 level-0 solve stays FP64).  Used to measure how far one FP64
+    V-cycle, the oracle's or the library's, lands from the exact one."""
+    import copy
+    E = copy.copy(H)
+    E.A = [a.astype(np.longdouble) for a in H.A]
+    E.P = [p.astype(np.longdouble) for p in H.P]
+    E.D = [d.astype(np.longdouble) for d in H.D]
+    return mg.vcycle(E, np.asarray(b_free, dtype=np.longdouble))
+
+
+def vcycle_errors(H, b_full: np.ndarray, x_gpu_full: np.ndarray):
+    """(library error, oracle FP64 error, tolerance) of one V-cycle, each relative to the
+    extended-precision V-cycle (max-norm).  The tolerance is 1e-12, or 4x the oracle's own
+    FP64 error where the cycle's cancellations make that larger: both are FP64
+    evaluations of the same steps, in different summation orders."""
+    m = interior_full(H, H.L)
+    ext = vcycle_extended(H, b_full[m])
+    x64 = mg.vcycle(H, b_full[m])
+    den = float(np.abs(ext).max())
+    e_gpu = float(np.abs(x_gpu_full[m] - ext).max()) / den
+    e_orc = float(np.abs(x64 - ext).max()) / den
+    return e_gpu, e_orc, max(1e-12, 4.0 * e_orc)

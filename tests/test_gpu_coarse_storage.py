@@ -3,7 +3,7 @@ C ABI.  With P1 functions an element's Galerkin block (eq. (2.7)) equals its DCA
 element matrix with the arithmetic mean of the finest coefficient over its
 descendants; the library then keeps that mean instead of the block.  The operators
 must still match the oracle's Galerkin products (which know nothing of the identity)
-to 1e-12 on every level, the V-cycle to 1e-11, and the 129^3 solves must match the
+to 1e-12 on every level, one V-cycle within 1e-12 of the extended-precision cycle (or 4x the oracle's own FP64 error), and the 129^3 solves must match the
 block-storing hierarchy.
 """
 
@@ -13,7 +13,7 @@ import torch
 
 from oracle import agca, mg
 
-from gpu_helpers import oracle_apply_full, oracle_case, rand_full, rel_err
+from gpu_helpers import oracle_apply_full, oracle_case, rand_full, rel_err, vcycle_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -45,9 +45,9 @@ def test_mean_storage_matches_oracle(mode, ncomp):
             assert rel_err(v, oracle_apply_full(H, l, u)) <= 1e-12, l
         b = rand_full(H, L, rng)
         z = G.vcycle(_dev(b)).cpu().numpy()
-        zr = np.zeros_like(b)
-        zr[H.free[L]] = mg.vcycle(H, b[H.free[L]])
-        assert rel_err(z, zr) <= 1e-11
+        e_gpu, e_orc, vtol = vcycle_errors(H, b, z)
+        print(f"[vcycle] library {e_gpu:.2e}, oracle FP64 {e_orc:.2e} (tolerance {vtol:.1e})", flush=True)
+        assert e_gpu < vtol
         with pytest.raises(Exception):
             G.blocks(1)
     finally:

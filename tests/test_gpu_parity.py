@@ -9,8 +9,9 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import adjoint, agca, fem, mesh, mg
-from tests.gpu_helpers import field_for, interior_full, oracle_apply_full, oracle_case, rand_full, rel_err
+from oracle import adjoint, agca, fem, floor, mesh, mg
+from tests.gpu_helpers import (field_for, interior_full, oracle_apply_full, oracle_case, rand_full, rel_err,
+                               vcycle_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -122,14 +123,14 @@ def test_transfers(pair):
 
 
 def test_vcycle(pair):
-    _, H, G = pair
+    case, H, G = pair
     rng = np.random.default_rng(3)
     b = rand_full(H, H.L, rng)
     x = G.vcycle(_dev(b)).cpu().numpy()
-    m = interior_full(H, H.L)
-    ref = np.zeros_like(b)
-    ref[m] = mg.vcycle(H, b[m])
-    assert rel_err(x, ref) < 1e-11
+    e_gpu, e_orc, tol = vcycle_errors(H, b, x)
+    print(f"[vcycle {case}] library {e_gpu:.2e}, oracle FP64 {e_orc:.2e} from the extended-precision "
+          f"cycle (tolerance {tol:.1e})", flush=True)
+    assert e_gpu < tol
 
 
 def test_dot_deterministic(pair):
@@ -160,13 +161,29 @@ def test_pcg_solve(pair):
     tol = 1e-10 if case[0] == "cube" else 1e-8
     ref = mg.pcg(H.A[H.L], b[m], lambda r: mg.vcycle(H, r), tol)
     x, st = G.solve(_dev(b), solver="pcg", tol=tol)
-    assert st["converged"] and st["rel_residual"] <= tol and st["replacements"] == 0
+    assert st["converged"] and st["rel_residual"] <= tol
     assert abs(st["iterations"] - ref.iterations) <= 1
+    _check_history(H, b, ref, st)
     xs = fem.restrict_free(H.ops_full[H.L], H.free[H.L])
     import scipy.sparse.linalg as spla
     exact = spla.splu(xs.tocsc()).solve(b[m])
     err = np.linalg.norm(x.cpu().numpy()[m] - exact) / np.linalg.norm(exact)
     assert err < 1e-4
+
+
+def _check_history(H, b_full, ref, st):
+    """PCG residual history against the oracle's, relative 1e-6, over the iterations whose
+    residual is at least 1e7 times the rounding floor of the oracle's solution (below
+    that the recurrences of the two FP64 runs, and the true residuals that replace the
+    library's recurrence, differ by rounding in the leading digits)."""
+    m = interior_full(H, H.L)
+    xr = np.zeros_like(b_full)
+    xr[m] = ref.x
+    rho = floor.residual_floor(H.levels[H.L], H.nu_levels[H.L], H.ncomp, b_full, xr)
+    hr = np.asarray(ref.history)
+    k = min(len(st["history"]), int(np.sum(hr >= 1e7 * rho)))
+    assert k >= 5, (k, rho)
+    assert np.allclose(st["history"][:k], hr[:k], rtol=1e-6, atol=0), (st["history"][:k], hr[:k])
 
 
 def test_adjoint_gradient_kernel(pair):
@@ -294,9 +311,10 @@ def test_chebyshev_smoother(case):
         b = rand_full(H, L, rng)
         m = interior_full(H, L)
         x = G.vcycle(_dev(b)).cpu().numpy()
-        ref = np.zeros_like(b)
-        ref[m] = mg.vcycle(H, b[m])
-        assert rel_err(x, ref) < 1e-11
+        e_gpu, e_orc, vtol = vcycle_errors(H, b, x)
+        print(f"[chebyshev {case}] V-cycle: library {e_gpu:.2e}, oracle FP64 {e_orc:.2e} "
+              f"(tolerance {vtol:.1e})", flush=True)
+        assert e_gpu < vtol
         lv = H.levels[L]
         f = field.force(mesh.centroids_canonical(lv), ncomp) if kind == "sinkers" else \
             np.ones(lv.tets.shape[0])
@@ -308,6 +326,7 @@ def test_chebyshev_smoother(case):
         print(f"[chebyshev {case}] PCG gpu {st['iterations']} oracle {r_ref.iterations} "
               f"(Jacobi V-cycle {r_jac.iterations})", flush=True)
         assert st["converged"] and abs(st["iterations"] - r_ref.iterations) <= 1
+        _check_history(H, bb, r_ref, st)
     finally:
         G.close()
     # the FP32 V-cycle with the Chebyshev smoother inside FCG reaches the FP64 residual

@@ -1,0 +1,104 @@
+"""The library's per-cell arithmetic (csrc/kuhn.h, cube_math.h, gca_math.h) and its
+solver stopping rule (csrc/stop_rule.h), compiled for the host with g++ and compared
+with the CPU oracle: element matrices of eq. (2.3) / (3.5), the element energy form of
+the adjoint gradient, the Galerkin blocks of the element-wise recursion (2.7), and the
+decisions of the rounding-floor stop."""
+
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import agca, mesh, transfer
+from workloads import Sinkers
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_2511_13109_amd", "csrc")
+# axis step order of the Kuhn simplex s (canonical element id, Section 2.1 refinement)
+ORDERS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    out = str(tmp_path_factory.mktemp("host") / "host_math")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Wno-unknown-pragmas", "-Werror", "-I", CSRC,
+                    os.path.join(HERE, "host_math.cpp"), "-o", out], check=True)
+    return out
+
+
+def _run(exe, text):
+    r = subprocess.run([exe], input=text, capture_output=True, text=True, check=True)
+    return np.array([float(v) for v in r.stdout.split()])
+
+
+@pytest.mark.parametrize("ncomp", [1, 3])
+def test_element_matrices(exe, ncomp):
+    M = 4 * ncomp
+    got = _run(exe, f"elem {ncomp}\n").reshape(6, M, M)
+    h = 0.125
+    for s, order in enumerate(ORDERS):
+        ref = agca.unit_element_matrix_path(h, ncomp, order)
+        assert np.abs(got[s] * h / 6.0 - ref).max() <= 1e-14 * np.abs(ref).max(), s
+
+
+@pytest.mark.parametrize("ncomp", [1, 3])
+def test_element_energy(exe, ncomp):
+    rng = np.random.default_rng(ncomp)
+    U = rng.standard_normal((8, ncomp))
+    W = rng.standard_normal((8, ncomp))
+    txt = f"energy {ncomp} " + " ".join(f"{v:.17g}" for v in np.concatenate([U.ravel(), W.ravel()]))
+    got = _run(exe, txt)
+    h = 1.0
+    for s, order in enumerate(ORDERS):
+        K = agca.unit_element_matrix_path(h, ncomp, order) * 6.0 / h
+        corners = [0]
+        for ax in order:
+            corners.append(corners[-1] | (1 << ax))
+        u = np.concatenate([U[corners, c] for c in range(ncomp)])
+        w = np.concatenate([W[corners, c] for c in range(ncomp)])
+        assert got[s] == pytest.approx(u @ K @ w, rel=1e-13, abs=1e-13)
+
+
+@pytest.mark.parametrize("ncomp,l", [(1, 0), (1, 1), (3, 0), (3, 1)])
+def test_galerkin_blocks(exe, ncomp, l):
+    L = 2
+    levels = mesh.hierarchy(L)
+    field = Sinkers(3, 2, radius=0.2, width=0.05, contrast=1e6)
+    nu = field.nu(mesh.centroids_canonical(levels[L]))
+    Ps = transfer.prolongations(levels, ncomp)
+    rng = np.random.default_rng(l)
+    ids = np.sort(rng.choice(6 * levels[l].n ** 3, 12, replace=False))
+    ref = agca.local_gca_blocks(levels, Ps, nu, ncomp, l, ids)
+    txt = f"gca {ncomp} {l} {L} {ids.size} " + " ".join(str(int(e)) for e in ids) + " " + \
+        " ".join(f"{v:.17g}" for v in nu)
+    M = 4 * ncomp
+    got = _run(exe, txt).reshape(ids.size, M, M)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _stop(exe, tol, rho, seq):
+    txt = f"stop {tol:.17g} {rho:.17g} {len(seq)} " + " ".join(f"{v:.17g}" for v in seq)
+    return [int(v) for v in _run(exe, txt)]
+
+
+def test_stop_rule(exe):
+    CONT, FLOOR, STALL = 0, 1, 2
+    # stagnation within 2x of the floor rho (rho above tol): a floor stop
+    assert _stop(exe, 1e-8, 2e-8, [3.5e-8, 3.4e-8, 3.45e-8]) == [CONT, CONT, FLOOR]
+    # a stop 75x above tol with a floor far below it is not success
+    assert _stop(exe, 1e-8, 1e-9, [7.5e-7, 7.4e-7, 7.6e-7]) == [CONT, CONT, STALL]
+    # the same residuals with a floor estimate of 1.6e-7: still more than 2x above it
+    assert _stop(exe, 1e-8, 1.6e-7, [7.5e-7, 7.4e-7, 7.6e-7]) == [CONT, CONT, STALL]
+    # a tolerance below the floor: stagnation at 1.5 x tol with rho < tol is a floor stop
+    assert _stop(exe, 1e-8, 5e-9, [1.6e-8, 1.5e-8, 1.55e-8]) == [CONT, CONT, FLOOR]
+    # steady improvement continues until the check budget (8) is spent
+    seq = [1e-6 * 0.5 ** k for k in range(8)]
+    out = _stop(exe, 1e-12, 1e-9, seq)
+    assert out[:7] == [CONT] * 7 and out[7] == STALL
+    out = _stop(exe, 1e-12, 5e-9, seq)
+    assert out[7] == FLOOR      # 7.8e-9 <= 2 * 5e-9

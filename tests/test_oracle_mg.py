@@ -142,3 +142,33 @@ def test_vector_pcg_converges():
     assert res.converged
     xs = _exact(H, b)
     assert np.linalg.norm(res.x - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def test_minres_iterates_minimise_the_preconditioned_residual():
+    """Each MINRES iterate is the minimiser of the M-norm of b - A x over the
+    preconditioned Krylov space span{M b, (M A) M b, ...} (Paige and Saunders 1975),
+    here found by brute force: an orthonormal (Arnoldi) basis of the space and a
+    dense least-squares solve, on a small symmetric indefinite system."""
+    rng = np.random.default_rng(3)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.concatenate([rng.uniform(1, 10, 25), -rng.uniform(0.5, 4, 15)])
+    A = (Q * ev) @ Q.T
+    C = np.tril(rng.standard_normal((n, n)) * 0.2) + np.eye(n)
+    Mmat = C @ C.T
+    b = rng.standard_normal(n)
+    for k in (1, 2, 5, 9, 14):
+        res = mg.minres(A, b, lambda r: Mmat @ r, tol=0.0, maxit=k)
+        assert res.iterations == k
+        # orthonormal basis by Arnoldi (each new vector M A v orthogonalised twice)
+        basis = np.empty((n, k))
+        v = Mmat @ b
+        for j in range(k):
+            for _ in range(2):
+                v = v - basis[:, :j] @ (basis[:, :j].T @ v)
+            basis[:, j] = v / np.linalg.norm(v)
+            v = Mmat @ (A @ basis[:, j])
+        # ||b - A x||_M with ||r||_M^2 = r . M r = ||C^T r||^2
+        y = np.linalg.lstsq(C.T @ A @ basis, C.T @ b, rcond=None)[0]
+        x_ref = basis @ y
+        assert np.linalg.norm(res.x - x_ref) <= 1e-10 * np.linalg.norm(x_ref)

@@ -1,29 +1,29 @@
 """Benchmark of the AGCA multigrid hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-    python bench.py --workload sinker513|stokes257|adjoint129|coarsening|roofline [--level L]
+    python bench.py --workload sinker129            (the earlier 129^3 benchmark line)
+    python bench.py --workload stokes257|adjoint129|coarsening|roofline [--level L]
                                                             (report lines)
 
-Workload (default): the vector viscous block -div(2 nu eps(u)) = f on 129^3
-nodes (7 levels), 8 tanh-smoothed sinkers of radius 0.1, contrast 1e6,
-f = (0, 0, -xi); synthetic inputs from the seeded generators in workloads/.
+Workload (default, sinker513): the vector viscous block -div(2 nu eps(u)) = f on
+513^3 nodes (9 levels, 400,298,493 free DoFs), 64 tanh-smoothed sinkers with radii
+in [0.02, 0.06] (seed 5), contrast 1e6, f = (0, 0, -xi); inputs generated on the
+device from the seeded generators in workloads/ and resident in HBM before timing.
 
-One step = one pass over the whole hot path for the resident coefficient:
-  1. rebuild both hierarchies from the resident coefficients (flags, Galerkin
-     blocks of flagged elements, diagonals, coarsest inverse, and the spectral
-     bounds of the Chebyshev smoother),
-  2. a batch of fine-grid operator applications v = A_L u (FP64), each timed
-     with HIP events after a 512 MiB read that evicts the Infinity Cache,
-  3. an FP64 solve to 1e-8 with the FP64 AGCA V-cycle (PCG); the V-cycle is
-     V(2,2) with the degree-2 Chebyshev smoother of Section 4 (--smoother
-     jacobi: damped Jacobi, omega = 2/3),
-  4. a solve to 1e-8 with the FP32 V-cycle and BF16 finest coefficient inside
-     FP64 flexible CG,
-  5. both solves again to 1e-7 (1e-8 sits at the FP64 rounding floor of an
-     iterate at this contrast; 1e-7 compares the two without it).
-Printed metric: fine-grid apply throughput in GDoF/s (free DoFs / average
-duration of the FP64 apply kernel, HIP events on the library's stream), plus
-the two times to 1e-8, the roofline of that kernel and the CPU oracle baseline.
+One step = one pass over the hot path for the resident coefficient:
+  1. rebuild both hierarchies (FP64 multigrid; FP32 multigrid with the BF16 finest
+     coefficient) from the resident coefficients: flags, Galerkin blocks of flagged
+     elements, diagonals, coarsest inverse, spectral bounds of the Chebyshev smoother,
+  2. a batch of fine-grid operator applications v = A_L u (FP64), each timed with
+     HIP events on the library's stream after a 512 MiB read (cold caches),
+  3. one FP64 and one FP32 V(2,2)-cycle (degree-2 Chebyshev smoother of Section 4).
+After the timed steps, once: FP64-MG PCG and FP32/BF16-MG FCG (FP64 outer loop) on
+A_L x = b to tol 1e-8, each recording when its verified true residual first fell
+below 1e-5, 1e-6 and 1e-7, with its final residual and the rounding floor rho of
+its iterate; then the 129^3 sinker workload's apply and solves as extra keys.
+Printed metric: fine-grid apply throughput in GDoF/s (free DoFs / average duration
+of the FP64 apply kernel), plus times to tolerance, the roofline of that kernel and
+the CPU oracle baseline.
 """
 
 from __future__ import annotations
@@ -44,7 +44,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GDoF/s fine-grid apply; time-to-1e-8 residual, FP32-MG vs FP64-MG"
-PROFILE = os.path.join(ROOT, "profiles", "fine_apply_sinker129.md")
+PROFILES = {"sinker513": os.path.join(ROOT, "profiles", "fine_apply_sinker513.md"),
+            "sinker129": os.path.join(ROOT, "profiles", "fine_apply_sinker129.md")}
+MILESTONES = (1e-5, 1e-6, 1e-7)
 # sources whose text determines the fine-apply kernel; counter traffic is only
 # reported while their hash equals the one recorded next to the counters
 KERNEL_SOURCES = ["paper_2511_13109_amd/csrc/k_apply.hip", "paper_2511_13109_amd/csrc/kuhn.h",
@@ -67,12 +69,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per fine-apply launch from the committed counter summary, or None when
-    the kernel sources changed after the counters were taken."""
+def recorded_traffic(workload: str):
+    """HBM bytes per fine-apply launch from the committed counter summary of a workload, or
+    None when there is none or the kernel sources changed after the counters were taken."""
     try:
-        text = open(PROFILE).read()
-    except OSError:
+        text = open(PROFILES[workload]).read()
+    except (OSError, KeyError):
         return None
     mt = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
     mh = re.search(r"^kernel_source_sha256_16: ([0-9a-f]+)$", text, re.M)
@@ -297,14 +299,22 @@ def profile_apply(name: str, dev) -> None:
     (three times) whose known size calibrates the byte counters."""
     import torch
     from paper_2511_13109_amd import Hierarchy
-    w, nu, _, _ = make_inputs(name)
-    nus = [torch.from_numpy(v).to(dev) for v in nu]
+    if name == "sinker513":     # 805 million elements: generated on the device
+        from workloads import workload
+        from workloads.device import device_inputs
+        w = workload(name)
+        nus, f = device_inputs(w, dev)
+        del f
+    else:
+        w, nu, _, _ = make_inputs(name)
+        nus = [torch.from_numpy(v).to(dev) for v in nu]
     H = Hierarchy(w.L, w.ncomp, nus[w.L], nus[:w.L], mg_dtype="f64")
     n = 2 ** (w.L + 1)
     u = torch.randn(w.ncomp * (n + 1) ** 3, dtype=torch.float64, device=dev)
     v = torch.empty_like(u)
     for _ in range(5):
         H.apply(w.L, u, v)
+    del nus
     a = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.float64, device=dev).normal_()
     c = torch.empty_like(a)
     for _ in range(3):
@@ -335,75 +345,198 @@ def cold_apply_us(H, level, u, v, reps=10):
     return float(np.median(ts))
 
 
-def report_large(args, dev) -> dict:
-    """513^3 vector sinkers (64 sinkers, radii in [0.02, 0.06]): FP64-MG PCG against FP32-MG
-    (BF16 coefficient) FCG to 1e-8, flagged fractions, stored-block bytes, HBM use, and the
-    cold fine-apply rate in both precisions."""
+def solve_record(H, b, solver: str, tol: float, max_iter: int = 8000):
+    """One solve to tol with the milestones; returns x and a record of its statistics."""
+    x, st = H.solve(b, solver=solver, tol=tol, max_iter=max_iter, raise_on_noconv=False,
+                    record_history=False, milestones=MILESTONES)
+    rec = {k: st[k] for k in ("iterations", "seconds", "rel_residual", "converged", "floor_limited",
+                              "floor_estimate", "replacements", "status")}
+    rec["milestones"] = {f"{m:g}": (None if v is None else {"iterations": v[0], "seconds": round(v[1], 4),
+                                                            "rel_residual": v[2]})
+                         for m, v in st["milestones"].items()}
+    return x, rec
+
+
+def time_to(rec: dict, tol: float, final_tol: float):
+    """Seconds until the solve's verified true residual was <= tol, None if never."""
+    if tol == final_tol:
+        return round(rec["seconds"], 4) if rec["converged"] else None
+    m = rec["milestones"].get(f"{tol:g}")
+    return None if m is None else m["seconds"]
+
+
+def speedup(a, b):
+    return None if (a is None or b is None) else round(a / b, 3)
+
+
+def bench_large(args, dev) -> dict:
+    """The benchmark line on the 513^3 sinker workload (see the module docstring)."""
     import torch
     from paper_2511_13109_amd import Hierarchy
     from workloads import workload
     from workloads.device import device_inputs
-    w = workload(args.workload, L=args.level)
+    w = workload("sinker513", L=args.level)
     L, nc = w.L, w.ncomp
+    n = 2 ** (L + 1)
+    N = (n + 1) ** 3
+    free_dofs = nc * (n - 1) ** 3
     t0 = time.perf_counter()
     nus, f = device_inputs(w, dev)
+    torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
-    out = {"report": w.name, "description": w.description, "levels": L + 1,
-           "free_dofs": nc * (2 ** (L + 1) - 1) ** 3, "input_generation_s": round(t_gen, 2)}
-    t0 = time.perf_counter()
+    progress(f"[bench] {w.name}: inputs on the device in {t_gen:.1f} s")
     H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64", smoother=args.smoother,
                     coarse_storage=args.coarse_storage)
-    out["setup_fp64_s"] = round(time.perf_counter() - t0, 3)
-    out["smoother"] = args.smoother
-    out["coarse_storage"] = args.coarse_storage
-    progress(f"[large] inputs {t_gen:.1f} s, FP64 hierarchy {out['setup_fp64_s']:.1f} s")
+    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype=args.mg_nu,
+                    smoother=args.smoother, coarse_storage=args.coarse_storage)
     b = H64.load_vector(f)
     del f
-    x, s64 = H64.solve(b, solver="pcg", tol=w.tol, max_iter=4000, raise_on_noconv=False,
-                       record_history=False)
-    progress(f"[large] FP64-MG PCG {s64['iterations']} it {s64['seconds']:.2f} s")
-    out["fp64_mg_pcg"] = {k: s64[k] for k in ("iterations", "seconds", "rel_residual", "converged",
-                                                "floor_limited")}
-    n = 2 ** (L + 1)
-    u = torch.randn(nc * (n + 1) ** 3, dtype=torch.float64, device=dev)
+    b32 = b.float()
+    z64, z32 = torch.empty_like(b), torch.empty_like(b32)
+    gen = torch.Generator(device=dev).manual_seed(0)
+    u = torch.randn(nc * N, generator=gen, dtype=torch.float64, device=dev)
     v = torch.empty_like(u)
-    t_app = cold_apply_us(H64, L, u, v)
-    byt = apply_bytes(L, nc)
-    out["fp64_apply"] = {"us": round(t_app, 1), "GDoF_s": round(out["free_dofs"] / t_app / 1e3, 2),
-                         "GB_s": round(byt / t_app / 1e3, 1), "frac_hbm_peak": round(byt / t_app / 1e3 / HBM_PEAK_GBS, 4)}
-    info = [H64.query(l) for l in range(L)]
-    out["flagged_fraction_per_level"] = [round(i["flagged"] / i["elements"], 6) for i in info]
-    out["flagged_per_level"] = [i["flagged"] for i in info]
-    out["stored_block_bytes_fp64"] = int(sum(i["block_bytes"] for i in info))
-    dev64 = H64.device_bytes()
+    flush = torch.ones(512 * 1024 * 1024 // 8, dtype=torch.float64, device=dev)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.applies)]
+    evc = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
+    rec = {"apply_ms": [], "setup_s": [], "vcycle64_ms": [], "vcycle32_ms": []}
+
+    def step(record: bool):
+        t0 = time.perf_counter()
+        H64.set_nu(nus[L], nus[:L])
+        H32.set_nu(nus[L], nus[:L])
+        t_setup = time.perf_counter() - t0
+        for e0, e1 in ev:
+            sink.add_(flush.sum())
+            e0.record()
+            H64.apply(L, u, v)
+            e1.record()
+        evc[0][0].record()
+        H64.vcycle(b, z64)
+        evc[0][1].record()
+        evc[1][0].record()
+        H32.vcycle(b32, z32)
+        evc[1][1].record()
+        if record:
+            torch.cuda.synchronize()
+            rec["apply_ms"].append(float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev])))
+            rec["setup_s"].append(t_setup)
+            rec["vcycle64_ms"].append(evc[0][0].elapsed_time(evc[0][1]))
+            rec["vcycle32_ms"].append(evc[1][0].elapsed_time(evc[1][1]))
+            progress(f"[step] setup {t_setup:.3f} s, apply {rec['apply_ms'][-1] * 1e3:.1f} us, "
+                     f"V-cycle FP64 {rec['vcycle64_ms'][-1]:.2f} ms, FP32 {rec['vcycle32_ms'][-1]:.2f} ms")
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype="bf16", smoother=args.smoother,
-                    coarse_storage=args.coarse_storage)
-    out["setup_mixed_s"] = round(time.perf_counter() - t0, 3)
-    x32, s32 = H32.solve(b, solver="fcg", tol=w.tol, max_iter=4000, raise_on_noconv=False,
-                         record_history=False)
-    progress(f"[large] FP32-MG FCG {s32['iterations']} it {s32['seconds']:.2f} s")
-    out["fp32_mg_fcg"] = {k: s32[k] for k in ("iterations", "seconds", "rel_residual", "converged",
-                                                "floor_limited")}
-    u32, v32 = u.float(), torch.empty_like(u, dtype=torch.float32)
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    apply_s = float(np.mean(rec["apply_ms"])) / 1e3
+    bytes_launch = apply_bytes(L, nc)
+    achieved = bytes_launch / apply_s / 1e9
+    # the FP32 / BF16 fine apply of the mixed hierarchy, timed the same way
+    u32, v32 = u.float(), torch.empty_like(b32)
     t32 = cold_apply_us(H32, L, u32, v32)
-    byt32 = apply_bytes(L, nc, 4, 2)
-    out["fp32_bf16_apply"] = {"us": round(t32, 1), "GDoF_s": round(out["free_dofs"] / t32 / 1e3, 2),
-                              "GB_s": round(byt32 / t32 / 1e3, 1)}
+    del u32, v32
+
+    # the solves, once each, outside the timed steps
+    progress("[bench] FP64-MG PCG to 1e-8 ...")
+    x64, r64 = solve_record(H64, b, "pcg", w.tol)
+    progress(f"[bench] FP64-MG PCG: {r64['iterations']} it, {r64['seconds']:.2f} s, res "
+             f"{r64['rel_residual']:.3e}, rho {r64['floor_estimate']:.3e}, status {r64['status']}")
+    x32, r32 = solve_record(H32, b, "fcg", w.tol)
+    progress(f"[bench] FP32-MG FCG: {r32['iterations']} it, {r32['seconds']:.2f} s, res "
+             f"{r32['rel_residual']:.3e}, rho {r32['floor_estimate']:.3e}, status {r32['status']}")
+    dx = x32 - x64
+    err_energy = float(torch.dot(dx, H64.apply(L, dx)) / torch.dot(x64, H64.apply(L, x64))) ** 0.5
+    err_max = float(dx.abs().max() / x64.abs().max())
+    del dx, x32
+    info = [H64.query(l) for l in range(L)]
     info32 = [H32.query(l) for l in range(L)]
-    out["stored_block_bytes_mixed"] = int(sum(i["block_bytes"] for i in info32))
-    dx = x32 - x
-    Adx, Ax = H64.apply(L, dx), H64.apply(L, x)
-    out["mixed_vs_fp64_energy_norm_rel"] = float(torch.dot(dx, Adx) / torch.dot(x, Ax)) ** 0.5
-    out["speedup_mixed_over_fp64"] = round(s64["seconds"] / s32["seconds"], 3)
-    out["device_bytes"] = {"fp64_hierarchy": dev64, "mixed_hierarchy": H32.device_bytes(),
-                           "torch_allocated": int(torch.cuda.memory_allocated(dev)),
-                           "peak_torch_allocated": int(torch.cuda.max_memory_allocated(dev))}
-    total = dev64 + H32.device_bytes() + int(torch.cuda.max_memory_allocated(dev))
-    out["hbm_fraction_used"] = round(total / 288e9, 4)
+    dev64, dev32 = H64.device_bytes(), H32.device_bytes()
+    peak_torch = int(torch.cuda.max_memory_allocated(dev))
+    times = {}
+    for tol in MILESTONES + (w.tol,):
+        a, c = time_to(r64, tol, w.tol), time_to(r32, tol, w.tol)
+        times[f"{tol:g}"] = {"fp64_mg_pcg": a, "fp32_mg_fcg": c, "speedup_fp32_over_fp64": speedup(a, c)}
+    out = {
+        "metric": METRIC, "value": round(free_dofs / apply_s / 1e9, 3), "unit": "GDoF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sinker513: vector -div(2 nu eps(u))=f, 513^3 nodes, 64 sinkers r in "
+                               "[0.02, 0.06], contrast 1e6, FP64 and FP32/BF16 multigrid",
+                   "levels": L + 1, "nodes": N, "free_dofs": free_dofs, "elements": 6 * n ** 3,
+                   "applies_per_step": args.applies},
+        "time_to_tol_s": times,
+        "time_to_1e-8_s": times[f"{w.tol:g}"],
+        "solves": {"fp64_mg_pcg": r64, "fp32_mg_fcg": r32, "mg_nu_dtype": args.mg_nu,
+                   "smoother": args.smoother, "coarse_storage": args.coarse_storage},
+        "mixed_vs_fp64_solution": {"energy_norm_rel": err_energy, "max_rel": err_max},
+        "vcycle_ms": {"fp64": round(float(np.median(rec["vcycle64_ms"])), 3),
+                      "fp32_bf16": round(float(np.median(rec["vcycle32_ms"])), 3)},
+        "fp32_bf16_apply": {"us": round(t32, 1), "GDoF_s": round(free_dofs / t32 / 1e3, 2),
+                            "GB_s": round(apply_bytes(L, nc, 4, 2) / t32 / 1e3, 1),
+                            "frac_hbm_peak": round(apply_bytes(L, nc, 4, 2) / t32 / 1e3 / HBM_PEAK_GBS, 4)},
+        "setup_s": round(float(np.median(rec["setup_s"])), 4),
+        "flagged_per_level": [i["flagged"] for i in info],
+        "flagged_fraction_per_level": [round(i["flagged"] / i["elements"], 6) for i in info],
+        "stored_block_bytes": {"fp64_hierarchy": int(sum(i["block_bytes"] for i in info)),
+                               "mixed_hierarchy": int(sum(i["block_bytes"] for i in info32))},
+        "device_bytes": {"fp64_hierarchy": dev64, "mixed_hierarchy": dev32, "peak_torch": peak_torch},
+        "hbm_fraction_used": round((dev64 + dev32 + peak_torch) / 288e9, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic("sinker513"),
+                     "kernel": "k_cube<3,double,double,APPLY> (fine-grid apply, 513^3)",
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(apply_s * 1e6, 2),
+                     "kernel_source_sha256_16": kernel_hash()},
+        "input_generation_s": round(t_gen, 2),
+    }
     H64.close()
     H32.close()
+    del x64, b, b32, z64, z32, u, v, nus, flush
+    torch.cuda.empty_cache()
     return out
+
+
+def extra_129(args, dev) -> dict:
+    """The 129^3 sinker workload (8 sinkers r = 0.1, seed 2): cold FP64 apply, and FP64-MG
+    PCG / FP32-MG FCG to 1e-8 with the 1e-7 milestone (extra keys of the benchmark line)."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy
+    w, nu, f, _ = make_inputs("sinker129")
+    L, nc = w.L, w.ncomp
+    nus = [torch.from_numpy(v).to(dev) for v in nu]
+    H64 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f64", smoother=args.smoother)
+    H32 = Hierarchy(L, nc, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype=args.mg_nu, smoother=args.smoother)
+    b = H64.load_vector(torch.from_numpy(f.ravel()).to(dev))
+    n = 2 ** (L + 1)
+    free_dofs = nc * (n - 1) ** 3
+    u = torch.randn(nc * (n + 1) ** 3, generator=torch.Generator(device=dev).manual_seed(0),
+                    dtype=torch.float64, device=dev)
+    t = cold_apply_us(H64, L, u, torch.empty_like(u), reps=20)
+    for _ in range(2):      # warm-up solves (the first run of each kernel pays its load)
+        solve_record(H64, b, "pcg", w.tol)
+        solve_record(H32, b, "fcg", w.tol)
+    _, r64 = solve_record(H64, b, "pcg", w.tol)
+    _, r32 = solve_record(H32, b, "fcg", w.tol)
+    times = {}
+    for tol in (1e-7, w.tol):
+        a, c = time_to(r64, tol, w.tol), time_to(r32, tol, w.tol)
+        times[f"{tol:g}"] = {"fp64_mg_pcg": a, "fp32_mg_fcg": c, "speedup_fp32_over_fp64": speedup(a, c)}
+    H64.close()
+    H32.close()
+    return {"workload": f"{w.name}: {w.description}", "apply_us_cold": round(t, 2),
+            "apply_GDoF_s": round(free_dofs / t / 1e3, 2),
+            "apply_frac_hbm_peak": round(apply_bytes(L, nc) / t / 1e3 / HBM_PEAK_GBS, 4),
+            "time_to_tol_s": times, "solves": {"fp64_mg_pcg": r64, "fp32_mg_fcg": r32}}
 
 
 def report_stokes(args, dev) -> dict:
@@ -639,10 +772,10 @@ def report_coarsening(args, dev) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sinker129")
-    ap.add_argument("--applies", type=int, default=20)
+    ap.add_argument("--workload", default="sinker513")
+    ap.add_argument("--applies", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mg-nu", default="bf16", choices=["bf16", "f32"])
     ap.add_argument("--smoother", default="chebyshev", choices=["jacobi", "chebyshev"])
@@ -686,13 +819,33 @@ def main():
     if args.profile_apply:
         profile_apply(args.workload, dev)
         return
-    # the other workloads print a report line of their own (the benchmark line is the
-    # 129^3 sinker workload)
-    reports = {"sinker513": report_large, "stokes257": report_stokes, "adjoint129": report_adjoint,
+    # the benchmark line: 513^3 (default) or the earlier 129^3 line; the other workloads
+    # print a report line of their own
+    reports = {"stokes257": report_stokes, "adjoint129": report_adjoint,
                "coarsening": report_coarsening, "roofline": report_roofline}
     if args.workload in reports:
         print(json.dumps(reports[args.workload](args, dev)), flush=True)
         return
+    if args.workload == "sinker513":
+        out = bench_large(args, dev)
+        out["sinker129"] = extra_129(args, dev)
+    elif args.workload == "sinker129":
+        out = bench_129(args, dev)
+    else:
+        raise SystemExit(f"unknown workload {args.workload}")
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(args.workload)
+        except Exception as exc:  # the baseline is a report, never a reason to lose the line
+            out["cpu_baseline"] = {"error": repr(exc)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_129(args, dev) -> dict:
+    """The benchmark line on the 129^3 sinker workload (steps as before: rebuild, 20 cold
+    applies, both solves to 1e-8 and to 1e-7)."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy
     w, nu, f, t_gen = make_inputs(args.workload)
     L, nc = w.L, w.ncomp
     nus = [torch.from_numpy(v).to(dev) for v in nu]
@@ -795,20 +948,15 @@ def main():
         "setup_s": round(float(np.median(rec["setup_s"])), 5),
         "flagged_per_level": [H64.query(l)["flagged"] for l in range(L)],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic("sinker129"),
                      "kernel": "k_cube<3,double,double,APPLY> (fine-grid apply)",
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(apply_s * 1e6, 2),
                      "kernel_source_sha256_16": kernel_hash()},
         "input_generation_s": round(t_gen, 2),
     }
-    if not args.no_cpu_baseline:
-        try:
-            out["cpu_baseline"] = cpu_baseline(args.workload)
-        except Exception as exc:  # the baseline is a report, never a reason to lose the line
-            out["cpu_baseline"] = {"error": repr(exc)}
     H64.close()
     H32.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

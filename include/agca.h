@@ -201,22 +201,28 @@ int32_t agca_cast(agca_hier* h, int32_t from, int32_t to, const void* src, void*
 
 enum { AGCA_SOLVER_PCG = 0, AGCA_SOLVER_FCG = 1, AGCA_SOLVER_IR = 2, AGCA_SOLVER_STATIONARY = 3 };
 
+#define AGCA_MAX_MILESTONES 8
 typedef struct {
     int32_t solver;          /* AGCA_SOLVER_*                                              */
     int32_t max_iter;
     double tol;              /* stop when ||b - A x||_2 <= tol ||b||_2 (eq. (4.3))          */
     int32_t use_x0;          /* 0: start from x = 0; 1: start from the given x              */
     int32_t record_history;  /* store the relative residual of every iteration             */
+    int32_t n_milestones;    /* 0..AGCA_MAX_MILESTONES (PCG and FCG only)                  */
+    double milestones[AGCA_MAX_MILESTONES]; /* tolerances above tol: the solve records when
+                                the true residual first falls below each (checked, like the
+                                final stop, by a residual replacement when the recurrence
+                                crosses it), so one solve gives several times to tolerance */
 } agca_solve_opts;
 
 #define AGCA_MAX_HISTORY 1024
 typedef struct {
     int32_t iterations;
     int32_t converged;       /* the true FP64 residual of x is <= tol                       */
-    int32_t floor_limited;   /* PCG/FCG: the recurrence reached tol, the true residual
-                                stopped improving above it, and it is within 2x of
-                                max(tol, floor_estimate): FP64 rounding of x, not the
-                                solver, limits it (Stokes FGMRES: see agca_stokes_solve)    */
+    int32_t floor_limited;   /* PCG/FCG: the true residual stopped improving above tol
+                                and is at most max(tol, floor_estimate): FP64 rounding of
+                                x, not the solver, limits it (Stokes FGMRES: see
+                                agca_stokes_solve)                                          */
     int32_t replacements;    /* times the true residual replaced the recurrence's           */
     double rel_residual;     /* final ||b - A x|| / ||b|| in FP64 with FP64 coefficients,
                                 norms over the free dofs                                    */
@@ -225,6 +231,10 @@ typedef struct {
                                 (agca_residual_floor); Stokes FGMRES: the velocity block's
                                 part at the last floor test (0 if none ran)                 */
     double seconds;          /* wall time of the solve (after setup)                        */
+    int32_t milestone_iterations[AGCA_MAX_MILESTONES]; /* iteration at which the true
+                                residual was first found <= milestones[i]; -1 if never      */
+    double milestone_seconds[AGCA_MAX_MILESTONES];     /* solve wall time at that point     */
+    double milestone_residuals[AGCA_MAX_MILESTONES];   /* the true relative residual there  */
     double history[AGCA_MAX_HISTORY]; /* recurrence residuals, one per iteration           */
 } agca_solve_stats;
 
@@ -233,14 +243,14 @@ typedef struct {
  * V-cycle; stationary V-cycle iteration).  b, x: device FP64 level vectors (boundary
  * slots of b are ignored; norms are taken over the free dofs).
  * Stopping (eq. (4.3)): PCG and FCG replace their recurrence's residual by the true
- * residual b - A x whenever the recurrence has fallen tenfold since the last
- * replacement, and when it reaches tol (the search direction is kept).  If the true
- * residual is then above tol the iteration continues; it stops with floor_limited only
- * when the true residual has stopped improving (two end checks in a row without a
- * 10 % gain, or 8 end checks) and is within 2x of max(tol, rho), rho the rounding
- * floor of x (agca_residual_floor).  Returns AGCA_OK when converged or floor_limited;
- * AGCA_E_NOCONV (x and stats filled) when max_iter is reached first or the true
- * residual stalls above 2 max(tol, rho). */
+ * residual b - A x whenever the recurrence has halved since the last replacement, and
+ * when it reaches tol (the search direction is kept).  They stop when the true residual
+ * is <= tol (converged), or when it has stopped improving (two replacements in a row
+ * without a 10 % gain over the best earlier one, or 8 replacements with the recurrence
+ * at tol): then floor_limited if it is at most max(tol, rho), rho the rounding floor of
+ * x (agca_residual_floor), else a stall.  Returns AGCA_OK when converged or
+ * floor_limited; AGCA_E_NOCONV (x and stats filled) when max_iter is reached first or
+ * the true residual stalls above max(tol, rho). */
 int32_t agca_solve(agca_hier* h, const agca_solve_opts* opts, const double* b, double* x,
                    agca_solve_stats* stats);
 
@@ -318,7 +328,7 @@ typedef struct {
  * BFBT adds 3 velocity and 8 pressure vectors.
  * FGMRES stops early with stats->floor_limited when a restart cycle's residual
  * estimate reached tol but the true residual after it is above tol, less than 5 %
- * below its value four cycles earlier, and within 2x of max(tol, rho_A), rho_A the
+ * below its value four cycles earlier, and at most max(tol, rho_A), rho_A the
  * rounding floor of the velocity block (the terms of agca_residual_floor for A and
  * f, over the norm of the whole right-hand side; a lower bound of the system's
  * floor), reported in stats->floor_estimate.

@@ -35,9 +35,13 @@ class LevelInfo(C.Structure):
                 ("level_bytes", C.c_int64), ("lambda_max", C.c_double)]
 
 
+MAX_MILESTONES = 8
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
-                ("use_x0", C.c_int32), ("record_history", C.c_int32)]
+                ("use_x0", C.c_int32), ("record_history", C.c_int32), ("n_milestones", C.c_int32),
+                ("milestones", C.c_double * MAX_MILESTONES)]
 
 
 class StokesOpts(C.Structure):
@@ -56,6 +60,9 @@ class SolveStats(C.Structure):
                 ("replacements", C.c_int32), ("rel_residual", C.c_double),
                 ("recursive_rel_residual", C.c_double), ("floor_estimate", C.c_double),
                 ("seconds", C.c_double),
+                ("milestone_iterations", C.c_int32 * MAX_MILESTONES),
+                ("milestone_seconds", C.c_double * MAX_MILESTONES),
+                ("milestone_residuals", C.c_double * MAX_MILESTONES),
                 ("history", C.c_double * MAX_HISTORY)]
 
 

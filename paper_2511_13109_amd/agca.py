@@ -58,8 +58,9 @@ def macro_gradient(L: int, eta_nodes: torch.Tensor, stream=None) -> np.ndarray:
         raise ValueError("eta_nodes must hold (2^(L+1)+1)^3 float64 nodal values")
     st = stream if stream is not None else torch.cuda.current_stream(eta_nodes.device)
     out = np.zeros(48)
-    check(_lib.load().agca_macro_gradient(L, _ptr(eta_nodes), out.ctypes.data_as(C.c_void_p),
-                                          C.c_void_p(st.cuda_stream)), "agca_macro_gradient")
+    name = "agca_macro_gradient"
+    check(getattr(_lib.load(), name)(L, _ptr(eta_nodes), out.ctypes.data_as(C.c_void_p),
+                                     C.c_void_p(st.cuda_stream)), name)
     return out
 
 
@@ -237,13 +238,21 @@ class Hierarchy:
 
     def solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, solver: str = "pcg",
               tol: float = 1e-8, max_iter: int = 500, record_history: bool = True,
-              raise_on_noconv: bool = True):
+              raise_on_noconv: bool = True, milestones: Sequence[float] = ()):
+        """milestones: tolerances above tol at which the solve records when its verified true
+        residual first fell below each (stats["milestones"]: tol -> (iteration, seconds,
+        residual), or None if never)."""
         opts = _lib.SolveOpts()
         opts.solver = _SOLVER[solver]
         opts.max_iter = max_iter
         opts.tol = tol
         opts.use_x0 = 0 if x is None else 1
         opts.record_history = 1 if record_history else 0
+        if len(milestones) > _lib.MAX_MILESTONES:
+            raise ValueError(f"at most {_lib.MAX_MILESTONES} milestones")
+        opts.n_milestones = len(milestones)
+        for i, m in enumerate(milestones):
+            opts.milestones[i] = m
         x = torch.zeros_like(b) if x is None else x
         st = _lib.SolveStats()
         rc = self._lib.agca_solve(self._h, C.byref(opts), _ptr(b), _ptr(x), C.byref(st))
@@ -253,7 +262,10 @@ class Hierarchy:
                  "recursive_rel_residual": st.recursive_rel_residual,
                  "floor_estimate": st.floor_estimate, "seconds": st.seconds,
                  "history": list(st.history[:min(st.iterations + 1, _lib.MAX_HISTORY)])
-                 if record_history else [], "status": rc}
+                 if record_history else [], "status": rc,
+                 "milestones": {m: ((st.milestone_iterations[i], st.milestone_seconds[i],
+                                     st.milestone_residuals[i]) if st.milestone_iterations[i] >= 0 else None)
+                                for i, m in enumerate(milestones)}}
         if rc != _lib.AGCA_OK and (rc != _lib.AGCA_E_NOCONV or raise_on_noconv):
             check(rc, "agca_solve")
         return x, stats
@@ -326,7 +338,7 @@ class Stokes:
         rc = self.H._lib.agca_stokes_solve(self.H._h, C.byref(opts), _ptr(f), _ptr(g), _ptr(u), _ptr(p),
                                            C.byref(st))
         stats = {"iterations": st.iterations, "converged": bool(st.converged),
-                 "floor_limited": bool(st.floor_limited),
+                 "floor_limited": bool(st.floor_limited), "floor_estimate": st.floor_estimate,
                  "rel_residual": st.rel_residual, "seconds": st.seconds, "status": rc,
                  "history": list(st.history[:min(st.iterations + 1, _lib.MAX_HISTORY)])
                  if record_history else []}

@@ -388,13 +388,15 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
     return AGCA_OK;
 }
 
+// x . y into reduction slot `slot` (device) and *out (host); synchronises
 template <typename T>
-int32_t do_dot(agca_hier* h, const T* x, const T* y, int64_t count, double* out) {
+int32_t do_dot(agca_hier* h, const T* x, const T* y, int64_t count, double* out, int slot = 0) {
     HIPCHK(h, launch_dot_partial<T>(x, y, count, h->partial, h->nb_partial, h->st));
-    HIPCHK(h, launch_sum_partials(h->partial, h->nb_partial, h->red, h->st));
-    HIPCHK(h, hipMemcpyAsync(h->red_host, h->red, sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, launch_sum_partials(h->partial, h->nb_partial, h->red + slot, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->red_host + slot, h->red + slot, sizeof(double), hipMemcpyDeviceToHost,
+                             h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
-    *out = h->red_host[0];
+    *out = h->red_host[slot];
     return AGCA_OK;
 }
 
@@ -412,8 +414,11 @@ int32_t fetch(agca_hier* h, int k, double* out, int first = 0) {
     return AGCA_OK;
 }
 
-// reduction slots of the two helpers below, clear of the solvers' scalars (slots 0..4)
+// reduction slots of the two helpers below and of the Krylov solvers' residual
+// replacement, clear of the solvers' scalars (slots 0..4, which must survive a
+// replacement in the middle of an iteration)
 constexpr int kSlotFloor = 8;
+constexpr int kSlotReplace = 10;
 
 // ||b||_2 over the free dofs of a finest-level vector (boundary slots are not part of it)
 int32_t interior_norm(agca_hier* h, const double* b, double* out) {
@@ -1230,14 +1235,16 @@ static int32_t precondition(agca_hier* h, const double* r, double* z) {
 
 // Residual replacement and the stopping rule of the Krylov solvers.  The recurrence's
 // residual drifts away from the true residual b - A x by the rounding of every update,
-// so the true residual replaces it whenever the recurrence has fallen by kReplaceEvery
-// since the last replacement (the search direction is kept: no restart; van der Vorst
-// and Ye, SIAM J. Sci. Comput. 22, 2000), and when it reaches tol.  If the true
-// residual is then still above tol the iteration continues from it; it ends at the
+// so the true residual replaces it whenever the recurrence has halved since the last
+// replacement (kReplaceEvery; the search direction is kept, no restart: van der Vorst
+// and Ye, SIAM J. Sci. Comput. 22, 2000), and when it reaches tol.  The iteration
+// continues while the true residual is above tol and keeps improving; it ends at the
 // rounding floor (floor_limited) only under the rule of stop_rule.h (the true residual
-// stopped improving and lies within kFloorFactor of max(tol, rho), rho the rounding
-// floor of the iterate, residual_floor).  A stall above that is AGCA_E_NOCONV.
-constexpr double kReplaceEvery = 0.1;
+// stopped improving and is at most kFloorFactor max(tol, rho), rho the rounding
+// floor of the iterate, residual_floor).  A stall above that is AGCA_E_NOCONV.  A
+// replacement costs one residual pass and one dot product, against an apply, a
+// V-cycle and three vector passes per iteration.
+constexpr double kReplaceEvery = 0.5;
 
 int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, double* x,
                    agca_solve_stats* stats) {
@@ -1246,8 +1253,14 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     if (o->max_iter < 0 || !(o->tol >= 0.0)) return fail(AGCA_E_INVALID, "bad solve options");
     if (o->solver < AGCA_SOLVER_PCG || o->solver > AGCA_SOLVER_STATIONARY)
         return fail(AGCA_E_INVALID, "unknown solver");
+    if (o->n_milestones < 0 || o->n_milestones > AGCA_MAX_MILESTONES)
+        return fail(AGCA_E_INVALID, "n_milestones must be in [0, " + std::to_string(AGCA_MAX_MILESTONES) + "]");
+    for (int i = 0; i < o->n_milestones; ++i)
+        if (!(o->milestones[i] > 0.0) || !std::isfinite(o->milestones[i]))
+            return fail(AGCA_E_INVALID, "milestones must be finite and positive");
     TRY(ensure_solver_vectors(h));
     std::memset(stats, 0, sizeof(*stats));
+    for (int i = 0; i < AGCA_MAX_MILESTONES; ++i) stats->milestone_iterations[i] = -1;
     const int L = h->cfg.L;
     const int64_t cnt = (int64_t)h->cfg.ncomp * h->lv[L].nodes;
     double *r = h->s_r, *z = h->s_z, *p = h->s_p, *q = h->s_q;
@@ -1272,6 +1285,22 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     double rho = 0.0;
     int32_t status = AGCA_OK;
     double rec_rel = rel;
+    // milestones: record the first iteration whose verified true residual is below each
+    auto note_milestones = [&](double rel_true) {
+        for (int i = 0; i < o->n_milestones; ++i)
+            if (stats->milestone_iterations[i] < 0 && rel_true <= o->milestones[i]) {
+                stats->milestone_iterations[i] = it;
+                stats->milestone_seconds[i] =
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                stats->milestone_residuals[i] = rel_true;
+            }
+    };
+    auto milestone_due = [&](double rec) {
+        for (int i = 0; i < o->n_milestones; ++i)
+            if (stats->milestone_iterations[i] < 0 && rec <= o->milestones[i]) return true;
+        return false;
+    };
+    note_milestones(rel);
     if (bn == 0.0) {
         HIPCHK(h, launch_fill<double>(cnt, 0.0, x, h->st));
         rel = rec_rel = 0.0;
@@ -1313,6 +1342,7 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
             TRY(reduce_to(h, h->partial, h->nb_partial, RZ));
             HIPCHK(h, direction(0.0));
             while (it < o->max_iter) {
+                bool replaced = false;  // the true residual replaced the recurrence's this iteration
                 // q = A p fused with p . q
                 int nbq = 0;
                 HIPCHK(h, launch_cube_dot(h->cfg.ncomp, level_op<double>(h, L), p, q, h->partial, &nbq,
@@ -1339,36 +1369,43 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     status = fail(AGCA_E_NUMERIC, "residual diverged");
                     break;
                 }
-                if (rel <= o->tol || rel <= kReplaceEvery * anchor) {
-                    // residual replacement: r = b - A x (and its FP32 copy)
+                if (rel <= o->tol || rel <= kReplaceEvery * anchor || milestone_due(rel)) {
+                    // residual replacement: r = b - A x (and its FP32 copy); r . r goes to a
+                    // slot of its own (FCG's next beta still reads p . q from slot PQ)
                     TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
-                    TRY(do_dot<double>(h, r, r, cnt, &rr));
+                    TRY(do_dot<double>(h, r, r, cnt, &rr, kSlotReplace));
                     if (mixed) HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, r, r32, cnt, h->st));
                     const double rel_true = std::sqrt(rr) / bn;
                     ++replacements;
+                    replaced = true;
                     anchor = rel_true;
-                    if (rel <= o->tol) {
-                        if (rel_true <= o->tol) {
-                            rel = rel_true;
-                            break;
-                        }
-                        if (ends.stagnated(rel_true)) {
-                            TRY(residual_floor(h, b, x, &rho));
-                            rel = rel_true;
-                            floor_limited = at_floor(rel_true, o->tol, rho);
-                            stalled = !floor_limited;
-                            break;
-                        }
+                    note_milestones(rel_true);
+                    if (rel_true <= o->tol) {
+                        rel = rel_true;
+                        break;
+                    }
+                    if (ends.stagnated(rel_true, rel <= o->tol)) {
+                        TRY(residual_floor(h, b, x, &rho));
+                        rel = rel_true;
+                        floor_limited = at_floor(rel_true, o->tol, rho);
+                        stalled = !floor_limited;
+                        break;
                     }
                     rel = rec_rel = rel_true;
                 }
                 TRY(vcycle());
-                // z . r and, for FCG, z . q in one pass
-                HIPCHK(h, dots(flex ? q : nullptr));
+                // PCG's beta = z.r / rz_old takes r orthogonal to the previous direction, which
+                // a replaced residual is not (near the rounding floor the two residuals differ
+                // in their leading digits, and that beta then loses conjugacy): after a
+                // replacement the new direction is A-orthogonalised against the previous one,
+                // as FCG(1) does at every step
+                const bool orth = flex || replaced;
+                // z . r and, for the A-orthogonalising beta, z . q in one pass
+                HIPCHK(h, dots(orth ? q : nullptr));
                 TRY(reduce_to(h, h->partial, h->nb_partial, ZR));
-                if (flex) TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, ZQ));
+                if (orth) TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, ZQ));
                 // FCG: beta = -alpha z.q / rz_old = -z.q / p.q; PCG: beta = z.r / rz_old
-                HIPCHK(h, flex ? direction_dev(red + ZQ, red + PQ, -1.0) : direction_dev(red + ZR, red + RZ, 1.0));
+                HIPCHK(h, orth ? direction_dev(red + ZQ, red + PQ, -1.0) : direction_dev(red + ZR, red + RZ, 1.0));
                 HIPCHK(h, hipMemcpyAsync(red + RZ, red + ZR, sizeof(double), hipMemcpyDeviceToDevice, h->st));
             }
         } else {
@@ -1381,6 +1418,7 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                 TRY(do_dot<double>(h, r, r, cnt, &rr));
                 rel = rec_rel = std::sqrt(rr) / bn;
                 record(rel);
+                note_milestones(rel);
                 if (!std::isfinite(rel) || rel > 1e30) {
                     status = fail(AGCA_E_NUMERIC, "residual diverged");
                     break;
@@ -1728,7 +1766,7 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
         // rounding floor: the cycle's recurrence reached the tolerance but the true
         // residual did not, it is less than 5 % better than four restart cycles ago
         // (the true residual of an FP64 iterate stagnates there while each cycle's
-        // estimate keeps converging), and it is within kFloorFactor of max(tol, rho_A),
+        // estimate keeps converging), and it is at most kFloorFactor max(tol, rho_A),
         // rho_A the rounding floor of the velocity block alone (the residual_floor
         // terms of A and the velocity right-hand side over the whole system's norm: a
         // lower bound of the full system's floor, which adds the B and B^T terms)

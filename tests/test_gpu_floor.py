@@ -1,6 +1,6 @@
 """The rounding floor of the residual and the solver's stopping rule on the GPU, through
 the C ABI: the floor kernel against the oracle (1e-12), the solve driven to stagnation
-(floor_limited only within 2x of max(tol, rho), solution against an exact solve within
+(floor_limited only at most max(tol, rho), solution against an exact solve within
 the condition-number bound), and boundary slots of the inputs that must be ignored."""
 
 import numpy as np
@@ -58,7 +58,7 @@ def test_floor_kernel(case):
 @pytest.mark.parametrize("case", [("cube", 3, 1), ("sinkers", 3, 3)], ids=lambda c: f"{c[0]}-L{c[1]}-nc{c[2]}")
 def test_solve_to_stagnation(case):
     """PCG asked for an unreachable tolerance stops at the rounding floor: floor_limited,
-    its true residual within 2x of rho; rho equals the oracle's floor of the returned x;
+    its true residual at most rho; rho equals the oracle's floor of the returned x;
     the solution matches an exact solve (sparse LU plus one refinement step with an
     extended-precision residual) within kappa_est (r_gpu + r_exact) / ||b||."""
     print(f"\n[stagnation {case}]", flush=True)
@@ -72,7 +72,7 @@ def test_solve_to_stagnation(case):
         print(f"[stagnation {case}] {st['iterations']} it, {st['replacements']} replacements, "
               f"rel {st['rel_residual']:.3e}, rho {rho:.3e}, floor_limited {st['floor_limited']}", flush=True)
         assert st["floor_limited"] and st["status"] == 0
-        assert st["rel_residual"] <= 2.0 * rho
+        assert st["rel_residual"] <= rho
         ref_rho = floor.residual_floor(H.levels[H.L], nu[H.L], H.ncomp, b, xg)
         assert abs(rho - ref_rho) <= 1e-12 * ref_rho
         A = H.A[H.L]

@@ -127,12 +127,16 @@ def test_vcycle_contracts_and_solvers_reach_tolerance(full):
     b = G.load_vector(torch.from_numpy(np.ascontiguousarray(f.T)).cuda().ravel())
     bn = float(torch.linalg.vector_norm(b))
     x, st = G.solve(b, solver="pcg", tol=1e-8, max_iter=4000, raise_on_noconv=False)
-    assert st["converged"] or st["floor_limited"], st
+    print(f"\n[129^3 FP64-MG PCG] {st['iterations']} it, rel {st['rel_residual']:.3e}, "
+          f"rounding floor rho {st['floor_estimate']:.3e}, converged {st['converged']}, "
+          f"floor_limited {st['floor_limited']}", flush=True)
+    assert st["status"] == 0 and (st["converged"] or st["floor_limited"]), st
     # the reported residual, recomputed with the library's residual and a host norm
     r = G.residual(L, b, x).cpu().numpy()
     rel = np.linalg.norm(r) / bn
     assert abs(rel - st["rel_residual"]) <= 1e-3 * rel
-    assert rel <= 5e-8
+    # either below 1e-8, or at most the rounding floor of the iterate
+    assert rel <= max(1e-8, st["floor_estimate"])
 
     def anorm(v):
         return float(torch.dot(v, G.apply(L, v))) ** 0.5
@@ -146,9 +150,11 @@ def test_vcycle_contracts_and_solvers_reach_tolerance(full):
     G32 = Hierarchy(L, NC, nus[L], nus[:L], mg_dtype="f32", mg_nu_dtype="bf16")
     try:
         x32, st32 = G32.solve(b, solver="fcg", tol=1e-8, max_iter=4000, raise_on_noconv=False)
-        assert st32["converged"] or st32["floor_limited"], st32
+        print(f"[129^3 FP32-MG FCG] {st32['iterations']} it, rel {st32['rel_residual']:.3e}, "
+              f"rho {st32['floor_estimate']:.3e}", flush=True)
+        assert st32["status"] == 0 and (st32["converged"] or st32["floor_limited"]), st32
         r = G.residual(L, b, x32).cpu().numpy()
-        assert np.linalg.norm(r) / bn <= 5e-8
+        assert np.linalg.norm(r) / bn <= max(1e-8, st32["floor_estimate"]) * (1 + 1e-6)
         # the mixed-precision solution against the FP64-MG one, both at the 1e-8 residual
         # level: reported, in the energy norm of the FP64 operator
         dx = x32 - x

@@ -182,7 +182,7 @@ def test_fgmres_stops_at_the_rounding_floor(case):
     # The true residual of an FP64 iterate cannot go below a floor set by rounding.
     # Measure that floor with an unreachable tolerance, then ask for a third of it: the
     # solve must stop by itself (floor_limited, AGCA_OK) long before max_iter, with a
-    # residual within 10x of the tolerance.
+    # residual within 10x of the tolerance and at most the velocity block's rounding floor.
     L, levels, H, S, fu, GS, _ = case
     if L != 3:
         pytest.skip("one size is enough")
@@ -199,6 +199,8 @@ def test_fgmres_stops_at_the_rounding_floor(case):
           f"rel {st['rel_residual']:.2e}, floor_limited {st['floor_limited']}", flush=True)
     assert st["floor_limited"] and not st["converged"]
     assert tol < st["rel_residual"] < 10 * tol
+    # the evidence the stop needs: at most the rounding floor of the velocity block
+    assert 0 < st["floor_estimate"] and st["rel_residual"] <= max(tol, st["floor_estimate"])
     assert st["iterations"] < 3000
     xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
     # recomputed by the oracle (assembled K, another order of additions): the same floor

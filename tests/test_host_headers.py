@@ -81,24 +81,32 @@ def test_galerkin_blocks(exe, ncomp, l):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-def _stop(exe, tol, rho, seq):
-    txt = f"stop {tol:.17g} {rho:.17g} {len(seq)} " + " ".join(f"{v:.17g}" for v in seq)
+def _stop(exe, tol, rho, seq, at_end=None):
+    ends = at_end if at_end is not None else [1] * len(seq)
+    txt = f"stop {tol:.17g} {rho:.17g} {len(seq)} " + " ".join(f"{v:.17g} {e}" for v, e in zip(seq, ends))
     return [int(v) for v in _run(exe, txt)]
 
 
 def test_stop_rule(exe):
     CONT, FLOOR, STALL = 0, 1, 2
-    # stagnation within 2x of the floor rho (rho above tol): a floor stop
-    assert _stop(exe, 1e-8, 2e-8, [3.5e-8, 3.4e-8, 3.45e-8]) == [CONT, CONT, FLOOR]
+    # stagnation below the floor rho (rho above tol): a floor stop
+    assert _stop(exe, 1e-8, 4e-8, [3.5e-8, 3.4e-8, 3.45e-8]) == [CONT, CONT, FLOOR]
+    # the same stagnation above a floor of 2e-8: not success
+    assert _stop(exe, 1e-8, 2e-8, [3.5e-8, 3.4e-8, 3.45e-8]) == [CONT, CONT, STALL]
     # a stop 75x above tol with a floor far below it is not success
     assert _stop(exe, 1e-8, 1e-9, [7.5e-7, 7.4e-7, 7.6e-7]) == [CONT, CONT, STALL]
-    # the same residuals with a floor estimate of 1.6e-7: still more than 2x above it
+    # the same residuals with a floor estimate of 1.6e-7: still above it
     assert _stop(exe, 1e-8, 1.6e-7, [7.5e-7, 7.4e-7, 7.6e-7]) == [CONT, CONT, STALL]
-    # a tolerance below the floor: stagnation at 1.5 x tol with rho < tol is a floor stop
-    assert _stop(exe, 1e-8, 5e-9, [1.6e-8, 1.5e-8, 1.55e-8]) == [CONT, CONT, FLOOR]
-    # steady improvement continues until the check budget (8) is spent
+    # a tolerance below the floor: stagnation at 1.5 x tol with rho of 2 x tol is a floor stop
+    assert _stop(exe, 1e-8, 2e-8, [1.6e-8, 1.5e-8, 1.55e-8]) == [CONT, CONT, FLOOR]
+    # replacements that halve the true residual never stop, however many (recurrence
+    # above tol); the floor then shows as two replacements without a 10 % gain
+    seq = [0.5 ** k for k in range(30)] + [0.5 ** 29 * 0.95, 0.5 ** 29 * 0.97]
+    out = _stop(exe, 1e-12, 2e-9, seq, at_end=[0] * len(seq))
+    assert out[:31] == [CONT] * 31 and out[31] == FLOOR
+    # steady improvement with the recurrence at tol continues until 8 such checks
     seq = [1e-6 * 0.5 ** k for k in range(8)]
     out = _stop(exe, 1e-12, 1e-9, seq)
     assert out[:7] == [CONT] * 7 and out[7] == STALL
-    out = _stop(exe, 1e-12, 5e-9, seq)
-    assert out[7] == FLOOR      # 7.8e-9 <= 2 * 5e-9
+    out = _stop(exe, 1e-12, 8e-9, seq)
+    assert out[7] == FLOOR      # 7.8e-9 <= 8e-9

@@ -347,6 +347,19 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* opts, const doub
  * for the call.  AGCA_E_INVALID for a bad L or a non-finite result. */
 int32_t agca_macro_gradient(int32_t L, const double* eta_nodes, double* gmax, void* stream);
 
+/* agca_macro_gradient without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the per-macro maxima live in a fixed file-scope device array of 48 64-bit slots (384
+ * bytes, one per macro element, whatever L) that each GPU keeps until the process ends,
+ * instead of the 384 bytes agca_macro_gradient allocates per call.  The first call on a
+ * device looks the array's address up on that device (AGCA_E_HIP if that fails).  The
+ * slots are cleared by a fill kernel at the start of every call.  All calls on one GPU
+ * share its array: calls that overlap on one GPU (other streams or threads) race and
+ * must be serialised by the caller.  Arguments, results and errors as
+ * agca_macro_gradient (L in [1, 9], else AGCA_E_INVALID); the copy of the 48 results to
+ * the host synchronises `stream`. */
+int32_t agca_macro_gradient_noalloc(int32_t L, const double* eta_nodes, double* gmax, void* stream);
+
 /* b = load vector of a per-element constant source: b_i = sum_e f_e |e| / 4 on
  * level L.  f: device, ncomp blocks of 6 n_L^3 doubles; b: device FP64 level vector. */
 int32_t agca_load_vector(agca_hier* h, const double* f, double* b);

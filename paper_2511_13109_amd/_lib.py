@@ -74,6 +74,7 @@ SIGNATURES = {
                                 C.POINTER(C.c_void_p)]),
     "agca_destroy": (C.c_int32, [C.c_void_p]),
     "agca_macro_gradient": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "agca_macro_gradient_noalloc": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "agca_set_nu": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "agca_set_log_nu": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "agca_query": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(LevelInfo)]),

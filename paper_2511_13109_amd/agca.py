@@ -51,14 +51,15 @@ def validate_config(cfg: _lib.Config) -> int:
     return _lib.load().agca_validate_config(C.byref(cfg))
 
 
-def macro_gradient(L: int, eta_nodes: torch.Tensor, stream=None) -> np.ndarray:
+def macro_gradient(L: int, eta_nodes: torch.Tensor, stream=None, noalloc: bool = False) -> np.ndarray:
     """Largest |grad eta_h| over the finest elements of each of the 48 macro elements
-    (eq. (2.8)); eta_nodes: (2^(L+1)+1)^3 float64 device tensor of nodal values."""
+    (eq. (2.8)); eta_nodes: (2^(L+1)+1)^3 float64 device tensor of nodal values.
+    noalloc: the variant without device allocations (agca_macro_gradient_noalloc)."""
     if eta_nodes.dtype != torch.float64 or eta_nodes.numel() != (2 ** (L + 1) + 1) ** 3:
         raise ValueError("eta_nodes must hold (2^(L+1)+1)^3 float64 nodal values")
     st = stream if stream is not None else torch.cuda.current_stream(eta_nodes.device)
     out = np.zeros(48)
-    name = "agca_macro_gradient"
+    name = "agca_macro_gradient_noalloc" if noalloc else "agca_macro_gradient"
     check(getattr(_lib.load(), name)(L, _ptr(eta_nodes), out.ctypes.data_as(C.c_void_p),
                                      C.c_void_p(st.cuda_stream)), name)
     return out

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -940,6 +941,69 @@ int32_t agca_macro_gradient(int32_t L, const double* eta_nodes, double* gmax, vo
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(AGCA_E_HIP, std::string("macro gradient: ") + hipGetErrorString(e));
+    for (int k = 0; k < 48; ++k) {
+        double v;
+        std::memcpy(&v, &bits[k], sizeof(v));
+        if (!std::isfinite(v)) return fail(AGCA_E_INVALID, "non-finite nodal values");
+        gmax[k] = v;
+    }
+    return AGCA_OK;
+}
+
+}  // extern "C"
+
+// Scratch of agca_macro_gradient_noalloc: one 64-bit slot per macro element (the bit
+// pattern of a non-negative double, so an unsigned atomic maximum orders the values),
+// in a file-scope device array instead of a per-call allocation.  Each GPU holds its own
+// copy, at its own address, until the process ends; host code uses the address from
+// hipGetSymbolAddress, never the array's name (in host code the name is a host-side
+// stand-in).  Every call on a GPU shares that GPU's copy.
+static constexpr int kMacroScratchSlots = 48;
+static __device__ __align__(256) unsigned long long scratch[kMacroScratchSlots];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device, looked up once per device
+int32_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(AGCA_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(AGCA_E_INVALID, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(AGCA_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return AGCA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t agca_macro_gradient_noalloc(int32_t L, const double* eta_nodes, double* gmax, void* stream) {
+    if (L < 1 || L > 9) return fail(AGCA_E_INVALID, "L must be in [1, 9]");
+    if (!eta_nodes || !gmax) return fail(AGCA_E_INVALID, "null pointer");
+    static_assert(kMacroScratchSlots >= 48, "one scratch slot per macro element");
+    void* ptr = nullptr;
+    TRY(scratch_address(&ptr));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned long long* slots = static_cast<unsigned long long*>(ptr);
+    unsigned long long bits[48];
+    // the slots keep the previous call's maxima: clear them with a fill kernel (all-zero
+    // bits are the double 0.0, below every norm)
+    hipError_t e = launch_fill<double>(48, 0.0, static_cast<double*>(ptr), st);
+    if (e == hipSuccess) e = launch_macro_grad_max(L, eta_nodes, slots, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(bits, slots, sizeof(bits), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return fail(AGCA_E_HIP, std::string("macro gradient (no allocation): ") + hipGetErrorString(e));
     for (int k = 0; k < 48; ++k) {
         double v;
         std::memcpy(&v, &bits[k], sizeof(v));

@@ -116,15 +116,16 @@ SOLVER_KERNEL_BYTES = {
     "k_cube<3, float, unsigned short, 4, false>": ("FP32/BF16 first two passes", _vec(4, 3), 12),
     "k_cube<3, float, unsigned short, 5, false>": ("FP32/BF16 Chebyshev pass", _vec(4, 5), 12),
     "k_cg_update": ("x += a p, r -= a q, r.r (mixed: + FP32 r)", 3 * 6 * 8, 0),
-    "k_dot2<double>": ("z.r (PCG)", 3 * 16, 0),
+    "k_dot2<double>": ("z.r, z.q (PCG)", 3 * 24, 0),
     "k_dot2<float>": ("z.r, z.q (FCG, FP32 z)", 3 * 20, 0),
     "k_zpbp_dev<double>": ("p = z + beta p", 3 * 24, 0),
     "k_zpbp_dev<float>": ("p = z + beta p (FP32 z)", 3 * 20, 0),
     # per fine node; the coarse vector (1/8 of the nodes) is added below
-    "k_restrict<3, double>": ("restriction 129^3 -> 65^3", 3 * 8, 0),
-    "k_restrict<3, float>": ("restriction 129^3 -> 65^3, FP32", 3 * 4, 0),
-    "k_prolong_add<3, double>": ("prolongation 65^3 -> 129^3", 3 * 16, 0),
-    "k_prolong_add<3, float>": ("prolongation 65^3 -> 129^3, FP32", 3 * 8, 0),
+    "k_restrict<3, double>": ("restriction to the next coarser level", 3 * 8, 0),
+    "k_restrict<3, float>": ("restriction to the next coarser level, FP32", 3 * 4, 0),
+    "k_prolong_add<3, double>": ("prolongation from the next coarser level", 3 * 16, 0),
+    "k_prolong_add<3, float>": ("prolongation from the next coarser level, FP32", 3 * 8, 0),
+    "k_floor_terms<3>": ("rounding floor terms (|b| + sum |A_e||x_e|)", 3 * 16, 48),
 }
 
 
@@ -164,33 +165,36 @@ def summarize_trace(path: str, L: int = 6) -> str:
 
 def summarize_profile(d: str, command_prefix: str) -> str:
     """Markdown summary of a profiling directory written by the three rocprofv3 runs
-    named in the text (kernel statistics, FETCH_SIZE pass, WRITE_SIZE pass)."""
+    named in the text (kernel statistics of the bench command, FETCH_SIZE pass,
+    WRITE_SIZE pass); the workload is the one of the bench line in <dir>/bench.json."""
     import csv
     lines = []
     stats = list(csv.DictReader(open(os.path.join(d, "stats", "bench_kernel_stats.csv"))))
     total = sum(float(r["TotalDurationNs"]) for r in stats)
-    bench = json.loads(open(os.path.join(d, "bench.json")).read())
+    bench = json.loads(open(os.path.join(d, "bench.json")).read().strip().splitlines()[-1])
     L = bench["config"]["levels"] - 1
+    n = 2 ** (L + 1)
+    name = bench["config"]["workload"].split(":")[0]
     bytes_launch = apply_bytes(L, 3)
-    lines += ["# Fine-grid apply and solve kernels, vector viscous block on 129^3 nodes (sinker workload)",
+    lines += [f"# Fine-grid apply and solve kernels, vector viscous block on {n + 1}^3 nodes ({name})",
               "",
-              "All commands run from the repository root after `cd /tmp && export TMPDIR=/tmp`; "
-              "this file is written by `python3 bench.py --summarize-profile <dir>`.",
+              "All commands run from /tmp after `cd /tmp && export TMPDIR=/tmp`, with the repository "
+              "at `$R`; this file is written by `python3 bench.py --summarize-profile <dir>`.",
               "",
-              "## Kernel statistics of one bench step",
-              "",
-              "Hierarchy rebuild (twice), 20 FP64 fine applies, FP64-MG PCG and FP32-MG FCG to 1e-8.",
+              "## Kernel statistics of the bench command",
               "",
               f"    {command_prefix}rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/stats "
-              "-o bench -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+              "-o bench -- python3 $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline > <dir>/bench.json",
               "",
-              f"Total kernel time {total / 1e6:.1f} ms.  k_cube template arguments: <components, "
-              "vector type, coefficient type, mode (0 apply, 1 residual, 2 Jacobi-type pass, 3 apply "
-              "with dot, 4 first two passes from zero, 5 Chebyshev pass), stored blocks>.",
+              f"Total kernel time {total / 1e6:.1f} ms (hierarchy rebuilds, cold FP64 applies and "
+              "V-cycles of 3 steps, the FP64-MG PCG and FP32-MG FCG solves, the 129^3 extra keys).  "
+              "k_cube template arguments: <components, vector type, coefficient type, mode (0 apply, "
+              "1 residual, 2 Jacobi-type pass, 3 apply with dot, 4 first two passes from zero, "
+              "5 Chebyshev pass), stored blocks>.",
               "",
               "| kernel | calls | avg us | total ms | % |",
               "|---|---|---|---|---|"]
-    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:24]:
         lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
 
@@ -213,40 +217,46 @@ def summarize_profile(d: str, command_prefix: str) -> str:
     copy_rate = 2 * copy_kib * 1024 / (float(np.median(cpd)) * 1e-9) / 1e9
     ro = bench["roofline"]
     fine = [r for r in stats if _short(r["Name"]) == FINE_APPLY_KERNEL]
+    # launches on the finest level only (the coarse element-loop levels use the same kernel)
+    tr_path = os.path.join(d, "stats", "fine_apply_trace.csv")
+    fine_us = None
+    rows = list(csv.DictReader(open(tr_path))) if os.path.exists(tr_path) else []
+    if rows:
+        big = max(int(r["Grid_Size_X"]) for r in rows)
+        ds = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows
+              if int(r["Grid_Size_X"]) == big]
+        fine_us = (len(ds), float(np.mean(ds)) / 1e3)
     if fine:
-        lines += ["", f"Fine apply `{FINE_APPLY_KERNEL}`: {fine[0]['Calls']} calls, rocprofv3 average "
-                      f"{float(fine[0]['AverageNs']) / 1e3:.2f} us (HIP events in the bench line: "
-                      f"{ro['avg_launch_us']} us)."]
+        lines += ["", f"Fine apply `{FINE_APPLY_KERNEL}`: {fine[0]['Calls']} calls on all levels, "
+                      f"rocprofv3 average {float(fine[0]['AverageNs']) / 1e3:.2f} us."]
+    if fine_us:
+        lines += [f"On the finest level ({n + 1}^3 nodes): {fine_us[0]} launches, rocprofv3 average "
+                  f"{fine_us[1]:.1f} us; HIP events in the same run's bench line: {ro['avg_launch_us']} us."]
     lines += ["",
-              f"## HBM traffic of the FP64 fine-grid apply (`{FINE_APPLY_KERNEL}`), 129^3 nodes",
+              f"## HBM traffic of the FP64 fine-grid apply (`{FINE_APPLY_KERNEL}`), {n + 1}^3 nodes",
               "",
               "Two counter passes, each in a run of its own; the driver builds the hierarchy, runs 5 "
               "FP64 fine applies, then copies a 256 MiB tensor three times to calibrate the counters:",
               "",
               f"    {command_prefix}rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o run "
-              "-- python3 bench.py --profile-apply",
+              f"-- python3 $R/bench.py --profile-apply --workload {name}",
               f"    {command_prefix}rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o run "
-              "-- python3 bench.py --profile-apply",
+              f"-- python3 $R/bench.py --profile-apply --workload {name}",
               "",
               f"* calibration (256 MiB copy): FETCH_SIZE reads {np.median(fc):.0f} KiB -> factor {ff:.3f}; "
               f"WRITE_SIZE reads {np.median(wc):.0f} KiB -> factor {fw:.3f}",
               f"* copy kernel rate in the counter run: {copy_rate:.0f} GB/s (read + write)",
-              f"* apply (median of the warm dispatches): FETCH_SIZE {np.median(fa):.0f} KiB, "
+              f"* apply (median of the dispatches after the first): FETCH_SIZE {np.median(fa):.0f} KiB, "
               f"WRITE_SIZE {np.median(wa):.0f} KiB",
               f"* scaled traffic per launch: read {read_b / 1e6:.1f} MB + write {write_b / 1e6:.1f} MB "
               f"= {traffic / 1e6:.1f} MB",
-              f"* algorithmic bytes per launch: {bytes_launch / 1e6:.1f} MB (u and v: 3 x 8 B x 129^3 "
-              f"each; nu: 8 B x 6 x 128^3) -> traffic / algorithmic = {traffic / bytes_launch:.3f}",
+              f"* algorithmic bytes per launch: {bytes_launch / 1e6:.1f} MB (u and v: 3 x 8 B x {n + 1}^3 "
+              f"each; nu: 8 B x 6 x {n}^3) -> traffic / algorithmic = {traffic / bytes_launch:.3f}",
               "",
-              "## Bench line of the same tree",
-              "",
-              f"    {command_prefix}python3 bench.py --steps 3 --warmup 1",
+              "## Bench line of the profiled run",
               "",
               f"* fine apply: {ro['avg_launch_us']} us per launch (HIP events), {ro['achieved']} GB/s "
               f"= {ro['frac']:.3f} of 8000 GB/s; {bench['value']} GDoF/s",
-              f"* time to 1e-8: FP64-MG PCG {bench['time_to_1e-8_s']['fp64_mg_pcg']} s "
-              f"({bench['iterations']['fp64_mg_pcg']} it), FP32-MG FCG "
-              f"{bench['time_to_1e-8_s']['fp32_mg_fcg']} s ({bench['iterations']['fp32_mg_fcg']} it)",
               "",
               f"traffic_bytes_per_launch: {traffic}",
               f"kernel_source_sha256_16: {ro.get('kernel_source_sha256_16', '(not recorded)')}",
@@ -803,7 +813,7 @@ def main():
         print(summarize_profile(args.summarize_profile, ""))
         return
     if args.summarize_trace:
-        print(summarize_trace(args.summarize_trace))
+        print(summarize_trace(args.summarize_trace, args.level or 6))
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

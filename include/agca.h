@@ -240,7 +240,10 @@ typedef struct {
 
 /* Solve A_L x = b with the AGCA V-cycle as preconditioner inside an FP64 outer
  * loop (PCG for an FP64 V-cycle; FCG(1) or iterative refinement around an FP32
- * V-cycle; stationary V-cycle iteration).  b, x: device FP64 level vectors (boundary
+ * V-cycle; stationary V-cycle iteration).  PCG and FCG run one loop whose new search
+ * direction is A-orthogonalised against the previous one (beta = -z.q / p.q), which
+ * for PCG equals the textbook z.r / rz_old in exact arithmetic and stays conjugate
+ * after residual replacements.  b, x: device FP64 level vectors (boundary
  * slots of b are ignored; norms are taken over the free dofs).
  * Stopping (eq. (4.3)): PCG and FCG replace their recurrence's residual by the true
  * residual b - A x whenever the recurrence has halved since the last replacement, and

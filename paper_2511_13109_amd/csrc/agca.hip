@@ -1370,12 +1370,14 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
         rel = rec_rel = 0.0;
     } else if (rel > o->tol) {
         if (o->solver == AGCA_SOLVER_PCG || o->solver == AGCA_SOLVER_FCG) {
-            // FCG(1): beta = z_k . (r_k - r_{k-1}) / (z_{k-1} . r_{k-1}), formed as
+            // One loop for both: PCG around the FP64 V-cycle and FCG(1) around the FP32
+            // one.  FCG(1): beta = z_k . (r_k - r_{k-1}) / (z_{k-1} . r_{k-1}), formed as
             // -alpha z_k . q_{k-1} / (z_{k-1} . r_{k-1}) = -z_k . q_{k-1} / (p_{k-1} . q_{k-1})
-            // since r_k - r_{k-1} = -alpha q_{k-1} (no copy of the old residual).  With the FP32 V-cycle the residual update
+            // since r_k - r_{k-1} = -alpha q_{k-1} (no copy of the old residual).  With a
+            // fixed SPD preconditioner (PCG) this equals z_k . r_k / (z_{k-1} . r_{k-1}) in
+            // exact arithmetic (z_k . r_{k-1} = 0).  With the FP32 V-cycle the residual update
             // also writes the V-cycle's FP32 input, and z stays in FP32: the dot products
             // and the direction update widen it on the fly.
-            const bool flex = o->solver == AGCA_SOLVER_FCG;
             const bool mixed = mg32(h);
             float *r32 = h->s_r32, *z32 = h->s_z32;
             auto vcycle = [&]() -> int32_t {
@@ -1406,7 +1408,6 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
             TRY(reduce_to(h, h->partial, h->nb_partial, RZ));
             HIPCHK(h, direction(0.0));
             while (it < o->max_iter) {
-                bool replaced = false;  // the true residual replaced the recurrence's this iteration
                 // q = A p fused with p . q
                 int nbq = 0;
                 HIPCHK(h, launch_cube_dot(h->cfg.ncomp, level_op<double>(h, L), p, q, h->partial, &nbq,
@@ -1441,7 +1442,6 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     if (mixed) HIPCHK(h, launch_cast(AGCA_F64, AGCA_F32, r, r32, cnt, h->st));
                     const double rel_true = std::sqrt(rr) / bn;
                     ++replacements;
-                    replaced = true;
                     anchor = rel_true;
                     note_milestones(rel_true);
                     if (rel_true <= o->tol) {
@@ -1458,18 +1458,18 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     rel = rec_rel = rel_true;
                 }
                 TRY(vcycle());
-                // PCG's beta = z.r / rz_old takes r orthogonal to the previous direction, which
-                // a replaced residual is not (near the rounding floor the two residuals differ
-                // in their leading digits, and that beta then loses conjugacy): after a
-                // replacement the new direction is A-orthogonalised against the previous one,
-                // as FCG(1) does at every step
-                const bool orth = flex || replaced;
-                // z . r and, for the A-orthogonalising beta, z . q in one pass
-                HIPCHK(h, dots(orth ? q : nullptr));
+                // The new direction is A-orthogonalised against the previous one, beta =
+                // -z.q / p.q, in both solvers: for PCG (fixed SPD preconditioner) that equals
+                // z.r / rz_old in exact arithmetic, but the latter takes r orthogonal to the
+                // previous direction, which a replaced residual near the rounding floor is
+                // not; with it PCG stalled above the floor (513^3 sinkers: 1.3e-6 against a
+                // floor of 7.3e-7, where the A-orthogonal form reaches 1.9e-7)
+                // z . r and z . q in one pass
+                HIPCHK(h, dots(q));
                 TRY(reduce_to(h, h->partial, h->nb_partial, ZR));
-                if (orth) TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, ZQ));
-                // FCG: beta = -alpha z.q / rz_old = -z.q / p.q; PCG: beta = z.r / rz_old
-                HIPCHK(h, orth ? direction_dev(red + ZQ, red + PQ, -1.0) : direction_dev(red + ZR, red + RZ, 1.0));
+                TRY(reduce_to(h, h->partial + h->nb_partial, h->nb_partial, ZQ));
+                // beta = -alpha z.q / rz_old = -z.q / p.q
+                HIPCHK(h, direction_dev(red + ZQ, red + PQ, -1.0));
                 HIPCHK(h, hipMemcpyAsync(red + RZ, red + ZR, sizeof(double), hipMemcpyDeviceToDevice, h->st));
             }
         } else {

@@ -80,12 +80,14 @@ def test_mean_storage_full_size_matches_blocks(mg_dtype):
         assert Gm.device_bytes() < Gb.device_bytes()
         b = Gb.load_vector(f)
         solver = "fcg" if mg_dtype == "f32" else "pcg"
-        _, sb = Gb.solve(b, solver=solver, tol=1e-8, max_iter=2000, raise_on_noconv=False)
-        _, sm = Gm.solve(b, solver=solver, tol=1e-8, max_iter=2000, raise_on_noconv=False)
+        # to 1e-7, above this workload's FP64 rounding floor (rho = 4.5e-8): near the floor
+        # the iteration at which stagnation shows moves with the order of additions
+        _, sb = Gb.solve(b, solver=solver, tol=1e-7, max_iter=2000, raise_on_noconv=False)
+        _, sm = Gm.solve(b, solver=solver, tol=1e-7, max_iter=2000, raise_on_noconv=False)
         print(f"[{mg_dtype}] blocks {sb['iterations']} it {sb['seconds']*1e3:.1f} ms, "
               f"mean {sm['iterations']} it {sm['seconds']*1e3:.1f} ms, "
               f"bytes {Gb.device_bytes()} -> {Gm.device_bytes()}", flush=True)
-        assert sm["converged"] or sm["floor_limited"]
+        assert sb["converged"] and sm["converged"]
         assert abs(sm["iterations"] - sb["iterations"]) <= max(3, sb["iterations"] // 20)
     finally:
         Gb.close()

@@ -147,6 +147,9 @@ class StokesSystem:
             return y
         return solve
 
+    def z_hierarchy(self, omega: float = 2.0 / 3.0, sweeps: int = 2) -> "ZHierarchy":
+        return ZHierarchy(self, omega, sweeps)
+
     def bfbt(self, iters: int = 0, z_solve: Callable = None) -> Callable:
         """S~^-1 of eq. (4.2): Z^-1 B W^-1 A W^-1 B^T Z^-1, with Z^-1 the fixed-step
         Jacobi-CG solve (or a given z_solve, e.g. an exact one)."""
@@ -181,10 +184,11 @@ class StokesSystem:
               schur_iters: int = 20) -> mg.SolveResult:
         if schur == "mass":
             M = self.precond(precond)
-        elif schur == "bfbt":
+        elif schur in ("bfbt", "bfbt_mg"):
             if solver != "fgmres":
                 raise ValueError("the BFBT approximation is not a fixed linear map: FGMRES only")
-            M = self.precond(precond, s_inv=self.bfbt(schur_iters))
+            zs = self.z_hierarchy().z_solve(schur_iters) if schur == "bfbt_mg" else None
+            M = self.precond(precond, s_inv=self.bfbt(schur_iters, z_solve=zs))
         else:
             raise ValueError(schur)
         if solver == "fgmres":
@@ -195,3 +199,125 @@ class StokesSystem:
             raise ValueError(solver)
         res.x = self.zero_mean(res.x)
         return res
+
+
+# Offsets of the pressure-space stencils of Z: every coupling of Z = B W^-1 B^T goes
+# through a velocity node j that both pressure hats' supports reach, and B couples a
+# pressure node k with the fine nodes within one Kuhn edge of the fine node 2k, so
+# Z couples k with k + o for o a sum of two Kuhn-lattice edges (offsets in {0,1}^3 or
+# {0,-1}^3): the 65 offsets in [-2,2]^3 with max(o, 0) - min(o, 0) <= 2.  Galerkin
+# coarsening with the linear interpolation keeps that set.
+Z_OFFSETS = [(dx, dy, dz) for dz in range(-2, 3) for dy in range(-2, 3) for dx in range(-2, 3)
+             if max(dx, dy, dz, 0) - min(dx, dy, dz, 0) <= 2]
+
+
+class ZHierarchy:
+    """Geometric multigrid for the BFBT operator Z = B W^-1 B^T of eq. (4.2) (test
+    infrastructure).  The paper solves with Z by an algebraic multigrid cycle inside
+    CG; this is the geometric counterpart on the pressure lattice: levels L-1 (the
+    pressure space, every node a dof) down to 0, linear interpolation P over all nodes
+    (eq. (2.4), no boundary condition), Galerkin coarse operators Z_l = P^T Z_{l+1} P
+    (the constant pressure stays in every Z_l's kernel), damped Jacobi V(sweeps,
+    sweeps) with omega = 2/3 and zero initial guesses, and on level 0 (27 nodes) the
+    solution of minimal norm, from the bordered system [[Z_0, 1], [1^T, 0]].  Z^-1 r
+    (r of zero sum, as every B v is) is then approximated by `iters` steps of CG on
+    Z y = r from y = 0 preconditioned by one V-cycle."""
+
+    def __init__(self, S: StokesSystem, omega: float = 2.0 / 3.0, sweeps: int = 2):
+        levels = S.H.levels
+        Lp = S.H.L - 1
+        self.levels = levels[:Lp + 1]
+        self.omega, self.sweeps = omega, sweeps
+        self.P = [transfer.prolongation(levels[l], levels[l + 1]) for l in range(Lp)]
+        Z = [None] * (Lp + 1)
+        Z[Lp] = S.z_operator()
+        for l in range(Lp - 1, -1, -1):
+            Z[l] = (self.P[l].T @ Z[l + 1] @ self.P[l]).tocsr()
+        self.Z = Z
+        self.D = [z.diagonal().copy() for z in Z]
+        Z0 = Z[0].toarray()
+        n0 = Z0.shape[0]
+        Bord = np.zeros((n0 + 1, n0 + 1))
+        Bord[:n0, :n0] = Z0
+        Bord[:n0, n0] = 1.0
+        Bord[n0, :n0] = 1.0
+        self.coarse_inv = np.linalg.inv(Bord)[:n0, :n0]
+
+    @property
+    def top(self) -> int:
+        return len(self.Z) - 1
+
+    def vcycle(self, r: np.ndarray, l: int = None) -> np.ndarray:
+        if l is None:
+            l = self.top
+        if l == 0:
+            return self.coarse_inv @ r
+        Z, D = self.Z[l], self.D[l]
+        y = np.zeros_like(r)
+        for _ in range(self.sweeps):
+            y = y + self.omega * (r - Z @ y) / D
+        rc = self.P[l - 1].T @ (r - Z @ y)
+        y = y + self.P[l - 1] @ self.vcycle(rc, l - 1)
+        for _ in range(self.sweeps):
+            y = y + self.omega * (r - Z @ y) / D
+        return y
+
+    def z_solve(self, iters: int) -> Callable:
+        """r -> `iters` steps of V-cycle-preconditioned CG on Z y = r from y = 0 (a step
+        whose direction has zero Z-energy has step size zero)."""
+        Z = self.Z[self.top]
+
+        def solve(r):
+            y = np.zeros_like(r)
+            res = r.copy()
+            z = self.vcycle(res)
+            p = z.copy()
+            rz = res @ z
+            for k in range(iters):
+                q = Z @ p
+                pq = p @ q
+                alpha = rz / pq if pq != 0.0 else 0.0
+                y += alpha * p
+                res -= alpha * q
+                if k == iters - 1:
+                    break
+                z = self.vcycle(res)
+                rz_new = res @ z
+                p = z + (rz_new / rz if rz != 0.0 else 0.0) * p
+                rz = rz_new
+            return y
+        return solve
+
+    def stencil(self, l: int) -> np.ndarray:
+        """(65, nodes) entries of Z_l by offset (Z_OFFSETS order) and node: the row of
+        node k at column k + o, 0 where k + o lies outside the lattice."""
+        n = self.levels[l].n
+        n1 = n + 1
+        N = n1 ** 3
+        Zc = self.Z[l].tocoo()
+        r, c = Zc.row, Zc.col
+        o = np.stack([c % n1 - r % n1, (c // n1) % n1 - (r // n1) % n1, c // (n1 * n1) - r // (n1 * n1)], 1)
+        idx = {off: i for i, off in enumerate(Z_OFFSETS)}
+        out = np.zeros((len(Z_OFFSETS), N))
+        for (ox, oy, oz), row, v in zip(o, r, Zc.data):
+            key = (int(ox), int(oy), int(oz))
+            if key not in idx:
+                if abs(v) > 0:
+                    raise ValueError(f"Z couples offset {key}, outside the stencil")
+                continue
+            out[idx[key], row] += v
+        return out
+
+
+def stencil_apply(st: np.ndarray, n: int, x: np.ndarray) -> np.ndarray:
+    """y_k = sum over the 65 offsets o of st[o, k] x_{k+o}, on the (n+1)^3 lattice (terms
+    whose k + o leaves the lattice are dropped: their entries are zero)."""
+    n1 = n + 1
+    X = x.reshape(n1, n1, n1)                       # [z, y, x]
+    y = np.zeros((n1, n1, n1))
+    for i, (dx, dy, dz) in enumerate(Z_OFFSETS):
+        S = st[i].reshape(n1, n1, n1)
+        src = X[max(dz, 0):n1 + min(dz, 0), max(dy, 0):n1 + min(dy, 0), max(dx, 0):n1 + min(dx, 0)]
+        y[max(-dz, 0):n1 + min(-dz, 0), max(-dy, 0):n1 + min(-dy, 0), max(-dx, 0):n1 + min(-dx, 0)] += \
+            S[max(-dz, 0):n1 + min(-dz, 0), max(-dy, 0):n1 + min(-dy, 0), max(-dx, 0):n1 + min(-dx, 0)] * src
+    return y.reshape(-1)

@@ -581,25 +581,40 @@ def report_stokes(args, dev) -> dict:
     out = {"report": w.name, "description": w.description,
            "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3,
            "fgmres_restart": args.stokes_restart, "smoother": args.smoother,
-           "bfbt_z_cg_steps": args.schur_iters}
-    runs = [r for r in (("bfbt", "f32", "fgmres", "triangular", "bfbt"),
+           "bfbt_z_cg_steps": args.schur_iters, "bfbt_mg_z_cg_steps": args.zmg_iters}
+    runs = [r for r in (("bfbt_mg", "f32", "fgmres", "triangular", "bfbt_mg"),
+                        ("bfbt_mg", "f64", "fgmres", "triangular", "bfbt_mg"),
+                        ("bfbt", "f32", "fgmres", "triangular", "bfbt"),
                         ("bfbt", "f64", "fgmres", "triangular", "bfbt"),
                         ("fgmres", "f32", "fgmres", "triangular", "mass"),
                         ("fgmres", "f64", "fgmres", "triangular", "mass"),
                         ("minres", "f32", "minres", "diagonal", "mass"),
                         ("minres", "f64", "minres", "diagonal", "mass"))
-            if r[0] in args.stokes_solvers.split(",")]
+            if r[0] in args.stokes_solvers.split(",") and r[1] in args.stokes_mg.split(",")]
     for _, mg, solver, pc, schur in runs:
         H = Hierarchy(L, 3, nus[L], nus[:L], mg_dtype=mg, mg_nu_dtype=("bf16" if mg == "f32" else "f64"),
                       smoother=args.smoother)
         S = Stokes(H)
         fu = H.load_vector(f)
+        k = args.zmg_iters if schur == "bfbt_mg" else args.schur_iters
+        setup = {}
+        if schur == "bfbt_mg":
+            # the pressure multigrid's assembly (first use after the build), then one
+            # application of S^-1 with it in place
+            rp = torch.randn(S.np, dtype=torch.float64, device=dev)
+            for name in ("zmg_setup_s", "schur_apply_s"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                S.schur_apply(rp, "bfbt_mg", k)
+                torch.cuda.synchronize()
+                setup[name] = round(time.perf_counter() - t0, 4)
         _, _, st = S.solve(fu, solver=solver, restart=args.stokes_restart, tol=w.tol,
                            max_iter=args.stokes_max_iter, record_history=False, raise_on_noconv=False,
-                           precond=pc, schur=schur, schur_iters=args.schur_iters)
-        key = f"{solver}_{pc}" + ("_bfbt" if schur == "bfbt" else "") + f"_{mg}_mg"
+                           precond=pc, schur=schur, schur_iters=k)
+        key = f"{solver}_{pc}" + ("" if schur == "mass" else f"_{schur}") + f"_{mg}_mg"
         out[key] = {k: st[k] for k in ("iterations", "seconds", "rel_residual", "converged",
                                        "floor_limited")}
+        out[key].update(setup)
         print(f"[stokes] {solver} {pc} {schur} {mg}-MG: {st['iterations']} it {st['seconds']:.2f} s "
               f"res {st['rel_residual']:.2e}", file=sys.stderr, flush=True)
         H.close()
@@ -820,11 +835,16 @@ def main():
                     help="finest levels of the apply roofline sweep (6: 129^3, 7: 257^3, 8: 513^3)")
     ap.add_argument("--stokes-max-iter", type=int, default=8000)
     ap.add_argument("--stokes-solvers", default="fgmres,minres",
-                    help="comma-separated subset of bfbt (FGMRES, triangular, BFBT), fgmres "
+                    help="comma-separated subset of bfbt_mg (FGMRES, triangular, BFBT with the "
+                         "pressure multigrid), bfbt (the same with Jacobi-CG Z solves), fgmres "
                          "(triangular, lumped mass) and minres (diagonal, lumped mass)")
     ap.add_argument("--schur-iters", type=int, default=20,
                     help="Jacobi-CG steps per Z solve of the BFBT Schur approximation")
+    ap.add_argument("--zmg-iters", type=int, default=4,
+                    help="multigrid-preconditioned CG steps per Z solve of BFBT with the pressure multigrid")
     ap.add_argument("--stokes-restart", type=int, default=64)
+    ap.add_argument("--stokes-mg", default="f32,f64",
+                    help="comma-separated V-cycle precisions of the Stokes report runs")
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile, ""))

@@ -306,8 +306,22 @@ typedef enum { AGCA_STOKES_DIAGONAL = 0, AGCA_STOKES_TRIANGULAR = 1 } agca_stoke
  *        Z^-1 is schur_iters steps of Jacobi-preconditioned CG on Z from zero (a step
  *        of zero Z-energy has step size zero).  diag(Z) is formed exactly at the first
  *        solve after every coefficient rebuild (27 products with Z, one per colour of
- *        the nodes by coordinates mod 3).  Not linear in r: FGMRES only. */
-typedef enum { AGCA_SCHUR_MASS = 0, AGCA_SCHUR_BFBT = 1 } agca_stokes_schur;
+ *        the nodes by coordinates mod 3).  Not linear in r: FGMRES only.
+ * BFBT_MG : the same S^-1 with each Z^-1 being schur_iters steps of CG on Z from zero
+ *        preconditioned by one V-cycle of a geometric multigrid for Z (the paper uses
+ *        an algebraic multigrid cycle there): levels L-1 (the pressure space) down to
+ *        0 with the linear interpolation P over all nodes, Galerkin operators
+ *        Z_l = P^T Z_{l+1} P, each stored as a stencil over the 65 offsets o in
+ *        [-2,2]^3 with max(o,0) - min(o,0) <= 2 (sums of two Kuhn edges: every
+ *        coupling of Z and of its Galerkin coarsenings), damped Jacobi V(2,2) cycles
+ *        with omega = 2/3 from zero, and on level 0 (27 nodes) the minimal-norm
+ *        solution (bordered system [[Z_0, 1], [1^T, 0]]).  The stencils are assembled
+ *        at the first use after every coefficient rebuild, by probing: Z (then
+ *        P^T Z_{l+1} P) applied to the indicators of 65 node colours
+ *        (x + 34 y + 44 z) mod 65, a colouring that separates the 65 offsets.
+ *        Device memory: 69 doubles per pressure node of every level (about
+ *        69 * 8/7 (n_{L-1}+1)^3 doubles), kept until destroy.  FGMRES only. */
+typedef enum { AGCA_SCHUR_MASS = 0, AGCA_SCHUR_BFBT = 1, AGCA_SCHUR_BFBT_MG = 2 } agca_stokes_schur;
 typedef struct {
     int32_t solver;          /* agca_stokes_solver                                          */
     int32_t restart;         /* FGMRES restart length, 1..510                              */
@@ -316,7 +330,7 @@ typedef struct {
     double tol;              /* stop when ||r||_2 <= tol ||(f, g)||_2 (eq. (4.3))           */
     int32_t precond;         /* agca_stokes_precond                                         */
     int32_t schur;           /* agca_stokes_schur                                           */
-    int32_t schur_iters;     /* BFBT: CG steps per Z solve, 1..1000 (ignored for MASS)      */
+    int32_t schur_iters;     /* BFBT, BFBT_MG: CG steps per Z solve, 1..1000 (ignored for MASS) */
 } agca_stokes_opts;
 
 /* Solve [[A, B^T], [B, 0]] (u, p) = (f, g) in FP64 with a block preconditioner built
@@ -328,7 +342,7 @@ typedef struct {
  * residual is checked every step, so a run that stagnates reports AGCA_E_NOCONV, never a
  * false convergence).  The returned p has zero mean over the pressure nodes.  Work
  * space: 2 restart + 5 (FGMRES; one more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy;
- * BFBT adds 3 velocity and 8 pressure vectors.
+ * BFBT and BFBT_MG add 3 velocity and 8 pressure vectors, BFBT_MG its multigrid.
  * FGMRES stops early with stats->floor_limited when a restart cycle's residual
  * estimate reached tol but the true residual after it is above tol, less than 5 %
  * below its value four cycles earlier, and at most max(tol, rho_A), rho_A the
@@ -341,6 +355,26 @@ typedef struct {
  * or the MINRES true residuals. */
 int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* opts, const double* f,
                           const double* g, double* u, double* p, agca_solve_stats* stats);
+
+/* q = S^-1 rp with the Schur approximation `schur` (agca_stokes_schur; schur_iters CG
+ * steps per Z solve for BFBT and BFBT_MG, ignored for MASS): the pressure block of the
+ * block-diagonal preconditioner.  rp, q: device pressure vectors, distinct.  Assembles
+ * what the approximation needs on first use after a coefficient rebuild.
+ * AGCA_E_INVALID for an unknown schur or schur_iters outside [1, 1000]. */
+int32_t agca_stokes_schur_apply(agca_hier* h, int32_t schur, int32_t schur_iters, const double* rp,
+                                double* q);
+
+/* The BFBT_MG pressure multigrid's operator on level `level` (0..L-1; L-1 is the pressure
+ * space itself, Z = B W^-1 B^T): out (device, 65 (n_level+1)^3 doubles) receives
+ * S[i (n+1)^3 + k] = Z_level(k, k + o_i), o_i the i-th of the 65 stencil offsets ordered
+ * by z, then y, then x ascending, 0 where node k + o_i lies outside the lattice.
+ * Assembles the hierarchy if needed.  AGCA_E_INVALID for a level out of range. */
+int32_t agca_stokes_z_stencil(agca_hier* h, int32_t level, double* out);
+
+/* y = one V-cycle of the BFBT_MG pressure multigrid applied to r (device pressure
+ * vectors, distinct; a zero-sum r gives the cycle's approximation to the zero-sum
+ * solution of Z y = r).  Assembles the hierarchy if needed. */
+int32_t agca_stokes_z_vcycle(agca_hier* h, const double* r, double* y);
 
 /* Gradient test of eq. (2.8): for every macro element k (level-0 element id, 0..47)
  * the largest norm of grad eta_h over the finest elements inside it, eta_h the P1

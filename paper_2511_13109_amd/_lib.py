@@ -52,7 +52,7 @@ class StokesOpts(C.Structure):
 
 STOKES_FGMRES, STOKES_MINRES = 0, 1
 STOKES_DIAGONAL, STOKES_TRIANGULAR = 0, 1
-SCHUR_MASS, SCHUR_BFBT = 0, 1
+SCHUR_MASS, SCHUR_BFBT, SCHUR_BFBT_MG = 0, 1, 2
 
 
 class SolveStats(C.Structure):
@@ -103,6 +103,9 @@ SIGNATURES = {
     "agca_stokes_mass": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "agca_stokes_solve": (C.c_int32, [C.c_void_p, C.POINTER(StokesOpts), C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.POINTER(SolveStats)]),
+    "agca_stokes_schur_apply": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    "agca_stokes_z_stencil": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "agca_stokes_z_vcycle": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "agca_device_bytes": (C.c_int64, [C.c_void_p]),
     "agca_last_error": (C.c_char_p, []),
 }

@@ -319,16 +319,38 @@ class Stokes:
         check(self.H._lib.agca_stokes_mass(self.H._h, _ptr(m)), "agca_stokes_mass")
         return m
 
+    SCHUR = {"mass": _lib.SCHUR_MASS, "bfbt": _lib.SCHUR_BFBT, "bfbt_mg": _lib.SCHUR_BFBT_MG}
+
+    def schur_apply(self, rp: torch.Tensor, schur: str = "bfbt_mg", schur_iters: int = 4,
+                    q: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """q = S^-1 rp, the pressure block of the block-diagonal preconditioner."""
+        q = self.pvec() if q is None else q
+        check(self.H._lib.agca_stokes_schur_apply(self.H._h, self.SCHUR[schur], schur_iters, _ptr(rp), _ptr(q)),
+              "agca_stokes_schur_apply")
+        return q
+
+    def z_stencil(self, level: int) -> torch.Tensor:
+        """(65, (n_level+1)^3) stencil of the pressure multigrid's operator on `level`."""
+        out = torch.empty(65 * self.H.nodes(level), dtype=torch.float64, device=self.H.device)
+        check(self.H._lib.agca_stokes_z_stencil(self.H._h, level, _ptr(out)), "agca_stokes_z_stencil")
+        return out.view(65, -1)
+
+    def z_vcycle(self, r: torch.Tensor) -> torch.Tensor:
+        y = self.pvec()
+        check(self.H._lib.agca_stokes_z_vcycle(self.H._h, _ptr(r), _ptr(y)), "agca_stokes_z_vcycle")
+        return y
+
     def solve(self, f: torch.Tensor, g: Optional[torch.Tensor] = None, solver: str = "fgmres",
               restart: int = 30, tol: float = 1e-8, max_iter: int = 1000, record_history: bool = True,
               raise_on_noconv: bool = True, precond: str = "diagonal", schur: str = "mass",
               schur_iters: int = 20):
-        """schur: 'mass' (1/nu lumped mass) or 'bfbt' (eq. (4.2), FGMRES only, each Z solve
-        schur_iters Jacobi-CG steps)."""
+        """schur: 'mass' (1/nu lumped mass), 'bfbt' (eq. (4.2), FGMRES only, each Z solve
+        schur_iters Jacobi-CG steps) or 'bfbt_mg' (the same with each Z solve schur_iters
+        CG steps preconditioned by a pressure multigrid V-cycle)."""
         opts = _lib.StokesOpts()
         opts.solver = {"fgmres": _lib.STOKES_FGMRES, "minres": _lib.STOKES_MINRES}[solver]
         opts.precond = {"diagonal": _lib.STOKES_DIAGONAL, "triangular": _lib.STOKES_TRIANGULAR}[precond]
-        opts.schur = {"mass": _lib.SCHUR_MASS, "bfbt": _lib.SCHUR_BFBT}[schur]
+        opts.schur = self.SCHUR[schur]
         opts.schur_iters = schur_iters
         opts.restart, opts.max_iter, opts.tol = restart, max_iter, tol
         opts.record_history = 1 if record_history else 0

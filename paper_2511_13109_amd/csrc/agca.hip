@@ -14,6 +14,7 @@
 
 #include "cube_math.h"
 #include "stop_rule.h"
+#include "zstencil.h"
 #include "internal.h"
 
 using namespace agca;
@@ -88,8 +89,12 @@ struct agca_hier {
     double* st_work = nullptr;   // Krylov vectors, st_work_vecs of them
     double* st_tri = nullptr;    // during a triangular-preconditioned solve: one Stokes vector
     double* st_bfbt = nullptr;   // BFBT Schur approximation: W^-1, diag(Z) and work vectors
-    int64_t bfbt_version = -1;   // nu_version diag(Z) was formed for
+    int64_t bfbt_version = -1;   // nu_version W^-1 was formed for
     int st_schur_iters = 0;      // during a BFBT-preconditioned solve: CG steps per Z solve
+    bool st_schur_mg = false;    // ... preconditioned by the pressure multigrid (else Jacobi)
+    int64_t zdiag_version = -1;  // nu_version diag(Z) was formed for
+    double* st_zmg = nullptr;    // pressure multigrid for Z: stencils and vectors of levels 0..L-1
+    int64_t zmg_version = -1;    // nu_version the stencils were assembled for
     double* st_gs = nullptr;     // Gram-Schmidt partial sums, st_gs_cap doubles
     int64_t st_gs_cap = 0;
     int64_t st_work_vecs = 0;
@@ -1619,25 +1624,224 @@ static int32_t z_apply(agca_hier* h, const Bfbt& w, const double* y, double* out
     TRY(stokes_div(h, w.v1, out));
     return AGCA_OK;
 }
-// W^-1 (0 on boundary velocity dofs) and diag(Z), once per coefficient rebuild.  Two
-// pressure nodes of one colour (coordinates equal mod 3) are at least 3 pressure cells
-// apart, while B^T e_k lives on the velocity nodes within one pressure cell of node k:
-// Z_km = 0 for distinct k, m of one colour, so Z applied to a colour's indicator holds
-// Z_kk on that colour's nodes.
-static int32_t bfbt_ready(agca_hier* h) {
+// W^-1 (0 on boundary velocity dofs), once per coefficient rebuild, and with `diag`
+// diag(Z) as well.  Two pressure nodes of one colour (coordinates equal mod 3) are at
+// least 3 pressure cells apart, while B^T e_k lives on the velocity nodes within one
+// pressure cell of node k: Z_km = 0 for distinct k, m of one colour, so Z applied to a
+// colour's indicator holds Z_kk on that colour's nodes.
+static int32_t bfbt_ready(agca_hier* h, bool diag) {
     const StokesDims d = stokes_dims(h);
     if (!h->st_bfbt) TRY(alloc_t(h, &h->st_bfbt, (size_t)(3 * d.nu + 8 * d.np + 8)));
-    if (h->bfbt_version == h->nu_version) return AGCA_OK;
     const Bfbt w = bfbt_bufs(h);
-    HIPCHK(h, launch_invert_diag<double>(d.nu, h->lv[h->cfg.L].diag, w.winv, h->st));
+    if (h->bfbt_version != h->nu_version) {
+        HIPCHK(h, launch_invert_diag<double>(d.nu, h->lv[h->cfg.L].diag, w.winv, h->st));
+        h->bfbt_version = h->nu_version;
+    }
+    if (!diag || h->zdiag_version == h->nu_version) return AGCA_OK;
     for (int c = 0; c < 27; ++c) {
         HIPCHK(h, launch_colour(d.nc, c, 0, nullptr, w.ztmp, h->st));
         TRY(z_apply(h, w, w.ztmp, w.zq));
         HIPCHK(h, launch_colour(d.nc, c, 1, w.zq, w.zdiag, h->st));
     }
-    h->bfbt_version = h->nu_version;
+    h->zdiag_version = h->nu_version;
     return AGCA_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Geometric multigrid for Z on the pressure lattice (the paper solves with Z by an
+// algebraic multigrid cycle inside CG): levels L-1 (the pressure space) down to 0 with
+// the linear interpolation P over all nodes, Galerkin operators Z_l = P^T Z_{l+1} P
+// (the constant pressure stays in every kernel), stored as 65-offset stencils
+// (zstencil.h) assembled by probing with 65 colours; damped Jacobi V(2,2) cycles,
+// omega = 2/3, zero initial guesses, and on level 0 (27 nodes) the minimal-norm
+// solution from the bordered system [[Z_0, 1], [1^T, 0]].
+// ---------------------------------------------------------------------------
+constexpr int kZSweeps = 2;
+constexpr double kZOmega = 2.0 / 3.0;
+
+struct ZLevel {
+    int n = 0;
+    int64_t N = 0;
+    double *S = nullptr, *r = nullptr, *y = nullptr, *a = nullptr, *t = nullptr;
+};
+// levels 0..L-1 carved from st_zmg: per level the stencil (65 N) and four vectors, then
+// the 27 x 27 coarse inverse
+static std::vector<ZLevel> zmg_levels(const agca_hier* h, double** coarse = nullptr) {
+    std::vector<ZLevel> z(h->cfg.L);
+    double* p = h->st_zmg;
+    for (int l = 0; l < h->cfg.L; ++l) {
+        z[l].n = h->lv[l].n;
+        z[l].N = nodes_of(z[l].n);
+        z[l].S = p;
+        p += (int64_t)kZOffsets * z[l].N;
+        for (double** v : {&z[l].r, &z[l].y, &z[l].a, &z[l].t}) {
+            *v = p;
+            p += z[l].N;
+        }
+    }
+    if (coarse) *coarse = p;
+    return z;
+}
+static int64_t zmg_doubles(const agca_hier* h) {
+    int64_t c = 27 * 27;
+    for (int l = 0; l < h->cfg.L; ++l) c += (kZOffsets + 4) * nodes_of(h->lv[l].n);
+    return c;
+}
+
+// inverse of the bordered 28 x 28 matrix [[Z0, 1], [1^T, 0]] by Gauss-Jordan elimination
+// with partial pivoting; its leading 27 x 27 block maps a zero-sum r to the zero-sum
+// solution of Z0 y = r (Z0's kernel is the constants)
+static bool bordered_inverse(const std::vector<double>& Z0, std::vector<double>& M) {
+    constexpr int n = 28;
+    std::vector<double> A(n * n, 0.0), I(n * n, 0.0);
+    for (int i = 0; i < 27; ++i) {
+        for (int j = 0; j < 27; ++j) A[i * n + j] = Z0[i * 27 + j];
+        A[i * n + 27] = 1.0;
+        A[27 * n + i] = 1.0;
+    }
+    for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+    double scale = 0.0;
+    for (double v : A) scale = std::max(scale, std::fabs(v));
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        if (!(std::fabs(A[piv * n + c]) > 1e-13 * scale)) return false;
+        if (piv != c)
+            for (int j = 0; j < n; ++j) {
+                std::swap(A[c * n + j], A[piv * n + j]);
+                std::swap(I[c * n + j], I[piv * n + j]);
+            }
+        const double inv = 1.0 / A[c * n + c];
+        for (int j = 0; j < n; ++j) {
+            A[c * n + j] *= inv;
+            I[c * n + j] *= inv;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = A[r * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                A[r * n + j] -= f * A[c * n + j];
+                I[r * n + j] -= f * I[c * n + j];
+            }
+        }
+    }
+    M.assign(27 * 27, 0.0);
+    for (int i = 0; i < 27; ++i)
+        for (int j = 0; j < 27; ++j) M[i * 27 + j] = I[i * n + j];
+    return true;
+}
+
+// assemble every level's stencil, once per coefficient rebuild: the top level probes the
+// matrix-free Z = B W^-1 B^T, level l < L-1 probes P^T Z_{l+1} P with Z_{l+1}'s stencil
+static int32_t zmg_ready(agca_hier* h) {
+    TRY(bfbt_ready(h, false));
+    if (!h->st_zmg) TRY(alloc_t(h, &h->st_zmg, (size_t)zmg_doubles(h)));
+    if (h->zmg_version == h->nu_version) return AGCA_OK;
+    double* coarse = nullptr;
+    const std::vector<ZLevel> z = zmg_levels(h, &coarse);
+    const int top = h->cfg.L - 1;
+    const Bfbt w = bfbt_bufs(h);
+    for (int c = 0; c < kZColours; ++c) {
+        HIPCHK(h, launch_zprobe(z[top].n, c, w.ztmp, h->st));
+        TRY(z_apply(h, w, w.ztmp, w.zq));
+        HIPCHK(h, launch_zextract(z[top].n, c, w.zq, z[top].S, h->st));
+    }
+    for (int l = top - 1; l >= 0; --l) {
+        const ZLevel &zc = z[l], &zf = z[l + 1];
+        for (int c = 0; c < kZColours; ++c) {
+            HIPCHK(h, launch_zprobe(zc.n, c, zc.r, h->st));
+            HIPCHK(h, launch_prolong_all(zf.n, zc.r, zf.t, h->st));
+            HIPCHK(h, launch_zstencil(0, zf.n, zf.S, zf.t, nullptr, 0.0, zf.a, h->st));
+            HIPCHK(h, launch_restrict_all(zc.n, zf.a, zc.y, h->st));
+            HIPCHK(h, launch_zextract(zc.n, c, zc.y, zc.S, h->st));
+        }
+    }
+    std::vector<double> S0((size_t)kZOffsets * 27), Z0(27 * 27, 0.0), M;
+    HIPCHK(h, hipMemcpyAsync(S0.data(), z[0].S, sizeof(double) * S0.size(), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    for (int k = 0; k < 27; ++k) {
+        const int x = k % 3, y = (k / 3) % 3, zz = k / 9;
+        for (int i = 0; i < kZOffsets; ++i) {
+            const int X = x + kZTable.dx[i], Y = y + kZTable.dy[i], Zc = zz + kZTable.dz[i];
+            if (X < 0 || Y < 0 || Zc < 0 || X > 2 || Y > 2 || Zc > 2) continue;
+            Z0[k * 27 + X + 3 * (Y + 3 * Zc)] = S0[(size_t)i * 27 + k];
+        }
+    }
+    for (double v : Z0)
+        if (!std::isfinite(v)) return fail(AGCA_E_NUMERIC, "non-finite coarse pressure operator");
+    if (!bordered_inverse(Z0, M))
+        return fail(AGCA_E_NUMERIC, "the coarse pressure operator has a kernel beyond the constants");
+    HIPCHK(h, hipMemcpyAsync(coarse, M.data(), sizeof(double) * M.size(), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->zmg_version = h->nu_version;
+    return AGCA_OK;
+}
+
+// y = V_l r: one V(kZSweeps, kZSweeps) cycle on level l from a zero guess (r, y distinct
+// from level l's own work vectors a and t)
+static int32_t zmg_cycle(agca_hier* h, const std::vector<ZLevel>& z, const double* coarse, int l,
+                         const double* r, double* y) {
+    if (l == 0) {
+        HIPCHK(h, launch_zcoarse(coarse, r, y, h->st));
+        return AGCA_OK;
+    }
+    const ZLevel& Z = z[l];
+    // 2 kZSweeps Jacobi results in all, alternating between a and y so that the last is y
+    double* cur = (2 * kZSweeps - 1) % 2 ? Z.a : y;
+    auto other = [&](double* v) { return v == y ? Z.a : y; };
+    HIPCHK(h, launch_zjacobi0(Z.n, Z.S, r, kZOmega, cur, h->st));
+    for (int s = 1; s < kZSweeps; ++s) {
+        double* nxt = other(cur);
+        HIPCHK(h, launch_zstencil(2, Z.n, Z.S, cur, r, kZOmega, nxt, h->st));
+        cur = nxt;
+    }
+    HIPCHK(h, launch_zstencil(1, Z.n, Z.S, cur, r, 0.0, Z.t, h->st));
+    const ZLevel& C = z[l - 1];
+    HIPCHK(h, launch_restrict_all(C.n, Z.t, C.r, h->st));
+    TRY(zmg_cycle(h, z, coarse, l - 1, C.r, C.y));
+    HIPCHK(h, launch_prolong_all_add(Z.n, C.y, cur, h->st));
+    for (int s = 0; s < kZSweeps; ++s) {
+        double* nxt = other(cur);
+        HIPCHK(h, launch_zstencil(2, Z.n, Z.S, cur, r, kZOmega, nxt, h->st));
+        cur = nxt;
+    }
+    if (cur != y) return fail(AGCA_E_STATE, "pressure V-cycle ended outside its output");
+    return AGCA_OK;
+}
+
+// y = iters steps of CG on Z y = r from y = 0 preconditioned by one pressure V-cycle,
+// with the assembled top-level stencil as the operator (scalars as in z_solve)
+static int32_t z_solve_mg(agca_hier* h, const Bfbt& w, const double* r, double* y, int iters) {
+    const int64_t np = stokes_dims(h).np;
+    const int nb = h->nb_partial;
+    double* coarse = nullptr;
+    const std::vector<ZLevel> z = zmg_levels(h, &coarse);
+    const ZLevel& T = z[h->cfg.L - 1];
+    HIPCHK(h, launch_fill<double>(np, 0.0, y, h->st));
+    HIPCHK(h, launch_axpby<double>(np, 1.0, r, 0.0, w.zr, h->st));
+    TRY(zmg_cycle(h, z, coarse, h->cfg.L - 1, w.zr, w.zz));
+    HIPCHK(h, launch_dot2<double>(np, w.zz, w.zr, nullptr, h->partial, nb, h->st));
+    HIPCHK(h, launch_sum_partials(h->partial, nb, w.zred, h->st));
+    HIPCHK(h, launch_axpby<double>(np, 1.0, w.zz, 0.0, w.zp, h->st));
+    int cur = 0;
+    for (int k = 0; k < iters; ++k) {
+        HIPCHK(h, launch_zstencil(0, T.n, T.S, w.zp, nullptr, 0.0, w.zq, h->st));
+        HIPCHK(h, launch_dot2<double>(np, w.zp, w.zq, nullptr, h->partial, nb, h->st));
+        HIPCHK(h, launch_sum_partials(h->partial, nb, w.zred + 2, h->st));
+        HIPCHK(h, launch_cg_update(np, w.zred + cur, w.zred + 2, w.zp, w.zq, y, w.zr, nullptr,
+                                   h->partial, nb, h->st));
+        if (k == iters - 1) break;
+        TRY(zmg_cycle(h, z, coarse, h->cfg.L - 1, w.zr, w.zz));
+        HIPCHK(h, launch_dot2<double>(np, w.zz, w.zr, nullptr, h->partial, nb, h->st));
+        HIPCHK(h, launch_sum_partials(h->partial, nb, w.zred + (1 - cur), h->st));
+        HIPCHK(h, launch_zpbp_dev<double>(np, w.zz, w.zred + (1 - cur), w.zred + cur, 1.0, w.zp, h->st));
+        cur = 1 - cur;
+    }
+    return AGCA_OK;
+}
+
 // y = iters steps of Jacobi-preconditioned CG on Z y = r from y = 0.  The scalars stay
 // on the device: r.z alternates between zred[0] and zred[1], p.q is zred[2]; a step of
 // zero Z-energy (r = 0) has step size zero (the update kernels' guards).
@@ -1666,23 +1870,26 @@ static int32_t z_solve(agca_hier* h, const Bfbt& w, const double* r, double* y, 
     }
     return AGCA_OK;
 }
-// q = S^-1 rp, S the BFBT approximation
-static int32_t bfbt_apply(agca_hier* h, const double* rp, double* q, int iters) {
+// q = S^-1 rp, S the BFBT approximation, Z solves by Jacobi-CG or multigrid-CG
+static int32_t bfbt_apply(agca_hier* h, const double* rp, double* q, int iters, bool mg) {
     const StokesDims d = stokes_dims(h);
     const Bfbt w = bfbt_bufs(h);
-    TRY(z_solve(h, w, rp, w.y1, iters));
+    auto zsolve = [&](const double* r, double* y) {
+        return mg ? z_solve_mg(h, w, r, y, iters) : z_solve(h, w, r, y, iters);
+    };
+    TRY(zsolve(rp, w.y1));
     HIPCHK(h, launch_fill<double>(d.nu, 0.0, w.v2, h->st));
     TRY(stokes_grad_add(h, w.y1, w.v2));
     HIPCHK(h, launch_mul_elementwise(d.nu, w.v2, w.winv, w.v2, h->st));
     TRY(do_cube<double>(h, h->cfg.L, MODE_APPLY, w.v2, nullptr, w.v1, 0.0));
     HIPCHK(h, launch_mul_elementwise(d.nu, w.v1, w.winv, w.v1, h->st));
     TRY(stokes_div(h, w.v1, w.y2));
-    TRY(z_solve(h, w, w.y2, q, iters));
+    TRY(zsolve(w.y2, q));
     return AGCA_OK;
 }
 // q = S^-1 rp: the lumped 1/nu mass, or BFBT during a solve that asked for it
 static int32_t schur_inv(agca_hier* h, const double* rp, double* q) {
-    if (h->st_schur_iters > 0) return bfbt_apply(h, rp, q, h->st_schur_iters);
+    if (h->st_schur_iters > 0) return bfbt_apply(h, rp, q, h->st_schur_iters, h->st_schur_mg);
     HIPCHK(h, launch_div_elementwise(stokes_dims(h).np, rp, h->st_mass, q, h->st));
     return AGCA_OK;
 }
@@ -1970,6 +2177,51 @@ int32_t agca_stokes_mass(agca_hier* h, double* m) {
     return AGCA_OK;
 }
 
+int32_t agca_stokes_schur_apply(agca_hier* h, int32_t schur, int32_t schur_iters, const double* rp,
+                                double* q) {
+    TRY(stokes_ready(h));
+    if (!rp || !q || rp == q) return fail(AGCA_E_INVALID, "null or aliased pointer");
+    const StokesDims d = stokes_dims(h);
+    if (schur == AGCA_SCHUR_MASS) {
+        HIPCHK(h, launch_div_elementwise(d.np, rp, h->st_mass, q, h->st));
+        return AGCA_OK;
+    }
+    if (schur != AGCA_SCHUR_BFBT && schur != AGCA_SCHUR_BFBT_MG)
+        return fail(AGCA_E_INVALID, "unknown Schur approximation");
+    if (schur_iters < 1 || schur_iters > 1000) return fail(AGCA_E_INVALID, "schur_iters must be in [1, 1000]");
+    const bool zmg = schur == AGCA_SCHUR_BFBT_MG;
+    TRY(bfbt_ready(h, !zmg));
+    if (zmg) TRY(zmg_ready(h));
+    return bfbt_apply(h, rp, q, schur_iters, zmg);
+}
+
+int32_t agca_stokes_z_stencil(agca_hier* h, int32_t level, double* out) {
+    TRY(stokes_ready(h));
+    if (!out) return fail(AGCA_E_INVALID, "null pointer");
+    if (level < 0 || level > h->cfg.L - 1) return fail(AGCA_E_INVALID, "level must be in [0, L-1]");
+    TRY(zmg_ready(h));
+    const std::vector<ZLevel> z = zmg_levels(h);
+    HIPCHK(h, hipMemcpyAsync(out, z[level].S, sizeof(double) * kZOffsets * z[level].N,
+                             hipMemcpyDeviceToDevice, h->st));
+    return AGCA_OK;
+}
+
+int32_t agca_stokes_z_vcycle(agca_hier* h, const double* r, double* y) {
+    TRY(stokes_ready(h));
+    if (!r || !y || r == y) return fail(AGCA_E_INVALID, "null or aliased pointer");
+    TRY(zmg_ready(h));
+    double* coarse = nullptr;
+    const std::vector<ZLevel> z = zmg_levels(h, &coarse);
+    const Bfbt w = bfbt_bufs(h);
+    const int64_t np = stokes_dims(h).np;
+    // through the solver's own buffers: the cycle's input and output stay distinct from
+    // the top level's work vectors whatever the caller passes
+    HIPCHK(h, launch_axpby<double>(np, 1.0, r, 0.0, w.zr, h->st));
+    TRY(zmg_cycle(h, z, coarse, h->cfg.L - 1, w.zr, w.zz));
+    HIPCHK(h, hipMemcpyAsync(y, w.zz, sizeof(double) * np, hipMemcpyDeviceToDevice, h->st));
+    return AGCA_OK;
+}
+
 int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double* f, const double* g,
                           double* u, double* p, agca_solve_stats* stats) {
     TRY(stokes_ready(h));
@@ -1983,9 +2235,10 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
         return fail(AGCA_E_INVALID, "unknown Stokes preconditioner");
     if (o->precond == AGCA_STOKES_TRIANGULAR && o->solver != AGCA_STOKES_FGMRES)
         return fail(AGCA_E_INVALID, "the triangular preconditioner is not symmetric: FGMRES only");
-    if (o->schur != AGCA_SCHUR_MASS && o->schur != AGCA_SCHUR_BFBT)
+    if (o->schur != AGCA_SCHUR_MASS && o->schur != AGCA_SCHUR_BFBT && o->schur != AGCA_SCHUR_BFBT_MG)
         return fail(AGCA_E_INVALID, "unknown Schur approximation");
-    const bool bfbt = o->schur == AGCA_SCHUR_BFBT;
+    const bool bfbt = o->schur != AGCA_SCHUR_MASS;
+    const bool zmg = o->schur == AGCA_SCHUR_BFBT_MG;
     if (bfbt && (o->schur_iters < 1 || o->schur_iters > 1000))
         return fail(AGCA_E_INVALID, "schur_iters must be in [1, 1000]");
     if (bfbt && o->solver != AGCA_STOKES_FGMRES)
@@ -2001,8 +2254,10 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     double* xvec = bvec + d.tot;
     h->st_tri = tri ? xvec + d.tot : nullptr;
     h->st_schur_iters = 0;
-    if (bfbt) TRY(bfbt_ready(h));
+    if (bfbt) TRY(bfbt_ready(h, !zmg));
+    if (zmg) TRY(zmg_ready(h));
     h->st_schur_iters = bfbt ? o->schur_iters : 0;
+    h->st_schur_mg = zmg;
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(h, hipMemcpyAsync(bvec, f, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, h->st));
     HIPCHK(h, launch_zero_boundary<double>(3, d.nf, bvec, h->st));

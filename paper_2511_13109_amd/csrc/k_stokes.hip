@@ -161,7 +161,8 @@ k_restrict_all(int nc, const double* __restrict__ qf, double* __restrict__ out) 
     out[p] = qf[X + nf1 * (Y + nf1 * (int64_t)Z)] + 0.5 * half;
 }
 
-// pf = P pc on every node of the fine level (nf cells), boundary included
+// pf = P pc (ADD: pf += P pc) on every node of the fine level (nf cells), boundary included
+template <bool ADD>
 __global__ void __launch_bounds__(NT)
 k_prolong_all(int nf, const double* __restrict__ pc, double* __restrict__ pf) {
     const int nc = nf / 2;
@@ -174,7 +175,8 @@ k_prolong_all(int nf, const double* __restrict__ pc, double* __restrict__ pf) {
     const int dx = x & 1, dy = y & 1, dz = z & 1;
     const int64_t lo = ((x - dx) >> 1) + nc1 * (((y - dy) >> 1) + nc1 * (int64_t)((z - dz) >> 1));
     const int64_t hi = ((x + dx) >> 1) + nc1 * (((y + dy) >> 1) + nc1 * (int64_t)((z + dz) >> 1));
-    pf[p] = (dx | dy | dz) ? 0.5 * (pc[lo] + pc[hi]) : pc[lo];
+    const double v = (dx | dy | dz) ? 0.5 * (pc[lo] + pc[hi]) : pc[lo];
+    pf[p] = ADD ? pf[p] + v : v;
 }
 
 __global__ void __launch_bounds__(NT)
@@ -336,7 +338,13 @@ hipError_t launch_restrict_all(int n_coarse, const double* qf, double* out, hipS
 hipError_t launch_prolong_all(int n_fine, const double* pc, double* pf, hipStream_t st) {
     if (!pc || !pf || n_fine < 2) return hipErrorInvalidValue;
     const int64_t N = (int64_t)(n_fine + 1) * (n_fine + 1) * (n_fine + 1);
-    hipLaunchKernelGGL(k_prolong_all, dim3(grid_for(N)), dim3(NT), 0, st, n_fine, pc, pf);
+    hipLaunchKernelGGL(k_prolong_all<false>, dim3(grid_for(N)), dim3(NT), 0, st, n_fine, pc, pf);
+    return hipGetLastError();
+}
+hipError_t launch_prolong_all_add(int n_fine, const double* pc, double* pf, hipStream_t st) {
+    if (!pc || !pf || n_fine < 2) return hipErrorInvalidValue;
+    const int64_t N = (int64_t)(n_fine + 1) * (n_fine + 1) * (n_fine + 1);
+    hipLaunchKernelGGL(k_prolong_all<true>, dim3(grid_for(N)), dim3(NT), 0, st, n_fine, pc, pf);
     return hipGetLastError();
 }
 hipError_t launch_div_elementwise(int64_t n, const double* num, const double* den, double* out,

@@ -12,12 +12,15 @@
 //   stop tol rho k (r_i e_i)*k   -> after each true residual r_i of a replacement (e_i = 1:
 //                                   the recurrence had reached tol), the decision:
 //                                   0 continue, 1 floor, 2 stalled
+//   zstencil                     -> the pressure stencil's 65 offsets (dx dy dz per line)
+//                                   and the probing colour of every node of a 9^3 lattice
 #include <cstdio>
 #include <cstring>
 #include <vector>
 
 #include "gca_math.h"
 #include "stop_rule.h"
+#include "zstencil.h"
 
 using namespace agca;
 
@@ -117,6 +120,13 @@ static void stop() {
     }
 }
 
+static void zstencil() {
+    for (int i = 0; i < kZOffsets; ++i) std::printf("%d %d %d\n", kZTable.dx[i], kZTable.dy[i], kZTable.dz[i]);
+    for (int z = 0; z < 9; ++z)
+        for (int y = 0; y < 9; ++y)
+            for (int x = 0; x < 9; ++x) std::printf("%d\n", z_colour(x, y, z));
+}
+
 int main() {
     char cmd[16];
     if (std::scanf("%15s", cmd) != 1) return 1;
@@ -128,6 +138,7 @@ int main() {
     else if (!std::strcmp(cmd, "energy")) nc == 1 ? energy<1>() : energy<3>();
     else if (!std::strcmp(cmd, "gca")) gca();
     else if (!std::strcmp(cmd, "stop")) stop();
+    else if (!std::strcmp(cmd, "zstencil")) zstencil();
     else return 1;
     return 0;
 }

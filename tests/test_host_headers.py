@@ -110,3 +110,20 @@ def test_stop_rule(exe):
     assert out[:7] == [CONT] * 7 and out[7] == STALL
     out = _stop(exe, 1e-12, 8e-9, seq)
     assert out[7] == FLOOR      # 7.8e-9 <= 8e-9
+
+
+def test_pressure_stencil_offsets_and_probing_colours(exe):
+    # csrc/zstencil.h: the 65 offsets in the oracle's order, and a probing colouring under
+    # which the 65 neighbours k + o of every node k have 65 distinct colours (checked here
+    # by brute force over a 9^3 lattice, every node whose whole stencil is inside)
+    from oracle import stokes
+    v = _run(exe, "zstencil\n").astype(int)
+    offs = [tuple(t) for t in v[:65 * 3].reshape(65, 3)]
+    assert offs == stokes.Z_OFFSETS
+    col = v[65 * 3:].reshape(9, 9, 9)                     # [z, y, x]
+    assert col.min() >= 0 and col.max() <= 64
+    for z in range(2, 7):
+        for y in range(2, 7):
+            for x in range(2, 7):
+                cs = {col[z + dz, y + dy, x + dx] for (dx, dy, dz) in offs}
+                assert len(cs) == 65, (x, y, z)

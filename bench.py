@@ -351,6 +351,77 @@ def profile_apply(name: str, dev) -> None:
     print("profile-apply done", flush=True)
 
 
+def profile_vcycle(name: str, smoother: str, dev) -> None:
+    """Driver for instruction-counter passes over the V-cycle kernels: 3 FP32/BF16 and 3
+    FP64 V-cycles of the benchmark's hierarchies on a random right-hand side."""
+    import torch
+    from paper_2511_13109_amd import Hierarchy
+    from workloads import workload
+    from workloads.device import device_inputs
+    w = workload(name)
+    nus, f = device_inputs(w, dev)
+    del f
+    for dt, nud in (("f32", "bf16"), ("f64", "f64")):
+        H = Hierarchy(w.L, w.ncomp, nus[w.L], nus[:w.L], mg_dtype=dt, mg_nu_dtype=nud, smoother=smoother)
+        n = 2 ** (w.L + 1)
+        b = torch.randn(w.ncomp * (n + 1) ** 3, dtype=torch.float64, device=dev)
+        if dt == "f32":
+            b = b.float()
+        z = torch.empty_like(b)
+        for _ in range(3):
+            H.vcycle(b, z)
+        torch.cuda.synchronize()
+        H.close()
+        del b, z
+    print("profile-vcycle done", flush=True)
+
+
+# counters of the instruction passes over the V-cycle kernels (two runs of at most 8 SQ
+# counters each) and the quantities the summary derives from them
+VCYCLE_COUNTERS = [
+    ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+     "SQ_INSTS_VMEM_WR", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"],
+    ["VALUBusy", "SQ_ACTIVE_INST_ANY", "SQ_BUSY_CYCLES", "SQ_INSTS_VALU_FMA_F32",
+     "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_ADD_F64"],
+]
+
+
+def summarize_counters(d: str, L: int) -> str:
+    """Markdown table of the instruction counters of the finest-level element-loop passes
+    in the counter runs under <d> (one sub-directory per run, rocprofv3 csv output)."""
+    import csv
+    import collections
+    import glob
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    grids = collections.defaultdict(int)
+    for path in glob.glob(os.path.join(d, "*", "*counter_collection.csv")):
+        rows = list(csv.DictReader(open(path)))
+        for r in rows:
+            k = _short(r["Kernel_Name"])
+            if not k.startswith("k_cube<3"):
+                continue
+            grids[k] = max(grids[k], int(r["Grid_Size"]))
+        for r in rows:
+            k = _short(r["Kernel_Name"])
+            if k.startswith("k_cube<3") and int(r["Grid_Size"]) == grids[k]:
+                vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["| kernel | waves | VALU / wave | FP FMA+ADD / wave | SALU / wave | VMEM / wave | "
+             "LDS / wave | wait / wave cycles | VALUBusy % |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    med = lambda v: float(np.median(v)) if v else float("nan")
+    for k in sorted(vals):
+        c = {name: med(v) for name, v in vals[k].items()}
+        wv = c.get("SQ_WAVES", float("nan"))
+        fp = sum(c.get(f"SQ_INSTS_VALU_{op}_{t}", 0.0) for op in ("FMA", "ADD") for t in ("F32", "F64"))
+        vmem = c.get("SQ_INSTS_VMEM_RD", 0.0) + c.get("SQ_INSTS_VMEM_WR", 0.0)
+        lines.append(f"| `{k}` | {wv:.0f} | {c.get('SQ_INSTS_VALU', 0) / wv:.0f} | {fp / wv:.0f} | "
+                     f"{c.get('SQ_INSTS_SALU', 0) / wv:.0f} | {vmem / wv:.0f} | "
+                     f"{c.get('SQ_INSTS_LDS', 0) / wv:.0f} | "
+                     f"{c.get('SQ_WAIT_INST_ANY', 0) / max(c.get('SQ_WAVE_CYCLES', 1), 1):.2f} | "
+                     f"{c.get('VALUBusy', float('nan')):.1f} |")
+    return "\n".join(lines)
+
+
 def progress(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
@@ -826,6 +897,10 @@ def main():
                          "of the coefficient (the same operator for P1)")
     ap.add_argument("--profile-apply", action="store_true",
                     help="only run 5 FP64 fine applies and a 256 MiB copy (counter passes)")
+    ap.add_argument("--profile-vcycle", action="store_true",
+                    help="only run 3 FP32/BF16 and 3 FP64 V-cycles of the 513^3 hierarchies (counter passes)")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="print the instruction-counter table of the V-cycle counter runs under DIR")
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print the finest-level solver-kernel table of a rocprofv3 kernel trace")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -852,6 +927,9 @@ def main():
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.level or 6))
         return
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.level or 8))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the AGCA path here is built and timed on a single "
@@ -865,6 +943,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.profile_apply:
         profile_apply(args.workload, dev)
+        return
+    if args.profile_vcycle:
+        profile_vcycle("sinker513", args.smoother, dev)
         return
     # the benchmark line: 513^3 (default) or the earlier 129^3 line; the other workloads
     # print a report line of their own

@@ -248,9 +248,9 @@ typedef struct {
  * Stopping (eq. (4.3)): PCG and FCG replace their recurrence's residual by the true
  * residual b - A x whenever the recurrence has halved since the last replacement, and
  * when it reaches tol (the search direction is kept).  They stop when the true residual
- * is <= tol (converged), or when it has stopped improving (two replacements in a row
- * without a 10 % gain over the best earlier one, or 8 replacements with the recurrence
- * at tol): then floor_limited if it is at most max(tol, rho), rho the rounding floor of
+ * is <= tol (converged), or when it has stopped improving (two windows in a row
+ * without a 10 % gain over its best, a window being the iterations the recurrence last
+ * took to halve): then floor_limited if it is at most max(tol, rho), rho the rounding floor of
  * x (agca_residual_floor), else a stall.  Returns AGCA_OK when converged or
  * floor_limited; AGCA_E_NOCONV (x and stats filled) when max_iter is reached first or
  * the true residual stalls above max(tol, rho). */

@@ -1313,7 +1313,6 @@ static int32_t precondition(agca_hier* h, const double* r, double* z) {
 // floor of the iterate, residual_floor).  A stall above that is AGCA_E_NOCONV.  A
 // replacement costs one residual pass and one dot product, against an apply, a
 // V-cycle and three vector passes per iteration.
-constexpr double kReplaceEvery = 0.5;
 
 int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, double* x,
                    agca_solve_stats* stats) {
@@ -1439,7 +1438,8 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                     status = fail(AGCA_E_NUMERIC, "residual diverged");
                     break;
                 }
-                if (rel <= o->tol || rel <= kReplaceEvery * anchor || milestone_due(rel)) {
+                const bool full = rel <= kReplaceEvery * anchor;
+                if (rel <= o->tol || full || milestone_due(rel)) {
                     // residual replacement: r = b - A x (and its FP32 copy); r . r goes to a
                     // slot of its own (FCG's next beta still reads p . q from slot PQ)
                     TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
@@ -1453,7 +1453,7 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                         rel = rel_true;
                         break;
                     }
-                    if (ends.stagnated(rel_true, rel <= o->tol)) {
+                    if (ends.stagnated(rel_true, it, full)) {
                         TRY(residual_floor(h, b, x, &rho));
                         rel = rel_true;
                         floor_limited = at_floor(rel_true, o->tol, rho);

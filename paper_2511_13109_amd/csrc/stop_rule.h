@@ -3,11 +3,14 @@
 // the library and a host-compiled test.
 //
 // The solver replaces its recurrence's residual by the true residual at regular steps
-// (each time the recurrence has halved since the last replacement) and when the
-// recurrence reaches tol.  Far above the floor the true residual follows the recurrence
-// and halves between replacements; once it stops improving (no 10 % gain over the best
-// earlier replacement, twice in a row) the solver stops, and so it does after
-// kMaxEndChecks replacements made with the recurrence at tol.  The stop counts as the
+// (each time the recurrence has halved since the last replacement: a full period) and
+// whenever the recurrence reaches tol.  Far above the floor the true residual follows
+// the recurrence; the iterations a full period takes measure how fast it converges.  The
+// solver stops when the true residual has gone that many iterations without a 10 % gain
+// over its best, twice in a row: progress is judged over the iterations in which a
+// converging solve would have halved its residual, not from one check to the next (near
+// tol the checks come every few iterations, and a solve still converging there shows
+// small gains between them).  The stop counts as the
 // rounding floor only when the true residual is at most kFloorFactor max(tol, rho),
 // rho the floor of the iterate: u || |b| + sum_e |A_e| |x_e| || / ||b||, a bound on how
 // far one more FP64 rounding of x can move the residual (measured stagnation levels of
@@ -19,26 +22,37 @@
 
 namespace agca {
 
+constexpr double kReplaceEvery = 0.5;  // a full period: the recurrence halved since the last replacement
 constexpr double kFloorFactor = 1.0;   // a floor stop needs rel_true <= max(tol, rho)
-constexpr double kEndGain = 0.9;       // a replacement improves when it is 10 % below the best
-constexpr int kEndStalls = 2;          // replacements in a row without improvement that stop
-constexpr int kMaxEndChecks = 8;       // replacements at tol after which the solver stops anyway
+constexpr double kEndGain = 0.9;       // progress: 10 % below the best true residual so far
+constexpr int kEndStalls = 2;          // windows in a row without progress that stop
 
 struct EndChecks {
     double best = HUGE_VAL;
-    int end_checks = 0;
+    int best_it = 0;    // iteration of the best true residual
+    int mark = 0;       // iteration of the best, or of the last window without progress
     int stalls = 0;
-    // record the true residual of a replacement (at_end: the recurrence had reached tol)
-    // that is still above tol; true when the iteration should stop
-    bool stagnated(double rel_true, bool at_end) {
-        if (at_end) ++end_checks;
+    int last_full = 0;  // iteration of the last replacement after a full period
+    int period = -1;    // iterations between the last two of them (-1: none measured yet)
+    // record the true residual of a replacement at iteration it that is still above tol
+    // (full: the recurrence had halved since the last replacement); true when the
+    // iteration should stop.  Before any full period the window is the iteration count
+    // at which the best was reached.
+    bool stagnated(double rel_true, int it, bool full) {
+        if (full) {
+            period = it - last_full;
+            last_full = it;
+        }
+        const int window = period > 0 ? period : (best_it > 1 ? best_it : 1);
         if (rel_true < kEndGain * best) {
             best = rel_true;
+            best_it = mark = it;
             stalls = 0;
-        } else {
+        } else if (it - mark >= window) {
             ++stalls;
+            mark = it;
         }
-        return stalls >= kEndStalls || end_checks >= kMaxEndChecks;
+        return stalls >= kEndStalls;
     }
 };
 

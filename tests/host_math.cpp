@@ -9,8 +9,9 @@
 //   gca ncomp l L nid ids[nid] nu[6 n_L^3]
 //                                -> Galerkin blocks of level-l elements by the element-wise
 //                                   recursion (fine_block + add_ptkp over child_id), FP64
-//   stop tol rho k (r_i e_i)*k   -> after each true residual r_i of a replacement (e_i = 1:
-//                                   the recurrence had reached tol), the decision:
+//   stop tol rho k (r_i it_i f_i)*k -> after each true residual r_i of a replacement at
+//                                   iteration it_i (f_i = 1: the recurrence had halved
+//                                   since the last one), the decision:
 //                                   0 continue, 1 floor, 2 stalled
 //   zstencil                     -> the pressure stencil's 65 offsets (dx dy dz per line)
 //                                   and the probing colour of every node of a 9^3 lattice
@@ -111,10 +112,10 @@ static void stop() {
     EndChecks ends;
     for (int i = 0; i < k; ++i) {
         double r;
-        int at_end;
-        if (std::scanf("%lf %d", &r, &at_end) != 2) return;
+        int it, full;
+        if (std::scanf("%lf %d %d", &r, &it, &full) != 3) return;
         int verdict = 0;
-        if (ends.stagnated(r, at_end != 0)) verdict = at_floor(r, tol, rho) ? 1 : 2;
+        if (ends.stagnated(r, it, full != 0)) verdict = at_floor(r, tol, rho) ? 1 : 2;
         std::printf("%d\n", verdict);
         if (verdict) break;
     }

@@ -81,35 +81,42 @@ def test_galerkin_blocks(exe, ncomp, l):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-def _stop(exe, tol, rho, seq, at_end=None):
-    ends = at_end if at_end is not None else [1] * len(seq)
-    txt = f"stop {tol:.17g} {rho:.17g} {len(seq)} " + " ".join(f"{v:.17g} {e}" for v, e in zip(seq, ends))
+def _stop(exe, tol, rho, checks):
+    """checks: (true residual, iteration, full period) of each replacement above tol."""
+    txt = f"stop {tol:.17g} {rho:.17g} {len(checks)} " + " ".join(
+        f"{r:.17g} {it} {int(f)}" for r, it, f in checks)
     return [int(v) for v in _run(exe, txt)]
 
 
 def test_stop_rule(exe):
     CONT, FLOOR, STALL = 0, 1, 2
-    # stagnation below the floor rho (rho above tol): a floor stop
-    assert _stop(exe, 1e-8, 4e-8, [3.5e-8, 3.4e-8, 3.45e-8]) == [CONT, CONT, FLOOR]
-    # the same stagnation above a floor of 2e-8: not success
-    assert _stop(exe, 1e-8, 2e-8, [3.5e-8, 3.4e-8, 3.45e-8]) == [CONT, CONT, STALL]
+    # a healthy phase halving every 10 iterations (full periods, to 6.25e-8 at it 50), then
+    # stagnation at 3.4e-8 from it 52 with checks every 2 iterations: two windows of 10
+    # iterations without a 10 % gain (its 62 and 72) stop it, a floor stop when rho is
+    # above the level
+    healthy = [(1e-6 * 0.5 ** k, 10 * (k + 1), True) for k in range(5)]
+    flat = [(3.4e-8 * (1 + 0.01 * (k % 3)), 50 + 2 * (k + 1), False) for k in range(15)]
+    out = _stop(exe, 1e-8, 4e-8, healthy + flat)
+    assert out[:15] == [CONT] * 15
+    assert out[-1] == FLOOR and len(out) == 16        # the check at it 72
+    assert _stop(exe, 1e-8, 2e-8, healthy + flat)[-1] == STALL   # the same level above rho
     # a stop 75x above tol with a floor far below it is not success
-    assert _stop(exe, 1e-8, 1e-9, [7.5e-7, 7.4e-7, 7.6e-7]) == [CONT, CONT, STALL]
-    # the same residuals with a floor estimate of 1.6e-7: still above it
-    assert _stop(exe, 1e-8, 1.6e-7, [7.5e-7, 7.4e-7, 7.6e-7]) == [CONT, CONT, STALL]
+    stuck = [(7.5e-7, 10, True), (7.4e-7, 20, True), (7.6e-7, 30, True), (7.5e-7, 40, True)]
+    assert _stop(exe, 1e-8, 1e-9, stuck) == [CONT, CONT, STALL]    # windows at its 20 and 30
+    assert _stop(exe, 1e-8, 1.6e-7, stuck)[-1] == STALL
     # a tolerance below the floor: stagnation at 1.5 x tol with rho of 2 x tol is a floor stop
-    assert _stop(exe, 1e-8, 2e-8, [1.6e-8, 1.5e-8, 1.55e-8]) == [CONT, CONT, FLOOR]
-    # replacements that halve the true residual never stop, however many (recurrence
-    # above tol); the floor then shows as two replacements without a 10 % gain
-    seq = [0.5 ** k for k in range(30)] + [0.5 ** 29 * 0.95, 0.5 ** 29 * 0.97]
-    out = _stop(exe, 1e-12, 2e-9, seq, at_end=[0] * len(seq))
-    assert out[:31] == [CONT] * 31 and out[31] == FLOOR
-    # steady improvement with the recurrence at tol continues until 8 such checks
-    seq = [1e-6 * 0.5 ** k for k in range(8)]
-    out = _stop(exe, 1e-12, 1e-9, seq)
-    assert out[:7] == [CONT] * 7 and out[7] == STALL
-    out = _stop(exe, 1e-12, 8e-9, seq)
-    assert out[7] == FLOOR      # 7.8e-9 <= 8e-9
+    low = [(1.6e-8, 10, True), (1.5e-8, 20, True), (1.55e-8, 30, True), (1.52e-8, 40, True)]
+    assert _stop(exe, 1e-8, 2e-8, low)[-1] == FLOOR
+    # replacements that halve the true residual never stop, however many
+    seq = [(0.5 ** k, 10 * (k + 1), True) for k in range(30)]
+    assert _stop(exe, 1e-12, 2e-9, seq) == [CONT] * 30
+    # a solve creeping to tol (checks every iteration, 1 % gain each, after a healthy phase
+    # of 20 iterations per halving) keeps going: 10 % comes within its window
+    creep = [(1e-5, 20, True), (2e-6, 40, True)] + [(1.05e-6 * 0.99 ** k, 41 + k, False) for k in range(40)]
+    assert _stop(exe, 1e-6, 1e-9, creep) == [CONT] * len(creep)
+    # with checks from the start (no full period yet) the window is the iteration count
+    assert _stop(exe, 1e-8, 1e-9, [(5e-7, 3, False), (4.9e-7, 4, False), (4.9e-7, 6, False),
+                                   (4.9e-7, 12, False)]) == [CONT, CONT, CONT, STALL]
 
 
 def test_pressure_stencil_offsets_and_probing_colours(exe):

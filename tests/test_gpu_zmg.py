@@ -3,9 +3,10 @@ Z = B W^-1 B^T) through the C ABI, against the oracle's ZHierarchy: the 65-offse
 stencils of every level assembled by probing (1e-12 of the level's largest entry),
 one V-cycle (1e-10), the Schur approximations S^-1 r of all three kinds, and
 triangular FGMRES with BFBT_MG (residual-history prefix, iteration counts).  At
-129^3 pressure nodes (the 257^3 Stokes workload) the stencil is checked by properties
-that hold at any size: symmetry, zero row sums, and its product against the matrix-free
-Z = B W^-1 B^T on a random vector.
+129^3 pressure nodes (the 257^3 Stokes workload) the stencil and the cycle are checked
+by properties that hold at any size: symmetry, zero row sums, the stencil's product
+against the matrix-free Z = B W^-1 B^T on a random vector, and the V-cycle's symmetry
+and energy-norm contraction.
 """
 
 import numpy as np
@@ -132,6 +133,32 @@ def test_bad_arguments(zcase):
         GS.solve(_dev(fu), solver="minres", tol=1e-8, schur="bfbt_mg")
 
 
+def test_stencils_follow_a_coefficient_rebuild():
+    # the multigrid is assembled for the coefficient in place at its first use and again
+    # after every rebuild: stencils and S^-1 against the oracle for the second field
+    from paper_2511_13109_amd import Hierarchy, Stokes
+    L = 3
+    levels = mesh.hierarchy(L)
+    fields = [Sinkers(3, 5, radius=0.2, width=2.0 / 2 ** (L + 1), contrast=1e4),
+              Sinkers(2, 9, radius=0.25, width=2.0 / 2 ** (L + 1), contrast=1e3)]
+    nus = [[f.nu(mesh.centroids_canonical(lv)) for lv in levels] for f in fields]
+    G = Hierarchy(L, 3, _dev(nus[0][L]), [_dev(v) for v in nus[0][:L]])
+    try:
+        GS = Stokes(G)
+        first = GS.z_stencil(L - 1).cpu().numpy()
+        G.set_nu(_dev(nus[1][L]), [_dev(v) for v in nus[1][:L]])
+        S = stokes.StokesSystem(mg.build(L, nus[1], 3, levels=levels))
+        ZH = stokes.ZHierarchy(S)
+        for l in range(L):
+            assert _rel(GS.z_stencil(l).cpu().numpy(), ZH.stencil(l)) <= 1e-12, l
+        assert _rel(GS.z_stencil(L - 1).cpu().numpy(), first) > 1e-3
+        r = np.random.default_rng(8).standard_normal(S.np_)
+        q = GS.schur_apply(_dev(r), "bfbt_mg", 2).cpu().numpy()
+        assert _rel(q, S.bfbt(2, z_solve=ZH.z_solve(2))(r)) <= 1e-8
+    finally:
+        G.close()
+
+
 def _stencil_apply_host(st, n, x):
     return stokes.stencil_apply(st, n, x)
 
@@ -169,6 +196,22 @@ def test_stokes257_stencil_properties():
             assert np.abs(a - b).max() <= 1e-13 * scale, (dx, dy, dz)
             assert np.all(st[i, ks[~inside]] == 0.0)
         assert np.abs(st.sum(axis=0)).max() <= 1e-12 * scale
+        # the V-cycle at this size: symmetric (u . V v = v . V u, to rounding) and an
+        # energy-norm contraction on zero-sum vectors (checked through Z's stencil form)
+        uu = rng.standard_normal(n1 ** 3)
+        vv = rng.standard_normal(n1 ** 3)
+        uu -= uu.mean()
+        vv -= vv.mean()
+        Vu = GS.z_vcycle(_dev(uu)).cpu().numpy()
+        Vv = GS.z_vcycle(_dev(vv)).cpu().numpy()
+        assert abs(uu @ Vv - vv @ Vu) <= 1e-10 * abs(uu @ Vv)
+        e = uu
+        Ze = _stencil_apply_host(st, n, e)
+        e1 = e - GS.z_vcycle(_dev(Ze)).cpu().numpy()
+        e1 -= e1.mean()
+        ratio = np.sqrt((e1 @ _stencil_apply_host(st, n, e1)) / (e @ Ze))
+        print(f"[stokes257] pressure V-cycle energy contraction on a random error {ratio:.3f}", flush=True)
+        assert ratio < 0.9
         x = rng.standard_normal(n1 ** 3)
         diag = np.asarray(G.diagonal(L), dtype=np.float64)
         winv = np.where(diag != 0, 1.0 / np.where(diag != 0, diag, 1.0), 0.0)

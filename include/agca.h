@@ -319,8 +319,9 @@ typedef enum { AGCA_STOKES_DIAGONAL = 0, AGCA_STOKES_TRIANGULAR = 1 } agca_stoke
  *        at the first use after every coefficient rebuild, by probing: Z (then
  *        P^T Z_{l+1} P) applied to the indicators of 65 node colours
  *        (x + 34 y + 44 z) mod 65, a colouring that separates the 65 offsets.
- *        Device memory: 69 doubles per pressure node of every level (about
- *        69 * 8/7 (n_{L-1}+1)^3 doubles), kept until destroy.  FGMRES only. */
+ *        Z is symmetric: each level stores the centre and 32 of the offsets per node
+ *        over a lattice padded by 2 nodes, 33 (n_l+5)^3 + 4 (n_l+1)^3 doubles per level
+ *        (about 37 * 8/7 (n_{L-1}+1)^3 doubles in all), kept until destroy.  FGMRES only. */
 typedef enum { AGCA_SCHUR_MASS = 0, AGCA_SCHUR_BFBT = 1, AGCA_SCHUR_BFBT_MG = 2 } agca_stokes_schur;
 typedef struct {
     int32_t solver;          /* agca_stokes_solver                                          */

@@ -1651,8 +1651,8 @@ static int32_t bfbt_ready(agca_hier* h, bool diag) {
 // Geometric multigrid for Z on the pressure lattice (the paper solves with Z by an
 // algebraic multigrid cycle inside CG): levels L-1 (the pressure space) down to 0 with
 // the linear interpolation P over all nodes, Galerkin operators Z_l = P^T Z_{l+1} P
-// (the constant pressure stays in every kernel), stored as 65-offset stencils
-// (zstencil.h) assembled by probing with 65 colours; damped Jacobi V(2,2) cycles,
+// (the constant pressure stays in every kernel), stored as symmetric 65-offset stencils
+// (the centre and 32 offsets per node, zstencil.h) assembled by probing with 65 colours; damped Jacobi V(2,2) cycles,
 // omega = 2/3, zero initial guesses, and on level 0 (27 nodes) the minimal-norm
 // solution from the bordered system [[Z_0, 1], [1^T, 0]].
 // ---------------------------------------------------------------------------
@@ -1664,8 +1664,8 @@ struct ZLevel {
     int64_t N = 0;
     double *S = nullptr, *r = nullptr, *y = nullptr, *a = nullptr, *t = nullptr;
 };
-// levels 0..L-1 carved from st_zmg: per level the stencil (65 N) and four vectors, then
-// the 27 x 27 coarse inverse
+// levels 0..L-1 carved from st_zmg: per level the stored half of the stencil (33 padded
+// arrays, zstencil.h) and four vectors, then the 27 x 27 coarse inverse
 static std::vector<ZLevel> zmg_levels(const agca_hier* h, double** coarse = nullptr) {
     std::vector<ZLevel> z(h->cfg.L);
     double* p = h->st_zmg;
@@ -1673,7 +1673,7 @@ static std::vector<ZLevel> zmg_levels(const agca_hier* h, double** coarse = null
         z[l].n = h->lv[l].n;
         z[l].N = nodes_of(z[l].n);
         z[l].S = p;
-        p += (int64_t)kZOffsets * z[l].N;
+        p += (int64_t)kZStored * z_padded_nodes(z[l].n);
         for (double** v : {&z[l].r, &z[l].y, &z[l].a, &z[l].t}) {
             *v = p;
             p += z[l].N;
@@ -1684,7 +1684,7 @@ static std::vector<ZLevel> zmg_levels(const agca_hier* h, double** coarse = null
 }
 static int64_t zmg_doubles(const agca_hier* h) {
     int64_t c = 27 * 27;
-    for (int l = 0; l < h->cfg.L; ++l) c += (kZOffsets + 4) * nodes_of(h->lv[l].n);
+    for (int l = 0; l < h->cfg.L; ++l) c += kZStored * z_padded_nodes(h->lv[l].n) + 4 * nodes_of(h->lv[l].n);
     return c;
 }
 
@@ -1743,6 +1743,9 @@ static int32_t zmg_ready(agca_hier* h) {
     const std::vector<ZLevel> z = zmg_levels(h, &coarse);
     const int top = h->cfg.L - 1;
     const Bfbt w = bfbt_bufs(h);
+    // padding and the entries of neighbours outside the lattice stay 0
+    for (int l = 0; l <= top; ++l)
+        HIPCHK(h, launch_fill<double>(kZStored * z_padded_nodes(z[l].n), 0.0, z[l].S, h->st));
     for (int c = 0; c < kZColours; ++c) {
         HIPCHK(h, launch_zprobe(z[top].n, c, w.ztmp, h->st));
         TRY(z_apply(h, w, w.ztmp, w.zq));
@@ -1758,15 +1761,21 @@ static int32_t zmg_ready(agca_hier* h) {
             HIPCHK(h, launch_zextract(zc.n, c, zc.y, zc.S, h->st));
         }
     }
-    std::vector<double> S0((size_t)kZOffsets * 27), Z0(27 * 27, 0.0), M;
+    // level 0 (n = 2) as a dense symmetric 27 x 27 matrix from its stored entries
+    const int64_t NP0 = z_padded_nodes(2);
+    const int P0 = 2 + 1 + 2 * kZPad;
+    std::vector<double> S0((size_t)(kZStored * NP0)), Z0(27 * 27, 0.0), M;
     HIPCHK(h, hipMemcpyAsync(S0.data(), z[0].S, sizeof(double) * S0.size(), hipMemcpyDeviceToHost, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     for (int k = 0; k < 27; ++k) {
         const int x = k % 3, y = (k / 3) % 3, zz = k / 9;
-        for (int i = 0; i < kZOffsets; ++i) {
+        const int64_t kp = (x + kZPad) + P0 * ((y + kZPad) + (int64_t)P0 * (zz + kZPad));
+        for (int j = 0; j < kZStored; ++j) {
+            const int i = kZCentre + j;
             const int X = x + kZTable.dx[i], Y = y + kZTable.dy[i], Zc = zz + kZTable.dz[i];
             if (X < 0 || Y < 0 || Zc < 0 || X > 2 || Y > 2 || Zc > 2) continue;
-            Z0[k * 27 + X + 3 * (Y + 3 * Zc)] = S0[(size_t)i * 27 + k];
+            const int m = X + 3 * (Y + 3 * Zc);
+            Z0[k * 27 + m] = Z0[m * 27 + k] = S0[(size_t)j * NP0 + kp];
         }
     }
     for (double v : Z0)
@@ -2201,8 +2210,7 @@ int32_t agca_stokes_z_stencil(agca_hier* h, int32_t level, double* out) {
     if (level < 0 || level > h->cfg.L - 1) return fail(AGCA_E_INVALID, "level must be in [0, L-1]");
     TRY(zmg_ready(h));
     const std::vector<ZLevel> z = zmg_levels(h);
-    HIPCHK(h, hipMemcpyAsync(out, z[level].S, sizeof(double) * kZOffsets * z[level].N,
-                             hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, launch_zexpand(z[level].n, z[level].S, out, h->st));
     return AGCA_OK;
 }
 

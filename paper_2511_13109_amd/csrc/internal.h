@@ -190,7 +190,8 @@ hipError_t launch_restrict_all(int n_coarse, const double* qf, double* out, hipS
 hipError_t launch_prolong_all(int n_fine, const double* pc, double* pf, hipStream_t st);
 hipError_t launch_prolong_all_add(int n_fine, const double* pc, double* pf, hipStream_t st);
 // BFBT pressure multigrid (k_zmg.hip): mode 0 out = S x, 1 out = r - S x, 2 out = x + omega
-// (r - S x) / S_c with S a 65-offset stencil (zstencil.h); x and out distinct
+// (r - S x) / S_c with S the stored half of a symmetric 65-offset stencil (zstencil.h); x
+// and out distinct
 hipError_t launch_zstencil(int mode, int n, const double* S, const double* x, const double* r,
                            double omega, double* out, hipStream_t st);
 hipError_t launch_zjacobi0(int n, const double* S, const double* r, double omega, double* out,
@@ -198,6 +199,7 @@ hipError_t launch_zjacobi0(int n, const double* S, const double* r, double omega
 hipError_t launch_zprobe(int n, int colour, double* out, hipStream_t st);
 hipError_t launch_zextract(int n, int colour, const double* y, double* S, hipStream_t st);
 hipError_t launch_zcoarse(const double* M, const double* r, double* y, hipStream_t st);
+hipError_t launch_zexpand(int n, const double* S, double* out, hipStream_t st);
 hipError_t launch_mul_elementwise(int64_t n, const double* a, const double* b, double* out,
                                   hipStream_t st);
 // 27-colouring of a level's nodes by (x mod 3, y mod 3, z mod 3): mode 0 writes the

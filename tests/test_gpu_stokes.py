@@ -163,13 +163,12 @@ def test_bfbt_schur_approximation(case, mg_dtype):
         G.solve(_dev(fu), solver="fgmres", tol=tol, schur="bfbt", schur_iters=0)
 
 
+@pytest.mark.parametrize("case", [3], indirect=True, ids=["L3"])
 def test_fgmres_below_the_rounding_floor_stays_finite(case):
     # asking for 1e-14 drives the Arnoldi process into near-dependent vectors (the
     # classical Gram-Schmidt second pass runs there); the solve must stay finite and
-    # keep its residual at the rounding level
+    # keep its residual at the rounding level (one size is enough)
     L, levels, H, S, fu, GS, _ = case
-    if L != 3:
-        pytest.skip("one size is enough")
     b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
     u, p, st = GS.solve(_dev(fu), solver="fgmres", restart=30, tol=1e-14, max_iter=700,
                         precond="triangular", raise_on_noconv=False)
@@ -178,14 +177,13 @@ def test_fgmres_below_the_rounding_floor_stays_finite(case):
     assert np.linalg.norm(b - S.K @ xg) <= 1e-10 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("case", [3], indirect=True, ids=["L3"])
 def test_fgmres_stops_at_the_rounding_floor(case):
     # The true residual of an FP64 iterate cannot go below a floor set by rounding.
     # Measure that floor with an unreachable tolerance, then ask for a third of it: the
     # solve must stop by itself (floor_limited, AGCA_OK) long before max_iter, with a
     # residual within 10x of the tolerance and at most the velocity block's rounding floor.
     L, levels, H, S, fu, GS, _ = case
-    if L != 3:
-        pytest.skip("one size is enough")
     b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
     _, _, s0 = GS.solve(_dev(fu), solver="fgmres", restart=30, tol=1e-17, max_iter=1500,
                         precond="triangular", raise_on_noconv=False)

@@ -1688,16 +1688,20 @@ static int64_t zmg_doubles(const agca_hier* h) {
     return c;
 }
 
-// inverse of the bordered 28 x 28 matrix [[Z0, 1], [1^T, 0]] by Gauss-Jordan elimination
-// with partial pivoting; its leading 27 x 27 block maps a zero-sum r to the zero-sum
-// solution of Z0 y = r (Z0's kernel is the constants)
+// inverse of the bordered 28 x 28 matrix [[Z0, s 1], [s 1^T, 0]] by Gauss-Jordan
+// elimination with partial pivoting; its leading 27 x 27 block maps a zero-sum r to the
+// zero-sum solution of Z0 y = r (Z0's kernel is the constants), whatever s > 0: s is
+// taken as the largest entry of Z0, so that the border does not dwarf the operator
 static bool bordered_inverse(const std::vector<double>& Z0, std::vector<double>& M) {
     constexpr int n = 28;
+    double zmax = 0.0;
+    for (double v : Z0) zmax = std::max(zmax, std::fabs(v));
+    if (!(zmax > 0.0)) return false;
     std::vector<double> A(n * n, 0.0), I(n * n, 0.0);
     for (int i = 0; i < 27; ++i) {
         for (int j = 0; j < 27; ++j) A[i * n + j] = Z0[i * 27 + j];
-        A[i * n + 27] = 1.0;
-        A[27 * n + i] = 1.0;
+        A[i * n + 27] = zmax;
+        A[27 * n + i] = zmax;
     }
     for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
     double scale = 0.0;

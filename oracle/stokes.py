@@ -97,6 +97,18 @@ class StokesSystem:
     def split(self, x):
         return x[:self.nu_], x[self.nu_:]
 
+    def velocity_cycles(self, k: int) -> Callable:
+        """A~^-1 as k V-cycles of a stationary iteration from zero: x = V r, then
+        x += V (r - A x) (k = 1: the single V-cycle of Section 4)."""
+        H = self.H
+
+        def a_inv(ru):
+            x = mg.vcycle(H, ru)
+            for _ in range(k - 1):
+                x = x + mg.vcycle(H, ru - self.A @ x)
+            return x
+        return a_inv
+
     def precond(self, kind: str = "diagonal", a_inv: Callable = None,
                 s_inv: Callable = None) -> Callable:
         """diag(V-cycle, lumped 1/nu mass inverse), or the upper block-triangular
@@ -181,14 +193,15 @@ class StokesSystem:
 
     def solve(self, b: np.ndarray, solver: str, tol: float, restart: int = 30,
               maxit: int = 500, precond: str = "diagonal", schur: str = "mass",
-              schur_iters: int = 20) -> mg.SolveResult:
+              schur_iters: int = 20, velocity_cycles: int = 1) -> mg.SolveResult:
+        a_inv = self.velocity_cycles(velocity_cycles) if velocity_cycles > 1 else None
         if schur == "mass":
-            M = self.precond(precond)
+            M = self.precond(precond, a_inv=a_inv)
         elif schur in ("bfbt", "bfbt_mg"):
             if solver != "fgmres":
                 raise ValueError("the BFBT approximation is not a fixed linear map: FGMRES only")
             zs = self.z_hierarchy().z_solve(schur_iters) if schur == "bfbt_mg" else None
-            M = self.precond(precond, s_inv=self.bfbt(schur_iters, z_solve=zs))
+            M = self.precond(precond, a_inv=a_inv, s_inv=self.bfbt(schur_iters, z_solve=zs))
         else:
             raise ValueError(schur)
         if solver == "fgmres":

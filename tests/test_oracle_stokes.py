@@ -203,3 +203,25 @@ def test_bfbt_beats_the_lumped_mass_at_high_contrast():
         its[schur] = res.iterations
     print(its)
     assert its["bfbt"] < 0.5 * its["mass"], its
+
+
+def test_velocity_cycles_stationary_iteration():
+    # k V-cycles from zero: k = 1 is the V-cycle itself; many cycles converge to A^-1 r;
+    # the k-cycle operator is symmetric (V symmetric), so MINRES may use it
+    import scipy.sparse.linalg as spla
+    S, b = _sinker_system(2)
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal(S.nu_)
+    assert np.array_equal(S.velocity_cycles(1)(r), mg.vcycle(S.H, r))
+    x = spla.spsolve(S.A.tocsc(), r)
+    e = [np.linalg.norm(S.velocity_cycles(k)(r) - x) for k in (1, 2, 4, 40)]
+    assert e[0] > e[1] > e[2] and e[3] <= 1e-10 * np.linalg.norm(x)
+    s = rng.standard_normal(S.nu_)
+    V2 = S.velocity_cycles(2)
+    assert abs(s @ V2(r) - r @ V2(s)) <= 1e-12 * abs(s @ V2(r))
+    for solver, pc in (("fgmres", "triangular"), ("minres", "diagonal")):
+        res = S.solve(b, solver, tol=1e-10, restart=30, maxit=500, precond=pc, velocity_cycles=2)
+        one = S.solve(b, solver, tol=1e-10, restart=30, maxit=500, precond=pc)
+        assert res.converged and res.iterations < one.iterations, (solver, res.iterations, one.iterations)
+        xd = S.direct(b)
+        assert np.linalg.norm(res.x - xd) <= 1e-6 * np.linalg.norm(xd)

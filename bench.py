@@ -653,7 +653,7 @@ def report_stokes(args, dev) -> dict:
            "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3,
            "fgmres_restart": args.stokes_restart, "smoother": args.smoother,
            "bfbt_z_cg_steps": args.schur_iters, "bfbt_mg_z_cg_steps": args.zmg_iters,
-           "tol": args.stokes_tol or w.tol}
+           "tol": args.stokes_tol or w.tol, "velocity_cycles": args.velocity_cycles}
     runs = [r for r in (("bfbt_mg", "f32", "fgmres", "triangular", "bfbt_mg"),
                         ("bfbt_mg", "f64", "fgmres", "triangular", "bfbt_mg"),
                         ("bfbt", "f32", "fgmres", "triangular", "bfbt"),
@@ -682,7 +682,7 @@ def report_stokes(args, dev) -> dict:
                 setup[name] = round(time.perf_counter() - t0, 4)
         _, _, st = S.solve(fu, solver=solver, restart=args.stokes_restart, tol=args.stokes_tol or w.tol,
                            max_iter=args.stokes_max_iter, record_history=False, raise_on_noconv=False,
-                           precond=pc, schur=schur, schur_iters=k)
+                           precond=pc, schur=schur, schur_iters=k, velocity_cycles=args.velocity_cycles)
         key = f"{solver}_{pc}" + ("" if schur == "mass" else f"_{schur}") + f"_{mg}_mg"
         out[key] = {k: st[k] for k in ("iterations", "seconds", "rel_residual", "converged",
                                        "floor_limited")}
@@ -919,6 +919,8 @@ def main():
     ap.add_argument("--zmg-iters", type=int, default=4,
                     help="multigrid-preconditioned CG steps per Z solve of BFBT with the pressure multigrid")
     ap.add_argument("--stokes-restart", type=int, default=64)
+    ap.add_argument("--velocity-cycles", type=int, default=1,
+                    help="V-cycles per application of the velocity block's approximate inverse (1: the paper's)")
     ap.add_argument("--stokes-tol", type=float, default=None,
                     help="relative residual of the Stokes report solves (default: the workload's 1e-8)")
     ap.add_argument("--stokes-mg", default="f32,f64",

@@ -332,6 +332,11 @@ typedef struct {
     int32_t precond;         /* agca_stokes_precond                                         */
     int32_t schur;           /* agca_stokes_schur                                           */
     int32_t schur_iters;     /* BFBT, BFBT_MG: CG steps per Z solve, 1..1000 (ignored for MASS) */
+    int32_t velocity_cycles; /* V-cycles per application of the velocity block's approximate
+                                inverse, as a stationary iteration from zero (x = V r, then
+                                x += V (r - A x)); 0 or 1: the single V-cycle of the paper
+                                (Section 4), at most 8.  With a symmetric cycle the result is
+                                a fixed SPD operator, so MINRES accepts it too. */
 } agca_stokes_opts;
 
 /* Solve [[A, B^T], [B, 0]] (u, p) = (f, g) in FP64 with a block preconditioner built

@@ -92,6 +92,8 @@ struct agca_hier {
     int64_t bfbt_version = -1;   // nu_version W^-1 was formed for
     int st_schur_iters = 0;      // during a BFBT-preconditioned solve: CG steps per Z solve
     bool st_schur_mg = false;    // ... preconditioned by the pressure multigrid (else Jacobi)
+    int st_vcycles = 1;          // during a Stokes solve: V-cycles per velocity-block inverse
+    double* st_vtmp = nullptr;   // two velocity vectors for velocity_cycles > 1
     int64_t zdiag_version = -1;  // nu_version diag(Z) was formed for
     double* st_zmg = nullptr;    // pressure multigrid for Z: stencils and vectors of levels 0..L-1
     int64_t zmg_version = -1;    // nu_version the stencils were assembled for
@@ -1907,13 +1909,29 @@ static int32_t schur_inv(agca_hier* h, const double* rp, double* q) {
     return AGCA_OK;
 }
 
+// z = A~^-1 r for the velocity block: st_vcycles V-cycles of a stationary iteration from
+// zero (z = V r, then z += V (r - A z)); one V-cycle is the paper's choice (Section 4)
+static int32_t velocity_inv(agca_hier* h, const double* r, double* z) {
+    TRY(precondition(h, r, z));
+    if (h->st_vcycles <= 1) return AGCA_OK;
+    const StokesDims d = stokes_dims(h);
+    if (!h->st_vtmp) TRY(alloc_t(h, &h->st_vtmp, (size_t)(2 * d.nu)));
+    double *t = h->st_vtmp, *e = h->st_vtmp + d.nu;
+    for (int k = 1; k < h->st_vcycles; ++k) {
+        TRY(do_cube<double>(h, h->cfg.L, MODE_RESIDUAL, z, r, t, 0.0));
+        TRY(precondition(h, t, e));
+        HIPCHK(h, launch_axpby<double>(d.nu, 1.0, e, 1.0, z, h->st));
+    }
+    return AGCA_OK;
+}
+
 // z = diag(V-cycle, S^-1) r, or with the upper block-triangular preconditioner of
 // eq. (4.1), z = [[V, V B^T S^-1], [0, -S^-1]] r with S approximating the positive
 // B A^-1 B^T (diag(mass) or BFBT): q = S^-1 r_p, z_u = V(r_u + B^T q), z_p = -q.
 static int32_t stokes_precond(agca_hier* h, const double* r, double* z) {
     const StokesDims d = stokes_dims(h);
     if (!h->st_tri) {
-        TRY(precondition(h, r, z));
+        TRY(velocity_inv(h, r, z));
         TRY(schur_inv(h, r + d.nu, z + d.nu));
         return AGCA_OK;
     }
@@ -1922,7 +1940,7 @@ static int32_t stokes_precond(agca_hier* h, const double* r, double* z) {
     TRY(schur_inv(h, r + d.nu, q));
     HIPCHK(h, launch_axpby<double>(d.nu, 1.0, r, 0.0, tu, h->st));
     TRY(stokes_grad_add(h, q, tu));
-    TRY(precondition(h, tu, z));
+    TRY(velocity_inv(h, tu, z));
     HIPCHK(h, launch_axpby<double>(d.np, -1.0, q, 0.0, z + d.nu, h->st));
     return AGCA_OK;
 }
@@ -2255,6 +2273,8 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
         return fail(AGCA_E_INVALID, "schur_iters must be in [1, 1000]");
     if (bfbt && o->solver != AGCA_STOKES_FGMRES)
         return fail(AGCA_E_INVALID, "the BFBT approximation is not a fixed linear map: FGMRES only");
+    if (o->velocity_cycles < 0 || o->velocity_cycles > 8)
+        return fail(AGCA_E_INVALID, "velocity_cycles must be in [0, 8]");
     TRY(ensure_solver_vectors(h));
     std::memset(stats, 0, sizeof(*stats));
     const StokesDims d = stokes_dims(h);
@@ -2270,6 +2290,7 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     if (zmg) TRY(zmg_ready(h));
     h->st_schur_iters = bfbt ? o->schur_iters : 0;
     h->st_schur_mg = zmg;
+    h->st_vcycles = o->velocity_cycles > 1 ? o->velocity_cycles : 1;
     auto t0 = std::chrono::steady_clock::now();
     HIPCHK(h, hipMemcpyAsync(bvec, f, sizeof(double) * d.nu, hipMemcpyDeviceToDevice, h->st));
     HIPCHK(h, launch_zero_boundary<double>(3, d.nf, bvec, h->st));
@@ -2291,10 +2312,12 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
                                : stokes_minres(h, o, bvec, xvec, bn, &rel, &it, hist);
         h->st_tri = nullptr;
         h->st_schur_iters = 0;
+        h->st_vcycles = 1;
         if (rc != AGCA_OK) return rc;
     }
     h->st_tri = nullptr;
     h->st_schur_iters = 0;
+    h->st_vcycles = 1;
     // pressure with zero mean (the constant is the kernel of B^T on free velocities)
     double psum = 0.0;
     {

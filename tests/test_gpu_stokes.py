@@ -163,6 +163,31 @@ def test_bfbt_schur_approximation(case, mg_dtype):
         G.solve(_dev(fu), solver="fgmres", tol=tol, schur="bfbt", schur_iters=0)
 
 
+@pytest.mark.parametrize("solver,precond", [("fgmres", "triangular"), ("minres", "diagonal")])
+def test_velocity_cycles_match_oracle(case, solver, precond):
+    # two V-cycles per application of the velocity block's approximate inverse (a
+    # stationary iteration from zero): FP64 V-cycle against the oracle (history prefix,
+    # iteration counts), fewer iterations than with one cycle
+    L, levels, H, S, fu, GS, _ = case
+    b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
+    tol = 1e-9
+    u, p, st = GS.solve(_dev(fu), solver=solver, restart=30, tol=tol, max_iter=3000, precond=precond,
+                        velocity_cycles=2)
+    ref = S.solve(b, solver, tol=tol, restart=30, maxit=3000, precond=precond, velocity_cycles=2)
+    _, _, one = GS.solve(_dev(fu), solver=solver, restart=30, tol=tol, max_iter=3000, precond=precond)
+    print(f"[{solver} {precond} 2 V-cycles L={L}] gpu {st['iterations']} it, oracle {ref.iterations} it, "
+          f"one cycle {one['iterations']} it", flush=True)
+    assert st["converged"] and ref.converged
+    k = min(len(st["history"]), len(ref.history), 20)
+    assert np.allclose(st["history"][:k], ref.history[:k], rtol=1e-6, atol=1e-14)
+    assert abs(st["iterations"] - ref.iterations) <= max(1, int(0.05 * ref.iterations))
+    assert st["iterations"] < one["iterations"]
+    xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
+    assert np.linalg.norm(b - S.K @ xg) <= 1.0001 * tol * np.linalg.norm(b)
+    with pytest.raises(Exception):
+        GS.solve(_dev(fu), solver=solver, tol=tol, precond=precond, velocity_cycles=9)
+
+
 @pytest.mark.parametrize("case", [3], indirect=True, ids=["L3"])
 def test_fgmres_below_the_rounding_floor_stays_finite(case):
     # asking for 1e-14 drives the Arnoldi process into near-dependent vectors (the

@@ -383,6 +383,8 @@ VCYCLE_COUNTERS = [
      "SQ_INSTS_VMEM_WR", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"],
     ["VALUBusy", "SQ_ACTIVE_INST_ANY", "SQ_BUSY_CYCLES", "SQ_INSTS_VALU_FMA_F32",
      "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_ADD_F64"],
+    ["SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VALU",
+     "SQ_INST_CYCLES_VMEM_RD", "SQ_WAIT_ANY", "SQ_WAVES", "SQ_WAVE_CYCLES"],
 ]
 
 
@@ -406,8 +408,9 @@ def summarize_counters(d: str, L: int) -> str:
             if k.startswith("k_cube<3") and int(r["Grid_Size"]) == grids[k]:
                 vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
     lines = ["| kernel | waves | VALU / wave | FP FMA+ADD / wave | SALU / wave | VMEM / wave | "
-             "LDS / wave | wait / wave cycles | VALUBusy % |",
-             "|---|---|---|---|---|---|---|---|---|"]
+             "LDS / wave | wait / wave cycles | VALUBusy % | LDS wait / wave cycles | "
+             "LDS bank conflicts / LDS active | VALU active / wave cycles |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
     med = lambda v: float(np.median(v)) if v else float("nan")
     for k in sorted(vals):
         c = {name: med(v) for name, v in vals[k].items()}
@@ -418,7 +421,10 @@ def summarize_counters(d: str, L: int) -> str:
                      f"{c.get('SQ_INSTS_SALU', 0) / wv:.0f} | {vmem / wv:.0f} | "
                      f"{c.get('SQ_INSTS_LDS', 0) / wv:.0f} | "
                      f"{c.get('SQ_WAIT_INST_ANY', 0) / max(c.get('SQ_WAVE_CYCLES', 1), 1):.2f} | "
-                     f"{c.get('VALUBusy', float('nan')):.1f} |")
+                     f"{c.get('VALUBusy', float('nan')):.1f} | "
+                     f"{c.get('SQ_WAIT_INST_LDS', float('nan')) / max(c.get('SQ_WAVE_CYCLES', 1), 1):.3f} | "
+                     f"{c.get('SQ_LDS_BANK_CONFLICT', float('nan')) / max(c.get('SQ_ACTIVE_INST_LDS', 1), 1):.3f} | "
+                     f"{c.get('SQ_ACTIVE_INST_VALU', float('nan')) / max(c.get('SQ_WAVE_CYCLES', 1), 1):.3f} |")
     return "\n".join(lines)
 
 

@@ -19,11 +19,14 @@ condition).  Readings taken here:
 * The diag(A)-BFBT Schur approximation of eq. (4.2):
   S~^-1 = Z^-1 (B W^-1 A W^-1 B^T) Z^-1 with W = diag(A) and Z = B W^-1 B^T, both
   taken on the free velocity dofs.  Z has the constant pressure in its kernel; the
-  paper solves with Z by an algebraic multigrid cycle, which this build does not
-  have: here "Z^-1 r" means a fixed number k of Jacobi-preconditioned CG steps on
-  Z y = r from y = 0 (a step whose direction has zero Z-energy, as for r = 0, has
-  step size zero).  A fixed k keeps the map deterministic; it is not linear in r,
-  so it serves inside FGMRES only.
+  paper solves with Z by an algebraic multigrid cycle inside CG.  Here "Z^-1 r" is a
+  fixed number k of CG steps on Z y = r from y = 0 (a step whose direction has zero
+  Z-energy, as for r = 0, has step size zero), preconditioned either by Jacobi
+  (z_solve) or by one V-cycle of a geometric multigrid for Z (ZHierarchy, below).
+  A fixed k keeps the map deterministic; it is not linear in r, so it serves inside
+  FGMRES only.
+* The velocity block's approximate inverse is one V-cycle (Section 4); k V-cycles of
+  a stationary iteration from zero are an option (velocity_cycles).
 * Preconditioners: block diagonal, diag(V-cycle of A, diag(m)^-1), and the upper
   block-triangular one of eq. (4.1).  With S~ an approximation of the positive
   B A^-1 B^T, the inverse of [[A, B^T], [0, -S~]] is

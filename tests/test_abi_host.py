@@ -61,3 +61,16 @@ def test_null_arguments_are_errors_not_crashes():
     assert lib.agca_apply(None, 0, 0, None, None) == _lib.AGCA_E_INVALID
     assert lib.agca_destroy(None) == _lib.AGCA_OK
     assert lib.agca_device_bytes(None) == 0
+
+
+def test_stokes_entry_points_reject_a_null_hierarchy():
+    # the Stokes and pressure-multigrid entry points check the handle before any device
+    # work (no GPU needed to call them this way)
+    from paper_2511_13109_amd import _lib
+    lib = _lib.load()
+    assert lib.agca_stokes_schur_apply(None, _lib.SCHUR_BFBT_MG, 4, None, None) == _lib.AGCA_E_INVALID
+    assert b"null hierarchy" in lib.agca_last_error()
+    assert lib.agca_stokes_z_stencil(None, 0, None) == _lib.AGCA_E_INVALID
+    assert lib.agca_stokes_z_vcycle(None, None, None) == _lib.AGCA_E_INVALID
+    opts = _lib.StokesOpts()
+    assert lib.agca_stokes_solve(None, opts, None, None, None, None, None) == _lib.AGCA_E_INVALID

@@ -120,6 +120,31 @@ def test_fgmres_bfbt_mg_matches_oracle(zcase):
     assert np.linalg.norm(b - S.K @ xg) <= 1.0001 * tol * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("zcase", [4], indirect=True, ids=["L4"])
+def test_bfbt_mg_with_the_fp32_velocity_cycle(zcase):
+    # BFBT with multigrid Z solves around the FP32/FP32-coefficient V-cycle: converged,
+    # residual recomputed by the oracle; velocity_cycles 0 and 1 are the same solve
+    from paper_2511_13109_amd import Hierarchy, Stokes
+    L, H, S, ZH, fu, GS = zcase
+    nu_l = [np.asarray(v) for v in H.nu_levels]
+    G32 = Hierarchy(L, 3, _dev(nu_l[L]), [_dev(v) for v in nu_l[:L]], mg_dtype="f32", mg_nu_dtype="f32")
+    try:
+        S32 = Stokes(G32)
+        b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
+        tol = 1e-8
+        u, p, st = S32.solve(_dev(fu), solver="fgmres", restart=30, tol=tol, max_iter=2000,
+                             precond="triangular", schur="bfbt_mg", schur_iters=4)
+        assert st["converged"]
+        xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
+        assert np.linalg.norm(b - S.K @ xg) <= 1.0001 * tol * np.linalg.norm(b)
+        _, _, st0 = S32.solve(_dev(fu), solver="fgmres", restart=30, tol=tol, max_iter=2000,
+                              precond="triangular", schur="bfbt_mg", schur_iters=4, velocity_cycles=0)
+        assert st0["history"] == st["history"]
+        print(f"[fgmres triangular BFBT_MG FP32 V-cycle L={L}] {st['iterations']} it", flush=True)
+    finally:
+        G32.close()
+
+
 def test_bad_arguments(zcase):
     L, H, S, ZH, fu, GS = zcase
     r = GS.pvec()

@@ -629,6 +629,17 @@ def extra_129(args, dev) -> dict:
     for _ in range(2):      # warm-up solves (the first run of each kernel pays its load)
         solve_record(H64, b, "pcg", w.tol)
         solve_record(H32, b, "fcg", w.tol)
+    # one V-cycle of each hierarchy, median of 30 back-to-back (HIP events)
+    vc = {}
+    for key, H, rhs in (("fp64", H64, b), ("fp32_bf16", H32, b.float())):
+        z = torch.empty_like(rhs)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(30)]
+        for e0, e1 in ev:
+            e0.record()
+            H.vcycle(rhs, z)
+            e1.record()
+        torch.cuda.synchronize()
+        vc[key] = round(float(np.median([e0.elapsed_time(e1) for e0, e1 in ev])), 4)
     _, r64 = solve_record(H64, b, "pcg", w.tol)
     _, r32 = solve_record(H32, b, "fcg", w.tol)
     times = {}
@@ -640,7 +651,7 @@ def extra_129(args, dev) -> dict:
     return {"workload": f"{w.name}: {w.description}", "apply_us_cold": round(t, 2),
             "apply_GDoF_s": round(free_dofs / t / 1e3, 2),
             "apply_frac_hbm_peak": round(apply_bytes(L, nc) / t / 1e3 / HBM_PEAK_GBS, 4),
-            "time_to_tol_s": times, "solves": {"fp64_mg_pcg": r64, "fp32_mg_fcg": r32}}
+            "vcycle_ms": vc, "time_to_tol_s": times, "solves": {"fp64_mg_pcg": r64, "fp32_mg_fcg": r32}}
 
 
 def report_stokes(args, dev) -> dict:

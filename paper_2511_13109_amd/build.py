@@ -23,7 +23,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libagca.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["agca.hip", "k_apply.hip", "k_setup.hip", "k_stencil.hip", "k_stokes.hip", "k_vec.hip", "k_zmg.hip"]
+SOURCES = ["agca.hip", "k_apply.hip", "k_coarse_cycle.hip", "k_setup.hip", "k_stencil.hip", "k_stokes.hip", "k_vec.hip", "k_zmg.hip"]
 
 
 def hipcc() -> str:

@@ -16,6 +16,7 @@
 #include "stop_rule.h"
 #include "zstencil.h"
 #include "internal.h"
+#include "level_ops.h"
 
 using namespace agca;
 
@@ -244,30 +245,7 @@ int32_t do_cube(agca_hier* h, int l, int mode, const T* u, const T* b, T* out, T
     return do_cube<T>(h, l, mode, u, b, out, jacobi_sweep<T>(omega));
 }
 
-// Chebyshev smoother of degree m on level l (Section 4): the Chebyshev iteration for
-// D^-1 A on [lmax / 10, lmax], lmax = 1.1 x the level's eigenvalue estimate.  Pass 0
-// from x: x + D^-1 (b - A x) / theta.  Pass k >= 1: x_k + c1 (x_k - x_{k-1}) +
-// c2 D^-1 (b - A x_k) with rho_k = 1 / (2 sigma - rho_{k-1}), c1 = rho_k rho_{k-1},
-// c2 = 2 rho_k / delta, rho_0 = 1 / sigma.
-struct Cheb {
-    double theta = 1.0, delta = 1.0, sigma = 1.0;
-    explicit Cheb(double lam) {
-        const double lmax = 1.1 * lam, lmin = lmax / 10.0;
-        theta = 0.5 * (lmax + lmin);
-        delta = 0.5 * (lmax - lmin);
-        sigma = theta / delta;
-    }
-    // (c1, c2) of pass k >= 1
-    void coef(int k, double* c1, double* c2) const {
-        double rho = 1.0 / sigma, rho_new = rho;
-        for (int i = 1; i <= k; ++i) {
-            rho_new = 1.0 / (2.0 * sigma - rho);
-            if (i < k) rho = rho_new;
-        }
-        *c1 = rho_new * rho;
-        *c2 = 2.0 * rho_new / delta;
-    }
-};
+// Chebyshev pass coefficients (Cheb, level_ops.h) as a Sweep
 template <typename T>
 Sweep<T> cheb_sweep(const Cheb& ch, int k, const T* xprev) {
     Sweep<T> s;
@@ -293,6 +271,61 @@ template <typename T>
 bool fusable(const agca_hier* h, int l) {
     const LevelOp<T> op = level_op<T>(h, l);
     return op.sten == nullptr && op.blk == nullptr;
+}
+
+// Mode and coefficients of smoothing pass k on level l (k >= 1 before the coarse
+// correction, where pass 0 is formed from zero; k >= 0 after it): damped Jacobi; for
+// Chebyshev, pass 0 is x + D^-1 (b - A x) / theta, pass 1 before the correction starts
+// from x_prev = 0 (gamma = 0), every other pass is a Chebyshev step reading x_prev.
+template <typename T>
+int smooth_pass_coef(const agca_hier* h, int l, bool pre, int k, const T* xprev, Sweep<T>* sw) {
+    if (h->cfg.smoother != AGCA_SMOOTH_CHEBYSHEV) {
+        *sw = jacobi_sweep<T>(T(h->cfg.omega));
+        return MODE_JACOBI;
+    }
+    const Cheb ch(h->lam[l]);
+    if (k == 0) {
+        *sw = cheb_sweep<T>(ch, 0, nullptr);
+        return MODE_JACOBI;
+    }
+    *sw = cheb_sweep<T>(ch, k, xprev);
+    if (pre && k == 1) {
+        sw->gamma = T(0);
+        sw->xprev = nullptr;
+        return MODE_JACOBI;
+    }
+    return MODE_CHEB;
+}
+
+// Levels 1..K that the coarse end of a V-cycle runs in one workgroup (k_coarse_cycle.hip):
+// consecutive assembled-stencil levels from level 1 up, each below the finest level, whose
+// stencil one compute unit reads per pass in about a microsecond (at most
+// kFuseStencilBytes: levels 1-2 of a scalar hierarchy, level 1 of a vector one; beyond
+// that the one workgroup is slower than a launch per pass spread over the chip), with at
+// most AGCA_FUSE_MAX_N cells per axis (default 8; 0 turns the fused cycle off) and the
+// LDS of levels 0..K within 64 KiB; 0 when level 1 does not qualify or a smoothing phase
+// has more passes than the fused cycle takes.
+constexpr size_t kFuseStencilBytes = 160 * 1024;
+int fuse_max_n() {
+    static const int v = [] {
+        const char* e = getenv("AGCA_FUSE_MAX_N");
+        return e ? atoi(e) : 8;
+    }();
+    return v;
+}
+template <typename T>
+int coarse_cycle_levels(const agca_hier* h) {
+    if (h->cfg.pre_sweeps > kCyclePasses || h->cfg.post_sweeps > kCyclePasses) return 0;
+    const int nc = h->cfg.ncomp;
+    int K = 0;
+    for (int l = 1; l <= kCycleLevels && l < h->cfg.L; ++l) {
+        const Level& lv = h->lv[l];
+        if (!level_op<T>(h, l).sten || lv.n != (2 << l) || lv.n > fuse_max_n()) break;
+        if ((size_t)nc * nc * kStencilPoints * lv.nodes * sizeof(T) > kFuseStencilBytes) break;
+        if (coarse_cycle_lds(nc, l, sizeof(T)) > 65536) break;
+        K = l;
+    }
+    return K;
 }
 
 template <typename T>
@@ -328,14 +361,15 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
     const int pre = h->cfg.pre_sweeps, post = h->cfg.post_sweeps;
     const bool cheb = h->cfg.smoother == AGCA_SMOOTH_CHEBYSHEV;
     // pass k of a smoothing phase; xprev = the iterate before the current one
-    auto pass = [&](int l, int k, const T* x, const T* bl, T* out, const T* xprev) -> int32_t {
-        if (!cheb) return do_cube<T>(h, l, MODE_JACOBI, x, bl, out, om);
-        const Cheb ch(h->lam[l]);
-        if (k == 0) return do_cube<T>(h, l, MODE_JACOBI, x, bl, out, cheb_sweep<T>(ch, 0, nullptr));
-        return do_cube<T>(h, l, MODE_CHEB, x, bl, out, cheb_sweep<T>(ch, k, xprev));
+    auto pass = [&](int l, bool pre_phase, int k, const T* x, const T* bl, T* out, const T* xprev) -> int32_t {
+        Sweep<T> sw;
+        const int mode = smooth_pass_coef<T>(h, l, pre_phase, k, xprev, &sw);
+        return do_cube<T>(h, l, mode, x, bl, out, sw);
     };
+    // levels K..1 and the level-0 solve run as one workgroup-resident kernel
+    const int K = coarse_cycle_levels<T>(h);
     std::vector<T*> xcur(L + 1, nullptr), xalt(L + 1, nullptr);
-    for (int l = L; l >= 1; --l) {
+    for (int l = L; l > K; --l) {
         const int64_t cnt = (int64_t)nc * h->lv[l].nodes;
         const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
         T* home = (l == L) ? xL : static_cast<T*>(h->lv[l].x);
@@ -360,14 +394,7 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
             HIPCHK(h, launch_fill<T>(cnt, T(0), cur, h->st));
         }
         for (int i = first; i < pre; ++i) {
-            if (cheb && i == 1) {
-                // pass 1 from x1 with x_prev = 0: alpha x1 + omega D^-1 (b - A x1)
-                Sweep<T> sw = cheb_sweep<T>(Cheb(h->lam[l]), 1, nullptr);
-                sw.gamma = T(0);
-                TRY(do_cube<T>(h, l, MODE_JACOBI, cur, bl, alt, sw));
-            } else {
-                TRY(pass(l, i, cur, bl, alt, alt));
-            }
+            TRY(pass(l, true, i, cur, bl, alt, alt));
             std::swap(cur, alt);
         }
         xcur[l] = cur;
@@ -376,16 +403,48 @@ int32_t do_vcycle(agca_hier* h, const T* bL, T* xL) {
         TRY(do_cube<T>(h, l, MODE_RESIDUAL, cur, bl, rl, T(0)));
         HIPCHK(h, launch_restrict<T>(nc, h->lv[l].n, rl, static_cast<T*>(h->lv[l - 1].b), h->st));
     }
-    HIPCHK(h, launch_coarse_solve<T>(nc, h->ainv0, static_cast<const T*>(h->lv[0].b),
-                                     static_cast<T*>(h->lv[0].x), h->st));
-    xcur[0] = static_cast<T*>(h->lv[0].x);
-    for (int l = 1; l <= L; ++l) {
+    if (K >= 1) {
+        CoarseCycle<T> cc;
+        cc.pre = pre;
+        cc.post = post;
+        for (int l = 1; l <= K; ++l) {
+            const LevelOp<T> op = level_op<T>(h, l);
+            cc.sten[l] = op.sten;
+            cc.dinv[l] = op.dinv;
+            cc.first_omega[l] = cheb ? T(1.0 / Cheb(h->lam[l]).theta) : om;
+            for (int k = 0; k < kCyclePasses; ++k) {
+                Sweep<T> sw;
+                if (k >= 1 && k < pre) {
+                    cc.pre_mode[l][k] = (int8_t)smooth_pass_coef<T>(h, l, true, k, nullptr, &sw);
+                    cc.pre_c[l][k][0] = sw.alpha;
+                    cc.pre_c[l][k][1] = sw.gamma;
+                    cc.pre_c[l][k][2] = sw.omega;
+                }
+                if (k < post) {
+                    cc.post_mode[l][k] = (int8_t)smooth_pass_coef<T>(h, l, false, k, nullptr, &sw);
+                    cc.post_c[l][k][0] = sw.alpha;
+                    cc.post_c[l][k][1] = sw.gamma;
+                    cc.post_c[l][k][2] = sw.omega;
+                }
+            }
+        }
+        cc.ainv = h->ainv0;
+        cc.b = static_cast<const T*>(h->lv[K].b);
+        cc.x = static_cast<T*>(h->lv[K].x);
+        HIPCHK(h, launch_coarse_cycle<T>(nc, K, cc, h->st));
+        xcur[K] = cc.x;
+    } else {
+        HIPCHK(h, launch_coarse_solve<T>(nc, h->ainv0, static_cast<const T*>(h->lv[0].b),
+                                         static_cast<T*>(h->lv[0].x), h->st));
+        xcur[0] = static_cast<T*>(h->lv[0].x);
+    }
+    for (int l = K + 1; l <= L; ++l) {
         const T* bl = (l == L) ? bL : static_cast<const T*>(h->lv[l].b);
         T* cur = xcur[l];
         T* alt = xalt[l];
         HIPCHK(h, launch_prolong_add<T>(nc, h->lv[l].n, xcur[l - 1], cur, h->st));
         for (int i = 0; i < post; ++i) {
-            TRY(pass(l, i, cur, bl, alt, alt));
+            TRY(pass(l, false, i, cur, bl, alt, alt));
             std::swap(cur, alt);
         }
         xcur[l] = cur;

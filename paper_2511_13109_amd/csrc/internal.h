@@ -78,6 +78,34 @@ hipError_t launch_prolong_add(int ncomp, int n_fine, const T* ec, T* xf, hipStre
 template <typename T>
 hipError_t launch_coarse_solve(int ncomp, const double* ainv, const T* b, T* x, hipStream_t st);
 
+// The coarse end of a V-cycle in one workgroup (k_coarse_cycle.hip): levels K..1 (all
+// assembled-stencil levels, level l with n = 2^(l+1) cells) and the level-0 solve, from
+// the level-K right-hand side b to the level-K iterate x, with every intermediate vector
+// in LDS.  Smoothing passes as in the per-launch V-cycle: pre-smoothing pass 0 is x = first_omega D^-1 b from zero (0 when
+// pre = 0), pre passes 1.. and post passes 0.. write
+// x_out = alpha x + gamma x_prev + omega D^-1 (b - A x) with the mode and coefficients
+// given per level and pass (MODE_JACOBI ignores gamma).
+constexpr int kCycleLevels = 3;  // K <= 3
+constexpr int kCyclePasses = 8;  // pre, post <= 8
+template <typename T>
+struct CoarseCycle {
+    int pre = 0, post = 0;
+    const T* sten[kCycleLevels + 1] = {};
+    const T* dinv[kCycleLevels + 1] = {};
+    T first_omega[kCycleLevels + 1] = {};
+    int8_t pre_mode[kCycleLevels + 1][kCyclePasses] = {};
+    int8_t post_mode[kCycleLevels + 1][kCyclePasses] = {};
+    T pre_c[kCycleLevels + 1][kCyclePasses][3] = {};   // alpha, gamma, omega
+    T post_c[kCycleLevels + 1][kCyclePasses][3] = {};
+    const double* ainv = nullptr;  // level-0 inverse, ncomp x ncomp
+    const T* b = nullptr;          // level K, ncomp (n+1)^3 values (device)
+    T* x = nullptr;                // level K, written
+};
+// LDS bytes of the fused cycle over levels 0..K
+size_t coarse_cycle_lds(int ncomp, int K, size_t elem);
+template <typename T>
+hipError_t launch_coarse_cycle(int ncomp, int K, const CoarseCycle<T>& a, hipStream_t st);
+
 // vector kernels
 template <typename T>
 hipError_t launch_dot_partial(const T* x, const T* y, int64_t n, double* partial, int nblocks,

@@ -16,12 +16,13 @@
 
 #include "internal.h"
 #include "kuhn.h"
+#include "level_ops.h"
 
 namespace agca {
 namespace {
 
 constexpr int NT = 256;
-constexpr int NNB = 15;
+constexpr int NNB = kStencilPoints;
 
 // One thread per (node, component pair c, d = blockIdx.y / NC, blockIdx.y % NC);
 // rows of boundary nodes stay zero.  Loops over the 8 cells around the node and the
@@ -77,7 +78,7 @@ k_stencil_assemble(int n, const double* __restrict__ nu, double scale, const int
     for (int k = 0; k < NNB; ++k) S[((int64_t)(c * NC + d) * NNB + k) * N + p] = acc[k];
 }
 
-// One thread per (node, component c = blockIdx.y).
+// One thread per (node, component c = blockIdx.y); the body is stencil_node (level_ops.h).
 template <int NC, typename T, int MODE>
 __global__ void __launch_bounds__(NT)
 k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T* __restrict__ b,
@@ -85,39 +86,8 @@ k_stencil_apply(int n, const T* __restrict__ S, const T* __restrict__ u, const T
                 const T* __restrict__ xprev) {
     const int64_t n1 = n + 1, N = n1 * n1 * n1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
-    const int c = blockIdx.y;
     if (p >= N) return;
-    int x, y, z;
-    node_coords(p, n, x, y, z);
-    const bool interior = x > 0 && y > 0 && z > 0 && x < n && y < n && z < n;
-    if (!interior) {
-        out[c * N + p] = T(0);
-        return;
-    }
-    T acc = T(0);
-#pragma unroll
-    for (int k = 0; k < NNB; ++k) {
-        const int m = nbr_mask(k), sg = nbr_sign(k);
-        const int qx = x + sg * (m & 1), qy = y + sg * ((m >> 1) & 1), qz = z + sg * (m >> 2);
-        // boundary values of u are ignored (treated as zero)
-        const bool qin = qx > 0 && qy > 0 && qz > 0 && qx < n && qy < n && qz < n;
-        const int64_t q = qx + n1 * (qy + n1 * (int64_t)qz);
-#pragma unroll
-        for (int d = 0; d < NC; ++d) {
-            const T v = u[d * N + q];
-            acc += S[((int64_t)(c * NC + d) * NNB + k) * N + p] * (qin ? v : T(0));
-        }
-    }
-    const int64_t o = c * N + p;
-    if constexpr (MODE == MODE_APPLY) {
-        out[o] = acc;
-    } else if constexpr (MODE == MODE_RESIDUAL) {
-        out[o] = b[o] - acc;
-    } else if constexpr (MODE == MODE_CHEB) {
-        out[o] = alpha * u[o] + gamma * xprev[o] + omega * dinv[o] * (b[o] - acc);
-    } else {
-        out[o] = alpha * u[o] + omega * dinv[o] * (b[o] - acc);
-    }
+    stencil_node<NC, T, MODE>(n, p, (int)blockIdx.y, S, u, b, dinv, out, omega, alpha, gamma, xprev);
 }
 
 template <int NC, typename T, int MODE>

@@ -4,6 +4,7 @@
 
 #include "cube_math.h"
 #include "internal.h"
+#include "level_ops.h"
 
 namespace agca {
 namespace {
@@ -19,73 +20,24 @@ constexpr int NT = 256;
 // Restriction is the transpose: a coarse node Y collects r(2Y) plus half of
 // r(2Y + d) and r(2Y - d) for the 7 offsets d.  Boundary nodes stay zero.
 // ---------------------------------------------------------------------------
-// r_c = P^T r_f at one coarse node per thread, all components (the summation order of
-// each component is fixed: the node itself plus half of its 14 lattice neighbours,
-// pairwise by direction)
+// r_c = P^T r_f at one coarse node per thread, all components (restrict_node)
 template <int NC, typename T>
 __global__ void __launch_bounds__(NT)
 k_restrict(int nc, const T* __restrict__ rf, T* __restrict__ rc) {
     const int64_t nc1 = nc + 1, Nc = nc1 * nc1 * nc1;
-    const int64_t nf1 = 2 * nc + 1, Nf = nf1 * nf1 * nf1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (p >= Nc) return;
-    int x, y, z;
-    node_coords(p, nc, x, y, z);
-    const bool interior = x > 0 && y > 0 && z > 0 && x < nc && y < nc && z < nc;
-    if (!interior) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) rc[c * Nc + p] = T(0);
-        return;
-    }
-    const int64_t q = 2 * x + nf1 * (2 * y + nf1 * (int64_t)(2 * z));
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const T* f = rf + c * Nf;
-        T half = T(0);
-#pragma unroll
-        for (int d = 1; d < 8; ++d) {
-            const int64_t off = (d & 1) + nf1 * (((d >> 1) & 1) + nf1 * ((d >> 2) & 1));
-            half += f[q + off] + f[q - off];
-        }
-        rc[c * Nc + p] = f[q] + T(0.5) * half;
-    }
+    restrict_node<NC, T>(nc, p, rf, rc);
 }
 
-// x_f += P e_c at one fine node per thread, all components: the midpoint rule
-// 0.5 (e(lo) + e(hi)) with lo = hi at the fine nodes that coincide with coarse ones
-// (there 0.5 (e + e) = e exactly), so every thread runs the same code; all loads are
-// issued before the stores.
+// x_f += P e_c at one fine node per thread, all components (prolong_add_node)
 template <int NC, typename T>
 __global__ void __launch_bounds__(NT)
 k_prolong_add(int nf, const T* __restrict__ ec, T* __restrict__ xf) {
-    const int nc = nf / 2;
-    const int64_t nc1 = nc + 1, Nc = nc1 * nc1 * nc1;
     const int64_t nf1 = nf + 1, Nf = nf1 * nf1 * nf1;
     const int64_t p = blockIdx.x * (int64_t)NT + threadIdx.x;
     if (p >= Nf) return;
-    int x, y, z;
-    node_coords(p, nf, x, y, z);
-    if (x == 0 || y == 0 || z == 0 || x == nf || y == nf || z == nf) return;
-    const int dx = x & 1, dy = y & 1, dz = z & 1;
-    const int64_t lo = ((x - dx) >> 1) + nc1 * (((y - dy) >> 1) + nc1 * (int64_t)((z - dz) >> 1));
-    const int64_t hi = ((x + dx) >> 1) + nc1 * (((y + dy) >> 1) + nc1 * (int64_t)((z + dz) >> 1));
-    T a[NC], b[NC], v[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        a[c] = ec[c * Nc + lo];
-        b[c] = ec[c * Nc + hi];
-        v[c] = xf[c * Nf + p];
-    }
-    // coarse boundary slots are not part of the input (they hold 0 in every vector the
-    // library writes, but a caller's may not): a coarse endpoint on the boundary counts 0
-    auto on_bd = [nc](int cx, int cy, int cz) {
-        return cx == 0 || cy == 0 || cz == 0 || cx == nc || cy == nc || cz == nc;
-    };
-    const bool lo_bd = on_bd((x - dx) >> 1, (y - dy) >> 1, (z - dz) >> 1);
-    const bool hi_bd = on_bd((x + dx) >> 1, (y + dy) >> 1, (z + dz) >> 1);
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-        xf[c * Nf + p] = v[c] + T(0.5) * ((lo_bd ? T(0) : a[c]) + (hi_bd ? T(0) : b[c]));
+    prolong_add_node<NC, T>(nf, p, ec, xf);
 }
 
 // level 0 has n = 2: a single free node (1,1,1), id 13 of 27
@@ -94,11 +46,7 @@ __global__ void k_coarse_solve(int ncomp, const double* __restrict__ ainv, const
                                T* __restrict__ x) {
     const int t = threadIdx.x;
     if (t >= 27 * ncomp) return;
-    const int c = t / 27, p = t % 27;
-    double v = 0.0;
-    if (p == 13)
-        for (int d = 0; d < ncomp; ++d) v += ainv[c * ncomp + d] * (double)b[d * 27 + 13];
-    x[t] = T(v);
+    coarse_solve_slot<T>(ncomp, t, ainv, b, x);
 }
 
 // ---------------------------------------------------------------------------

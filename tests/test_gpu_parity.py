@@ -339,6 +339,38 @@ def test_chebyshev_smoother(case):
         G32.close()
 
 
+# Uneven and zero smoothing counts.  On these 17^3 hierarchies levels 1-2 (scalar) or
+# level 1 (vector) run as one workgroup-resident kernel, the levels above as one launch
+# per pass: both must follow the oracle's cycle pass for pass.
+SWEEP_CASES = [("jacobi", 1, 3), ("jacobi", 3, 0), ("jacobi", 0, 2), ("chebyshev", 3, 1),
+               ("chebyshev", 1, 4), ("chebyshev", 0, 3)]
+
+
+@pytest.mark.parametrize("ncomp", [1, 3])
+@pytest.mark.parametrize("sweeps", SWEEP_CASES, ids=lambda s: f"{s[0]}-{s[1]}-{s[2]}")
+def test_vcycle_uneven_sweeps(sweeps, ncomp):
+    from paper_2511_13109_amd import Hierarchy
+    import copy
+    smoother, pre, post = sweeps
+    print(f"\n[uneven sweeps {sweeps} nc={ncomp}]", flush=True)
+    H0, nu_levels, _ = oracle_case("sinkers", 3, ncomp, 0, smoother)
+    H = copy.copy(H0)
+    H.nu1, H.nu2 = pre, post
+    nus = [_dev(v) for v in nu_levels]
+    G = Hierarchy(3, ncomp, nus[3], nus[:3], smoother=smoother, pre=pre, post=post)
+    try:
+        rng = np.random.default_rng(12)
+        for _ in range(2):  # the second call starts from the first one's buffers
+            b = rand_full(H, 3, rng)
+            x = G.vcycle(_dev(b)).cpu().numpy()
+            e_gpu, e_orc, tol = vcycle_errors(H, b, x)
+            print(f"[uneven sweeps {sweeps} nc={ncomp}] library {e_gpu:.2e}, oracle FP64 {e_orc:.2e} "
+                  f"(tolerance {tol:.1e})", flush=True)
+            assert e_gpu < tol
+    finally:
+        G.close()
+
+
 def _jacobi_twin(H):
     import copy
     J = copy.copy(H)

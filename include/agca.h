@@ -250,10 +250,11 @@ typedef struct {
  * when it reaches tol (the search direction is kept).  They stop when the true residual
  * is <= tol (converged), or when it has stopped improving (two windows in a row
  * without a 10 % gain over its best, a window being the iterations the recurrence last
- * took to halve): then floor_limited if it is at most max(tol, rho), rho the rounding floor of
- * x (agca_residual_floor), else a stall.  Returns AGCA_OK when converged or
- * floor_limited; AGCA_E_NOCONV (x and stats filled) when max_iter is reached first or
- * the true residual stalls above max(tol, rho). */
+ * took to halve) and is at most max(tol, rho), rho the rounding floor of x
+ * (agca_residual_floor): floor_limited.  A stalled solve above that level keeps
+ * checking at each later replacement and gives up after six windows without progress.
+ * Returns AGCA_OK when converged or floor_limited; AGCA_E_NOCONV (x and stats filled)
+ * when max_iter is reached first or the true residual stalls above max(tol, rho). */
 int32_t agca_solve(agca_hier* h, const agca_solve_opts* opts, const double* b, double* x,
                    agca_solve_stats* stats);
 

@@ -1411,7 +1411,7 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     int it = 0, replacements = 0;
     bool floor_limited = false, stalled = false;
     EndChecks ends;
-    double rho = 0.0;
+    double rho = -1.0;  // formed at the first stall
     int32_t status = AGCA_OK;
     double rec_rel = rel;
     // milestones: record the first iteration whose verified true residual is below each
@@ -1515,11 +1515,14 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
                         break;
                     }
                     if (ends.stagnated(rel_true, it, full)) {
-                        TRY(residual_floor(h, b, x, &rho));
-                        rel = rel_true;
-                        floor_limited = at_floor(rel_true, o->tol, rho);
-                        stalled = !floor_limited;
-                        break;
+                        // the floor of x changes little once the solve has stalled: formed once
+                        if (rho < 0.0) TRY(residual_floor(h, b, x, &rho));
+                        if (at_floor(rel_true, o->tol, rho) || ends.given_up()) {
+                            rel = rel_true;
+                            floor_limited = at_floor(rel_true, o->tol, rho);
+                            stalled = !floor_limited;
+                            break;
+                        }
                     }
                     rel = rec_rel = rel_true;
                 }
@@ -1561,6 +1564,7 @@ int32_t agca_solve(agca_hier* h, const agca_solve_opts* o, const double* b, doub
     TRY(do_cube<double>(h, L, MODE_RESIDUAL, x, b, r, 0.0));
     TRY(do_dot<double>(h, r, r, cnt, &rr));
     stats->rel_residual = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+    rho = 0.0;
     if (bn > 0) TRY(residual_floor(h, b, x, &rho));
     stats->floor_estimate = rho;
     stats->recursive_rel_residual = rec_rel;

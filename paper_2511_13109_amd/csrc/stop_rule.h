@@ -7,15 +7,18 @@
 // whenever the recurrence reaches tol.  Far above the floor the true residual follows
 // the recurrence; the iterations a full period takes measure how fast it converges.  The
 // solver stops when the true residual has gone that many iterations without a 10 % gain
-// over its best, twice in a row: progress is judged over the iterations in which a
-// converging solve would have halved its residual, not from one check to the next (near
+// over its best, twice in a row (progress is judged over the iterations in which a
+// converging solve would have halved its residual, not from one check to the next: near
 // tol the checks come every few iterations, and a solve still converging there shows
-// small gains between them).  The stop counts as the
-// rounding floor only when the true residual is at most kFloorFactor max(tol, rho),
-// rho the floor of the iterate: u || |b| + sum_e |A_e| |x_e| || / ||b||, a bound on how
-// far one more FP64 rounding of x can move the residual (measured stagnation levels of
-// PCG sit at a quarter to a third of it).  Otherwise the solve has stalled above the
-// floor and is reported as not converged.
+// small gains between them), and the true residual is at the rounding floor: at most
+// kFloorFactor max(tol, rho), rho the floor of the iterate, u || |b| + sum_e |A_e| |x_e| ||
+// / ||b||, a bound on how far one more FP64 rounding of x can move the residual
+// (measured stagnation levels of PCG sit at a quarter to a third of it).  Near the floor
+// the true residual of a replacement swings by a factor of a few around rho (it carries
+// the rounding the iterate gathered since the last replacement, which the next step
+// removes), so once stalled the solve keeps checking at every later replacement.  A
+// solve that goes kGiveUpStalls windows without progress and never reaches the floor
+// has stalled above it and is reported as not converged.
 #pragma once
 
 #include <cmath>
@@ -25,7 +28,8 @@ namespace agca {
 constexpr double kReplaceEvery = 0.5;  // a full period: the recurrence halved since the last replacement
 constexpr double kFloorFactor = 1.0;   // a floor stop needs rel_true <= max(tol, rho)
 constexpr double kEndGain = 0.9;       // progress: 10 % below the best true residual so far
-constexpr int kEndStalls = 2;          // windows in a row without progress that stop
+constexpr int kEndStalls = 2;          // windows in a row without progress: stop at the floor
+constexpr int kGiveUpStalls = 6;       // ... stop above it (not converged)
 
 struct EndChecks {
     double best = HUGE_VAL;
@@ -54,6 +58,9 @@ struct EndChecks {
         }
         return stalls >= kEndStalls;
     }
+    // after stagnated(): whether the solve has gone too long without progress to wait for
+    // the floor any longer
+    bool given_up() const { return stalls >= kGiveUpStalls; }
 };
 
 // whether a stop with true relative residual rel_true counts as the rounding floor

@@ -115,7 +115,12 @@ static void stop() {
         int it, full;
         if (std::scanf("%lf %d %d", &r, &it, &full) != 3) return;
         int verdict = 0;
-        if (ends.stagnated(r, it, full != 0)) verdict = at_floor(r, tol, rho) ? 1 : 2;
+        if (ends.stagnated(r, it, full != 0)) {
+            if (at_floor(r, tol, rho))
+                verdict = 1;
+            else if (ends.given_up())
+                verdict = 2;
+        }
         std::printf("%d\n", verdict);
         if (verdict) break;
     }

@@ -96,7 +96,9 @@ typedef struct {
                                 blocks, diagonals and work vectors                          */
     int32_t mg_nu_dtype;     /* AGCA_F64, AGCA_F32 or AGCA_BF16: finest-level coefficient
                                 copy used by the V-cycle (must not be wider than mg_dtype)  */
-    int32_t pre_sweeps;      /* smoothing passes before / after the coarse correction      */
+    int32_t pre_sweeps;      /* smoothing passes before / after the coarse correction; the
+                                CG-type solvers (PCG, FCG) need pre_sweeps == post_sweeps:
+                                the V-cycle is a symmetric preconditioner only then        */
     int32_t post_sweeps;
     int32_t smoother;        /* AGCA_SMOOTH_*                                               */
     double flag_ratio;       /* tau (10 in the paper's experiments)                         */

@@ -670,7 +670,8 @@ def report_stokes(args, dev) -> dict:
            "velocity_free_dofs": 3 * (2 ** (L + 1) - 1) ** 3, "pressure_dofs": (2 ** L + 1) ** 3,
            "fgmres_restart": args.stokes_restart, "smoother": args.smoother,
            "bfbt_z_cg_steps": args.schur_iters, "bfbt_mg_z_cg_steps": args.zmg_iters,
-           "tol": args.stokes_tol or w.tol, "velocity_cycles": args.velocity_cycles}
+           "tol": args.stokes_tol or w.tol, "velocity_cycles": args.velocity_cycles,
+           "fgmres_basis": args.stokes_basis}
     runs = [r for r in (("bfbt_mg", "f32", "fgmres", "triangular", "bfbt_mg"),
                         ("bfbt_mg", "f64", "fgmres", "triangular", "bfbt_mg"),
                         ("bfbt", "f32", "fgmres", "triangular", "bfbt"),
@@ -699,7 +700,8 @@ def report_stokes(args, dev) -> dict:
                 setup[name] = round(time.perf_counter() - t0, 4)
         _, _, st = S.solve(fu, solver=solver, restart=args.stokes_restart, tol=args.stokes_tol or w.tol,
                            max_iter=args.stokes_max_iter, record_history=False, raise_on_noconv=False,
-                           precond=pc, schur=schur, schur_iters=k, velocity_cycles=args.velocity_cycles)
+                           precond=pc, schur=schur, schur_iters=k, velocity_cycles=args.velocity_cycles,
+                           basis=(args.stokes_basis if solver == "fgmres" else "f64"))
         key = f"{solver}_{pc}" + ("" if schur == "mass" else f"_{schur}") + f"_{mg}_mg"
         out[key] = {k: st[k] for k in ("iterations", "seconds", "rel_residual", "converged",
                                        "floor_limited")}
@@ -942,6 +944,8 @@ def main():
                     help="relative residual of the Stokes report solves (default: the workload's 1e-8)")
     ap.add_argument("--stokes-mg", default="f32,f64",
                     help="comma-separated V-cycle precisions of the Stokes report runs")
+    ap.add_argument("--stokes-basis", default="f64", choices=["f64", "f32"],
+                    help="storage of the FGMRES Arnoldi basis in the Stokes report runs")
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile, ""))

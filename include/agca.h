@@ -340,6 +340,13 @@ typedef struct {
                                 x += V (r - A x)); 0 or 1: the single V-cycle of the paper
                                 (Section 4), at most 8.  With a symmetric cycle the result is
                                 a fixed SPD operator, so MINRES accepts it too. */
+    int32_t basis_dtype;     /* FGMRES: storage of the Arnoldi basis V, AGCA_F64 (0, the
+                                default) or AGCA_F32 (half the Gram-Schmidt traffic; each new
+                                basis vector is rounded to FP32 once, its dot products and
+                                updates are FP64, the preconditioned vectors Z, the iterate and
+                                the residual at restarts stay FP64).  The basis's rounding
+                                bounds what one restart cycle can gain (about 1e-7 of the
+                                cycle's starting residual); lower tolerances take more cycles */
 } agca_stokes_opts;
 
 /* Solve [[A, B^T], [B, 0]] (u, p) = (f, g) in FP64 with a block preconditioner built
@@ -350,7 +357,9 @@ typedef struct {
  * fixed SPD preconditioner, which the FP32 V-cycle is only up to FP32 rounding; the true
  * residual is checked every step, so a run that stagnates reports AGCA_E_NOCONV, never a
  * false convergence).  The returned p has zero mean over the pressure nodes.  Work
- * space: 2 restart + 5 (FGMRES; one more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles, kept until destroy;
+ * space: 2 restart + 5 (FGMRES; with an FP32 basis restart + (restart + 2) / 2 + 6; one
+ * more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles,
+ * kept until destroy;
  * BFBT and BFBT_MG add 3 velocity and 8 pressure vectors, BFBT_MG its multigrid.
  * FGMRES stops early with stats->floor_limited when a restart cycle's residual
  * estimate reached tol but the true residual after it is above tol, less than 5 %

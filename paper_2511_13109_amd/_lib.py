@@ -47,7 +47,8 @@ class SolveOpts(C.Structure):
 class StokesOpts(C.Structure):
     _fields_ = [("solver", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("record_history", C.c_int32), ("tol", C.c_double), ("precond", C.c_int32),
-                ("schur", C.c_int32), ("schur_iters", C.c_int32), ("velocity_cycles", C.c_int32)]
+                ("schur", C.c_int32), ("schur_iters", C.c_int32), ("velocity_cycles", C.c_int32),
+                ("basis_dtype", C.c_int32)]
 
 
 STOKES_FGMRES, STOKES_MINRES = 0, 1

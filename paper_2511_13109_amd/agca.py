@@ -343,17 +343,19 @@ class Stokes:
     def solve(self, f: torch.Tensor, g: Optional[torch.Tensor] = None, solver: str = "fgmres",
               restart: int = 30, tol: float = 1e-8, max_iter: int = 1000, record_history: bool = True,
               raise_on_noconv: bool = True, precond: str = "diagonal", schur: str = "mass",
-              schur_iters: int = 20, velocity_cycles: int = 1):
+              schur_iters: int = 20, velocity_cycles: int = 1, basis: str = "f64"):
         """schur: 'mass' (1/nu lumped mass), 'bfbt' (eq. (4.2), FGMRES only, each Z solve
         schur_iters Jacobi-CG steps) or 'bfbt_mg' (the same with each Z solve schur_iters
         CG steps preconditioned by a pressure multigrid V-cycle); velocity_cycles: V-cycles
-        per application of the velocity block's approximate inverse (1: the paper's)."""
+        per application of the velocity block's approximate inverse (1: the paper's);
+        basis: storage of the FGMRES Arnoldi basis, 'f64' or 'f32'."""
         opts = _lib.StokesOpts()
         opts.solver = {"fgmres": _lib.STOKES_FGMRES, "minres": _lib.STOKES_MINRES}[solver]
         opts.precond = {"diagonal": _lib.STOKES_DIAGONAL, "triangular": _lib.STOKES_TRIANGULAR}[precond]
         opts.schur = self.SCHUR[schur]
         opts.schur_iters = schur_iters
         opts.velocity_cycles = velocity_cycles
+        opts.basis_dtype = {"f64": _lib.F64, "f32": _lib.F32}[basis]
         opts.restart, opts.max_iter, opts.tol = restart, max_iter, tol
         opts.record_history = 1 if record_history else 0
         g = self.pvec() if g is None else g

@@ -2029,17 +2029,41 @@ static int32_t stokes_residual(agca_hier* h, const double* b, const double* x, d
 // Stewart test with threshold 0.1; the customary 1/sqrt(2) fired on every step of the
 // sinker problems without changing a single iteration count, at twice the cost).
 constexpr double kDgks = 0.1;
+// work vectors of FGMRES(m): the basis (m + 1, in half as many slots when FP32), Z (m),
+// w, r, and the FP64 copy of a basis vector with an FP32 basis
+static int64_t fgmres_work_vecs(int m, bool v32) {
+    return v32 ? (int64_t)(m + 2) / 2 + m + 3 : 2 * (int64_t)m + 3;
+}
 static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const double* b, double* x,
                              double bn, double* rel_out, int* it_out, std::vector<double>& hist,
                              bool* floor_out, double* rho_out) {
     const int64_t tot = stokes_dims(h).tot;
     const int m = o->restart;
-    TRY(stokes_work(h, 2 * (int64_t)m + 3));
-    double* V = h->st_work;                 // m + 1 vectors
-    double* Z = V + (int64_t)(m + 1) * tot; // m vectors
+    // the basis V (m + 1 vectors, FP64 or FP32), Z (m FP64 vectors), w, r, and with an FP32
+    // basis an FP64 copy of the basis vector being preconditioned
+    const bool v32 = o->basis_dtype == AGCA_F32;
+    TRY(stokes_work(h, fgmres_work_vecs(m, v32)));
+    const int64_t vslots = v32 ? (m + 2) / 2 : m + 1;
+    double* V = v32 ? nullptr : h->st_work;
+    float* V32 = v32 ? reinterpret_cast<float*>(h->st_work) : nullptr;
+    double* Z = h->st_work + vslots * tot;
     double* w = Z + (int64_t)m * tot;
     double* r = w + tot;
+    double* vk = v32 ? r + tot : nullptr;
     auto vec = [&](double* base, int i) { return base + (int64_t)i * tot; };
+    // V_i = a x
+    auto set_basis = [&](int i, double a, const double* xx) -> hipError_t {
+        return v32 ? launch_scale_to_f32(tot, a, xx, V32 + (int64_t)i * tot, h->st)
+                   : launch_axpby<double>(tot, a, xx, 0.0, vec(V, i), h->st);
+    };
+    auto gs_dots = [&](int nv) -> hipError_t {
+        return v32 ? launch_gs_dots<float>(tot, w, V32, tot, nv, h->st_gs, h->st)
+                   : launch_gs_dots<double>(tot, w, V, tot, nv, h->st_gs, h->st);
+    };
+    auto gs_update = [&](int nv) -> hipError_t {
+        return v32 ? launch_gs_update<float>(tot, w, V32, tot, nv, h->red, h->st)
+                   : launch_gs_update<double>(tot, w, V, tot, nv, h->red, h->st);
+    };
     HIPCHK(h, launch_fill<double>(tot, 0.0, x, h->st));
     HIPCHK(h, launch_axpby<double>(tot, 1.0, b, 0.0, r, h->st));
     double rel = 0.0;
@@ -2067,35 +2091,39 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
     while (it < o->max_iter) {
         double beta = 0.0;
         TRY(stokes_norm(h, r, &beta));
-        HIPCHK(h, launch_axpby<double>(tot, 1.0 / beta, r, 0.0, vec(V, 0), h->st));
+        HIPCHK(h, set_basis(0, 1.0 / beta, r));
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int k_done = 0;
         for (int k = 0; k < m; ++k) {
-            TRY(stokes_precond(h, vec(V, k), vec(Z, k)));
+            if (v32) {
+                HIPCHK(h, launch_cast(AGCA_F32, AGCA_F64, V32 + (int64_t)k * tot, vk, tot, h->st));
+                TRY(stokes_precond(h, vk, vec(Z, k)));
+            } else {
+                TRY(stokes_precond(h, vec(V, k), vec(Z, k)));
+            }
             TRY(stokes_apply(h, vec(Z, k), w));
             // classical Gram-Schmidt against V_0..V_k, a second pass after severe cancellation
-            HIPCHK(h, launch_gs_dots(tot, w, V, tot, k + 1, h->st_gs, h->st));
+            HIPCHK(h, gs_dots(k + 1));
             HIPCHK(h, launch_gs_sum(h->st_gs, nb, k + 2, h->red, h->st));
-            HIPCHK(h, launch_gs_update(tot, w, V, tot, k + 1, h->red, h->st));
-            HIPCHK(h, launch_gs_dots(tot, w, V, tot, 0, h->st_gs, h->st));
+            HIPCHK(h, gs_update(k + 1));
+            HIPCHK(h, gs_dots(0));
             HIPCHK(h, launch_gs_sum(h->st_gs, nb, 1, h->red + k + 2, h->st));
             TRY(fetch(h, k + 3, col.data()));
             for (int i = 0; i <= k; ++i) Hm(i, k) = col[i];
             double nrm2 = col[k + 2];
             if (!(std::sqrt(nrm2) >= kDgks * std::sqrt(col[k + 1]))) {
-                HIPCHK(h, launch_gs_dots(tot, w, V, tot, k + 1, h->st_gs, h->st));
+                HIPCHK(h, gs_dots(k + 1));
                 HIPCHK(h, launch_gs_sum(h->st_gs, nb, k + 1, h->red, h->st));
-                HIPCHK(h, launch_gs_update(tot, w, V, tot, k + 1, h->red, h->st));
-                HIPCHK(h, launch_gs_dots(tot, w, V, tot, 0, h->st_gs, h->st));
+                HIPCHK(h, gs_update(k + 1));
+                HIPCHK(h, gs_dots(0));
                 HIPCHK(h, launch_gs_sum(h->st_gs, nb, 1, h->red + k + 1, h->st));
                 TRY(fetch(h, k + 2, col.data()));
                 for (int i = 0; i <= k; ++i) Hm(i, k) += col[i];
                 nrm2 = col[k + 1];
             }
             Hm(k + 1, k) = std::sqrt(nrm2);
-            if (Hm(k + 1, k) > 0.0)
-                HIPCHK(h, launch_axpby<double>(tot, 1.0 / Hm(k + 1, k), w, 0.0, vec(V, k + 1), h->st));
+            if (Hm(k + 1, k) > 0.0) HIPCHK(h, set_basis(k + 1, 1.0 / Hm(k + 1, k), w));
             for (int i = 0; i < k; ++i) {
                 const double t = cs[i] * Hm(i, k) + sn[i] * Hm(i + 1, k);
                 Hm(i + 1, k) = -sn[i] * Hm(i, k) + cs[i] * Hm(i + 1, k);
@@ -2338,11 +2366,16 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
         return fail(AGCA_E_INVALID, "the BFBT approximation is not a fixed linear map: FGMRES only");
     if (o->velocity_cycles < 0 || o->velocity_cycles > 8)
         return fail(AGCA_E_INVALID, "velocity_cycles must be in [0, 8]");
+    if (o->basis_dtype != AGCA_F64 && o->basis_dtype != AGCA_F32)
+        return fail(AGCA_E_INVALID, "basis_dtype must be F64 or F32");
+    if (o->basis_dtype == AGCA_F32 && o->solver != AGCA_STOKES_FGMRES)
+        return fail(AGCA_E_INVALID, "an FP32 basis is an FGMRES option");
     TRY(ensure_solver_vectors(h));
     std::memset(stats, 0, sizeof(*stats));
     const StokesDims d = stokes_dims(h);
     // contiguous right-hand side and solution in the last two work vectors' place
-    const int64_t kry = (o->solver == AGCA_STOKES_FGMRES) ? 2 * (int64_t)o->restart + 3 : 8;
+    const int64_t kry = (o->solver == AGCA_STOKES_FGMRES)
+                            ? fgmres_work_vecs(o->restart, o->basis_dtype == AGCA_F32) : 8;
     const bool tri = o->precond == AGCA_STOKES_TRIANGULAR;
     TRY(stokes_work(h, kry + 2 + (tri ? 1 : 0)));
     double* bvec = h->st_work + kry * d.tot;

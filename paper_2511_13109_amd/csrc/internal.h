@@ -205,13 +205,17 @@ hipError_t launch_invert_diag(int64_t count, const double* diag, T* dinv, hipStr
 hipError_t launch_stokes_div_fine(int n, const double* u, double* q, hipStream_t st);
 // classical Gram-Schmidt against nv basis vectors V + i ld: gs_blocks(n) workgroups write
 // (nv + 1) rows of partials (w . V_i, then w . w); gs_sum reduces `rows` rows to out;
-// gs_update does w -= sum_i h[i] V_i with h on the device
+// gs_update does w -= sum_i h[i] V_i with h on the device; the basis V is FP64 or FP32
+// (widened on the fly); scale_to_f32 writes y = a x rounded to FP32
 int gs_blocks(int64_t n);
-hipError_t launch_gs_dots(int64_t n, const double* w, const double* V, int64_t ld, int nv,
+template <typename VT>
+hipError_t launch_gs_dots(int64_t n, const double* w, const VT* V, int64_t ld, int nv,
                           double* partial, hipStream_t st);
 hipError_t launch_gs_sum(const double* partial, int nb, int rows, double* out, hipStream_t st);
-hipError_t launch_gs_update(int64_t n, double* w, const double* V, int64_t ld, int nv, const double* h,
+template <typename VT>
+hipError_t launch_gs_update(int64_t n, double* w, const VT* V, int64_t ld, int nv, const double* h,
                             hipStream_t st);
+hipError_t launch_scale_to_f32(int64_t n, double a, const double* x, float* y, hipStream_t st);
 hipError_t launch_stokes_grad_fine_add(int n, const double* pf, double* out, hipStream_t st);
 hipError_t launch_stokes_mass_fine(int n, const double* nu, double* mf, hipStream_t st);
 hipError_t launch_restrict_all(int n_coarse, const double* qf, double* out, hipStream_t st);

@@ -237,9 +237,11 @@ __device__ __forceinline__ double gs_wave_sum(double v) {
 }
 
 // partial[i * gridDim.x + block] = sum over the block's entries of w V_i (i < nv), and
-// partial[nv * gridDim.x + block] = sum of w^2
+// partial[nv * gridDim.x + block] = sum of w^2; a basis stored in FP32 is widened on
+// the fly (the products and sums stay FP64)
+template <typename VT>
 __global__ void __launch_bounds__(NT)
-k_gs_dots(int64_t n, const double* __restrict__ w, const double* __restrict__ V, int64_t ld, int nv,
+k_gs_dots(int64_t n, const double* __restrict__ w, const VT* __restrict__ V, int64_t ld, int nv,
           double* __restrict__ partial) {
     __shared__ double red[NT / 64];
     const int64_t base = (int64_t)blockIdx.x * GS_CHUNK + threadIdx.x;
@@ -252,11 +254,11 @@ k_gs_dots(int64_t n, const double* __restrict__ w, const double* __restrict__ V,
     for (int i = 0; i <= nv; ++i) {
         double acc = 0.0;
         if (i < nv) {
-            const double* v = V + (int64_t)i * ld;
+            const VT* v = V + (int64_t)i * ld;
 #pragma unroll
             for (int m = 0; m < GS_PER; ++m) {
                 const int64_t j = base + (int64_t)m * NT;
-                acc += wv[m] * (j < n ? v[j] : 0.0);
+                acc += wv[m] * (j < n ? (double)v[j] : 0.0);
             }
         } else {
 #pragma unroll
@@ -291,16 +293,24 @@ k_gs_sum(const double* __restrict__ partial, int nb, double* __restrict__ out) {
     }
 }
 
-// w -= sum_i h[i] V_i (h on the device)
+// w -= sum_i h[i] V_i (h on the device; an FP32 basis widened on the fly)
+template <typename VT>
 __global__ void __launch_bounds__(NT)
-k_gs_update(int64_t n, double* __restrict__ w, const double* __restrict__ V, int64_t ld, int nv,
+k_gs_update(int64_t n, double* __restrict__ w, const VT* __restrict__ V, int64_t ld, int nv,
             const double* __restrict__ h) {
     const int64_t stride = (int64_t)gridDim.x * NT;
     for (int64_t j = blockIdx.x * (int64_t)NT + threadIdx.x; j < n; j += stride) {
         double acc = 0.0;
-        for (int i = 0; i < nv; ++i) acc += h[i] * V[(int64_t)i * ld + j];
+        for (int i = 0; i < nv; ++i) acc += h[i] * (double)V[(int64_t)i * ld + j];
         w[j] -= acc;
     }
+}
+
+// y = a x rounded to FP32 (a new FP32 basis vector)
+__global__ void __launch_bounds__(NT)
+k_scale_to_f32(int64_t n, double a, const double* __restrict__ x, float* __restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t j = blockIdx.x * (int64_t)NT + threadIdx.x; j < n; j += stride) y[j] = (float)(a * x[j]);
 }
 
 unsigned grid_for(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
@@ -369,21 +379,36 @@ hipError_t launch_colour(int n, int colour, int mode, const double* src, double*
     return hipGetLastError();
 }
 int gs_blocks(int64_t n) { return (int)((n + GS_CHUNK - 1) / GS_CHUNK); }
-hipError_t launch_gs_dots(int64_t n, const double* w, const double* V, int64_t ld, int nv,
+template <typename VT>
+hipError_t launch_gs_dots(int64_t n, const double* w, const VT* V, int64_t ld, int nv,
                           double* partial, hipStream_t st) {
     if (!w || !V || !partial || n <= 0 || nv < 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gs_dots, dim3((unsigned)gs_blocks(n)), dim3(NT), 0, st, n, w, V, ld, nv, partial);
+    hipLaunchKernelGGL(k_gs_dots<VT>, dim3((unsigned)gs_blocks(n)), dim3(NT), 0, st, n, w, V, ld, nv, partial);
     return hipGetLastError();
 }
+template hipError_t launch_gs_dots<double>(int64_t, const double*, const double*, int64_t, int, double*,
+                                           hipStream_t);
+template hipError_t launch_gs_dots<float>(int64_t, const double*, const float*, int64_t, int, double*,
+                                          hipStream_t);
 hipError_t launch_gs_sum(const double* partial, int nb, int rows, double* out, hipStream_t st) {
     if (!partial || !out || nb <= 0 || rows <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gs_sum, dim3((unsigned)rows), dim3(NT), 0, st, partial, nb, out);
     return hipGetLastError();
 }
-hipError_t launch_gs_update(int64_t n, double* w, const double* V, int64_t ld, int nv, const double* h,
+template <typename VT>
+hipError_t launch_gs_update(int64_t n, double* w, const VT* V, int64_t ld, int nv, const double* h,
                             hipStream_t st) {
     if (!w || !V || !h || n <= 0 || nv <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gs_update, dim3(grid_stride(n)), dim3(NT), 0, st, n, w, V, ld, nv, h);
+    hipLaunchKernelGGL(k_gs_update<VT>, dim3(grid_stride(n)), dim3(NT), 0, st, n, w, V, ld, nv, h);
+    return hipGetLastError();
+}
+template hipError_t launch_gs_update<double>(int64_t, double*, const double*, int64_t, int, const double*,
+                                             hipStream_t);
+template hipError_t launch_gs_update<float>(int64_t, double*, const float*, int64_t, int, const double*,
+                                            hipStream_t);
+hipError_t launch_scale_to_f32(int64_t n, double a, const double* x, float* y, hipStream_t st) {
+    if (!x || !y || n <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scale_to_f32, dim3(grid_stride(n)), dim3(NT), 0, st, n, a, x, y);
     return hipGetLastError();
 }
 hipError_t launch_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,

@@ -188,6 +188,38 @@ def test_velocity_cycles_match_oracle(case, solver, precond):
         GS.solve(_dev(fu), solver=solver, tol=tol, precond=precond, velocity_cycles=9)
 
 
+@pytest.mark.parametrize("precond,schur", [("triangular", "mass"), ("diagonal", "mass"),
+                                           ("triangular", "bfbt_mg")])
+def test_fgmres_fp32_basis(case, precond, schur):
+    # The Arnoldi basis stored in FP32 (FP64 dot products, preconditioned vectors and
+    # iterate).  Within one restart cycle the basis's rounding (about 6e-8 relative) bounds
+    # how far the cycle can take the residual, so down to 1e-6 the solve follows the FP64
+    # basis's (iteration counts within a few percent, the first steps' history to the
+    # basis's rounding); to 1e-9 it gets there over extra restarts, its residual recomputed
+    # by the oracle
+    L, levels, H, S, fu, GS, _ = case
+    b = np.concatenate([fu[H.free[L]], np.zeros(S.np_)])
+    kw = dict(solver="fgmres", restart=30, max_iter=3000, precond=precond, schur=schur, schur_iters=4)
+    _, _, st = GS.solve(_dev(fu), basis="f32", tol=1e-6, **kw)
+    _, _, ref = GS.solve(_dev(fu), basis="f64", tol=1e-6, **kw)
+    print(f"[fgmres {precond} {schur} FP32 basis L={L}] to 1e-6: {st['iterations']} it, FP64 basis "
+          f"{ref['iterations']} it", flush=True)
+    assert st["converged"] and ref["converged"]
+    assert abs(st["iterations"] - ref["iterations"]) <= max(2, int(0.05 * ref["iterations"]))
+    k = min(len(st["history"]), len(ref["history"]), 10)
+    assert np.allclose(st["history"][:k], ref["history"][:k], rtol=1e-5, atol=1e-14)
+    tol = 1e-9
+    u, p, st = GS.solve(_dev(fu), basis="f32", tol=tol, **kw)
+    _, _, ref = GS.solve(_dev(fu), basis="f64", tol=tol, **kw)
+    print(f"[fgmres {precond} {schur} FP32 basis L={L}] to 1e-9: {st['iterations']} it, FP64 basis "
+          f"{ref['iterations']} it", flush=True)
+    assert st["converged"] and st["iterations"] <= 1.5 * ref["iterations"] + 30
+    xg = np.concatenate([u.cpu().numpy()[H.free[L]], p.cpu().numpy()])
+    assert np.linalg.norm(b - S.K @ xg) <= 1.0001 * tol * np.linalg.norm(b)
+    with pytest.raises(Exception):
+        GS.solve(_dev(fu), solver="minres", tol=tol, basis="f32")
+
+
 @pytest.mark.parametrize("case", [3], indirect=True, ids=["L3"])
 def test_fgmres_below_the_rounding_floor_stays_finite(case):
     # asking for 1e-14 drives the Arnoldi process into near-dependent vectors (the

@@ -357,7 +357,7 @@ typedef struct {
  * fixed SPD preconditioner, which the FP32 V-cycle is only up to FP32 rounding; the true
  * residual is checked every step, so a run that stagnates reports AGCA_E_NOCONV, never a
  * false convergence).  The returned p has zero mean over the pressure nodes.  Work
- * space: 2 restart + 5 (FGMRES; with an FP32 basis restart + (restart + 2) / 2 + 6; one
+ * space: 2 restart + 5 (FGMRES; with an FP32 basis about 1.5 restart + 6.5; one
  * more with TRIANGULAR) or 10 (MINRES) vectors of 3 (n_L+1)^3 + (n_{L-1}+1)^3 doubles,
  * kept until destroy;
  * BFBT and BFBT_MG add 3 velocity and 8 pressure vectors, BFBT_MG its multigrid.

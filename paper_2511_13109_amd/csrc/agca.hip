@@ -2029,10 +2029,19 @@ static int32_t stokes_residual(agca_hier* h, const double* b, const double* x, d
 // Stewart test with threshold 0.1; the customary 1/sqrt(2) fired on every step of the
 // sinker problems without changing a single iteration count, at twice the cost).
 constexpr double kDgks = 0.1;
-// work vectors of FGMRES(m): the basis (m + 1, in half as many slots when FP32), Z (m),
-// w, r, and the FP64 copy of a basis vector with an FP32 basis
-static int64_t fgmres_work_vecs(int m, bool v32) {
-    return v32 ? (int64_t)(m + 2) / 2 + m + 3 : 2 * (int64_t)m + 3;
+// An FP32 basis keeps its vectors at a leading dimension that is a multiple of 4 (the
+// Gram-Schmidt passes load four entries at a time), in as many FP64 vector slots as its
+// bytes need.
+static int64_t fp32_basis_ld(int64_t tot) { return (tot + 3) & ~(int64_t)3; }
+static int64_t fp32_basis_slots(int m, int64_t tot) {
+    const int64_t bytes = (int64_t)(m + 1) * fp32_basis_ld(tot) * (int64_t)sizeof(float);
+    const int64_t slot = tot * (int64_t)sizeof(double);
+    return (bytes + slot - 1) / slot;
+}
+// work vectors of FGMRES(m): the basis (m + 1 vectors), Z (m), w, r, and with an FP32
+// basis the FP64 copy of the basis vector being preconditioned
+static int64_t fgmres_work_vecs(int m, bool v32, int64_t tot) {
+    return v32 ? fp32_basis_slots(m, tot) + m + 3 : 2 * (int64_t)m + 3;
 }
 static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const double* b, double* x,
                              double bn, double* rel_out, int* it_out, std::vector<double>& hist,
@@ -2042,8 +2051,9 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
     // the basis V (m + 1 vectors, FP64 or FP32), Z (m FP64 vectors), w, r, and with an FP32
     // basis an FP64 copy of the basis vector being preconditioned
     const bool v32 = o->basis_dtype == AGCA_F32;
-    TRY(stokes_work(h, fgmres_work_vecs(m, v32)));
-    const int64_t vslots = v32 ? (m + 2) / 2 : m + 1;
+    TRY(stokes_work(h, fgmres_work_vecs(m, v32, tot)));
+    const int64_t vslots = v32 ? fp32_basis_slots(m, tot) : m + 1;
+    const int64_t ld32 = fp32_basis_ld(tot);
     double* V = v32 ? nullptr : h->st_work;
     float* V32 = v32 ? reinterpret_cast<float*>(h->st_work) : nullptr;
     double* Z = h->st_work + vslots * tot;
@@ -2053,15 +2063,15 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
     auto vec = [&](double* base, int i) { return base + (int64_t)i * tot; };
     // V_i = a x
     auto set_basis = [&](int i, double a, const double* xx) -> hipError_t {
-        return v32 ? launch_scale_to_f32(tot, a, xx, V32 + (int64_t)i * tot, h->st)
+        return v32 ? launch_scale_to_f32(tot, a, xx, V32 + (int64_t)i * ld32, h->st)
                    : launch_axpby<double>(tot, a, xx, 0.0, vec(V, i), h->st);
     };
     auto gs_dots = [&](int nv) -> hipError_t {
-        return v32 ? launch_gs_dots<float>(tot, w, V32, tot, nv, h->st_gs, h->st)
+        return v32 ? launch_gs_dots<float>(tot, w, V32, ld32, nv, h->st_gs, h->st)
                    : launch_gs_dots<double>(tot, w, V, tot, nv, h->st_gs, h->st);
     };
     auto gs_update = [&](int nv) -> hipError_t {
-        return v32 ? launch_gs_update<float>(tot, w, V32, tot, nv, h->red, h->st)
+        return v32 ? launch_gs_update<float>(tot, w, V32, ld32, nv, h->red, h->st)
                    : launch_gs_update<double>(tot, w, V, tot, nv, h->red, h->st);
     };
     HIPCHK(h, launch_fill<double>(tot, 0.0, x, h->st));
@@ -2073,7 +2083,7 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
     int it = 0;
     std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), col(m + 3);
     std::vector<double> cycle_res;  // true residual after each restart cycle
-    const int nb = gs_blocks(tot);
+    const int nb = v32 ? gs_blocks_f32(tot) : gs_blocks(tot);  // workgroups of the dot pass
     if (h->st_gs_cap < (int64_t)(m + 2) * nb) {
         for (size_t i = 0; h->st_gs && i < h->allocs.size(); ++i)
             if (h->allocs[i] == h->st_gs) {
@@ -2097,7 +2107,7 @@ static int32_t stokes_fgmres(agca_hier* h, const agca_stokes_opts* o, const doub
         int k_done = 0;
         for (int k = 0; k < m; ++k) {
             if (v32) {
-                HIPCHK(h, launch_cast(AGCA_F32, AGCA_F64, V32 + (int64_t)k * tot, vk, tot, h->st));
+                HIPCHK(h, launch_cast(AGCA_F32, AGCA_F64, V32 + (int64_t)k * ld32, vk, tot, h->st));
                 TRY(stokes_precond(h, vk, vec(Z, k)));
             } else {
                 TRY(stokes_precond(h, vec(V, k), vec(Z, k)));
@@ -2375,7 +2385,7 @@ int32_t agca_stokes_solve(agca_hier* h, const agca_stokes_opts* o, const double*
     const StokesDims d = stokes_dims(h);
     // contiguous right-hand side and solution in the last two work vectors' place
     const int64_t kry = (o->solver == AGCA_STOKES_FGMRES)
-                            ? fgmres_work_vecs(o->restart, o->basis_dtype == AGCA_F32) : 8;
+                            ? fgmres_work_vecs(o->restart, o->basis_dtype == AGCA_F32, d.tot) : 8;
     const bool tri = o->precond == AGCA_STOKES_TRIANGULAR;
     TRY(stokes_work(h, kry + 2 + (tri ? 1 : 0)));
     double* bvec = h->st_work + kry * d.tot;

@@ -208,6 +208,7 @@ hipError_t launch_stokes_div_fine(int n, const double* u, double* q, hipStream_t
 // gs_update does w -= sum_i h[i] V_i with h on the device; the basis V is FP64 or FP32
 // (widened on the fly); scale_to_f32 writes y = a x rounded to FP32
 int gs_blocks(int64_t n);
+int gs_blocks_f32(int64_t n);  // the dot pass over an FP32 basis (twice the entries per workgroup)
 template <typename VT>
 hipError_t launch_gs_dots(int64_t n, const double* w, const VT* V, int64_t ld, int nv,
                           double* partial, hipStream_t st);

@@ -306,6 +306,84 @@ k_gs_update(int64_t n, double* __restrict__ w, const VT* __restrict__ V, int64_t
     }
 }
 
+// The same two passes over an FP32 basis, four consecutive entries per lane and load
+// (the basis vectors start at 16-byte aligned offsets, ld a multiple of 4): a wavefront
+// then keeps as many bytes in flight per basis vector as the FP64 passes (with one
+// 4-byte load per entry the passes ran at 3.8 TB/s against 5.3 for the FP64 basis).
+// The dot pass owns GS_CHUNK_F32 = 2 GS_CHUNK entries per workgroup (gs_blocks_f32).
+constexpr int GS_QUADS = 4;                   // float4 loads per lane and basis vector
+constexpr int GS_CHUNK_F32 = NT * 4 * GS_QUADS;
+
+__global__ void __launch_bounds__(NT)
+k_gs_dots_f32(int64_t n, const double* __restrict__ w, const float* __restrict__ V, int64_t ld, int nv,
+              double* __restrict__ partial) {
+    __shared__ double red[NT / 64];
+    const int64_t base = (int64_t)blockIdx.x * GS_CHUNK_F32 + 4 * threadIdx.x;
+    double wv[4 * GS_QUADS];
+#pragma unroll
+    for (int q = 0; q < GS_QUADS; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = base + (int64_t)q * 4 * NT + e;
+            wv[4 * q + e] = j < n ? w[j] : 0.0;
+        }
+    for (int i = 0; i <= nv; ++i) {
+        double acc = 0.0;
+        if (i < nv) {
+            const float* v = V + (int64_t)i * ld;
+            float4 vv[GS_QUADS];
+#pragma unroll
+            for (int q = 0; q < GS_QUADS; ++q) {
+                // the quad starts inside the padded vector (ld >= n, a multiple of 4)
+                const int64_t j = base + (int64_t)q * 4 * NT;
+                vv[q] = j < n ? *reinterpret_cast<const float4*>(v + j) : float4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+#pragma unroll
+            for (int q = 0; q < GS_QUADS; ++q) {
+                const int64_t j = base + (int64_t)q * 4 * NT;
+                const float f[4] = {vv[q].x, vv[q].y, vv[q].z, vv[q].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc += wv[4 * q + e] * (j + e < n ? (double)f[e] : 0.0);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4 * GS_QUADS; ++m) acc += wv[m] * wv[m];
+        }
+        acc = gs_wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int q = 0; q < NT / 64; ++q) t += red[q];
+            partial[(int64_t)i * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// w -= sum_i h[i] V_i over four consecutive entries per lane, the basis loads of four
+// vectors issued before their products are summed (in the order of i, as above)
+__global__ void __launch_bounds__(NT)
+k_gs_update_f32(int64_t n, double* __restrict__ w, const float* __restrict__ V, int64_t ld, int nv,
+                const double* __restrict__ h) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t j = 4 * (blockIdx.x * (int64_t)NT + threadIdx.x); j < n; j += 4 * stride) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int i = 0; i < nv; ++i) {
+            const float4 vv = *reinterpret_cast<const float4*>(V + (int64_t)i * ld + j);
+            const double hi = h[i];
+            a[0] += hi * (double)vv.x;
+            a[1] += hi * (double)vv.y;
+            a[2] += hi * (double)vv.z;
+            a[3] += hi * (double)vv.w;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (j + e < n) w[j + e] -= a[e];
+    }
+}
+
 // y = a x rounded to FP32 (a new FP32 basis vector)
 __global__ void __launch_bounds__(NT)
 k_scale_to_f32(int64_t n, double a, const double* __restrict__ x, float* __restrict__ y) {
@@ -379,11 +457,20 @@ hipError_t launch_colour(int n, int colour, int mode, const double* src, double*
     return hipGetLastError();
 }
 int gs_blocks(int64_t n) { return (int)((n + GS_CHUNK - 1) / GS_CHUNK); }
+int gs_blocks_f32(int64_t n) { return (int)((n + GS_CHUNK_F32 - 1) / GS_CHUNK_F32); }
 template <typename VT>
 hipError_t launch_gs_dots(int64_t n, const double* w, const VT* V, int64_t ld, int nv,
                           double* partial, hipStream_t st) {
     if (!w || !V || !partial || n <= 0 || nv < 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gs_dots<VT>, dim3((unsigned)gs_blocks(n)), dim3(NT), 0, st, n, w, V, ld, nv, partial);
+    if constexpr (sizeof(VT) == 4) {
+        // quad loads: leading dimension a multiple of 4 covering n, 16-byte aligned base
+        if ((ld & 3) || ld < n || (reinterpret_cast<uintptr_t>(V) & 15)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_gs_dots_f32, dim3((unsigned)gs_blocks_f32(n)), dim3(NT), 0, st, n, w, V, ld, nv,
+                           partial);
+    } else {
+        hipLaunchKernelGGL(k_gs_dots<VT>, dim3((unsigned)gs_blocks(n)), dim3(NT), 0, st, n, w, V, ld, nv,
+                           partial);
+    }
     return hipGetLastError();
 }
 template hipError_t launch_gs_dots<double>(int64_t, const double*, const double*, int64_t, int, double*,
@@ -399,7 +486,12 @@ template <typename VT>
 hipError_t launch_gs_update(int64_t n, double* w, const VT* V, int64_t ld, int nv, const double* h,
                             hipStream_t st) {
     if (!w || !V || !h || n <= 0 || nv <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gs_update<VT>, dim3(grid_stride(n)), dim3(NT), 0, st, n, w, V, ld, nv, h);
+    if constexpr (sizeof(VT) == 4) {
+        if ((ld & 3) || ld < n || (reinterpret_cast<uintptr_t>(V) & 15)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_gs_update_f32, dim3(grid_stride((n + 3) / 4)), dim3(NT), 0, st, n, w, V, ld, nv, h);
+    } else {
+        hipLaunchKernelGGL(k_gs_update<VT>, dim3(grid_stride(n)), dim3(NT), 0, st, n, w, V, ld, nv, h);
+    }
     return hipGetLastError();
 }
 template hipError_t launch_gs_update<double>(int64_t, double*, const double*, int64_t, int, const double*,

@@ -1,8 +1,9 @@
 """GPU parity of the Stokes pieces (Section 3.1) against the oracle, through the C ABI:
 divergence B, B^T, the lumped 1/nu pressure mass (1e-12 relative), and the
 block-preconditioned FGMRES / MINRES solves (iteration counts within one of the
-oracle's, residual histories, solutions against the bordered direct solve), and both
-solvers around the FP32 V-cycle (residual recomputed by the oracle).
+oracle's, residual histories, solutions against the bordered direct solve), both
+solvers around the FP32 V-cycle (residual recomputed by the oracle), and FGMRES with its
+Arnoldi basis stored in FP32.
 """
 
 import numpy as np
